@@ -1,0 +1,212 @@
+"""Python access to the plain FP64 CPU oracle (mek_oracle.c) plus the
+pseudoinverse references the paper's theorems name.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the GPU library and
+its Python binding never do. Nothing here shares code with the GPU path.
+
+Functions that are not thin wrappers of the C oracle:
+  least_norm(A, C, B)      X* = A^+ C B^+, the least-norm solution (Sec. 2).
+  bk_limit(A, B, C, X0)    A^+ C B^+ + X0 - A^+ A X0 B B^+, the ME-BK limit
+                           (Theorem 3.3).
+  spectral_alpha(B)        1 / ||B||_2^2, the step used in Sec. 5.
+Each uses numpy's SVD-based pinv / norm as the library primitive.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mek_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+BK, RBK, GRBK, RGRBK, MWRBK = 0, 1, 2, 3, 4
+VARIANTS = {"bk": BK, "rbk": RBK, "grbk": GRBK, "rgrbk": RGRBK, "mwrbk": MWRBK}
+STOP_NONE, STOP_REL_ERR, STOP_REL_RESID = 0, 1, 2
+OK, MAXITER, EXACT, EINVAL, ENOMEM, EDIVERGED = 0, 1, 2, -1, -2, -5
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        d, i64, u64 = ctypes.c_double, ctypes.c_int64, ctypes.c_uint64
+        dp, lp, bp = P(d), P(i64), P(ctypes.c_ubyte)
+        L.mo_philox4x64_10.argtypes = [P(u64), P(u64), P(u64)]
+        L.mo_philox4x64_10.restype = None
+        L.mo_uniform.argtypes = [u64, u64, i64]
+        L.mo_uniform.restype = d
+        L.mo_select.argtypes = [ctypes.c_int, i64, dp, dp, d, d, u64, u64, i64, bp, dp, dp]
+        L.mo_select.restype = i64
+        L.mo_residual.argtypes = [i64, i64, i64, i64, dp, dp, dp, dp, dp]
+        L.mo_residual.restype = None
+        L.mo_gram_rows.argtypes = [i64, i64, dp, dp]
+        L.mo_gram_rows.restype = None
+        L.mo_gram_cols.argtypes = [i64, i64, dp, dp]
+        L.mo_gram_cols.restype = None
+        L.mo_solve.argtypes = [i64, i64, i64, i64, dp, dp, dp, dp, ctypes.c_int, d, d,
+                               ctypes.c_int, d, dp, i64, u64, u64, lp, i64, ctypes.c_int, d,
+                               dp, lp, P(ctypes.c_int), dp, dp, lp, lp, i64]
+        L.mo_solve.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(x: Optional[np.ndarray]):
+    if x is None:
+        return None
+    assert x.dtype == np.float64 and x.flags.c_contiguous
+    return x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(x):
+    return None if x is None else np.ascontiguousarray(x, dtype=np.float64)
+
+
+def philox4x64_10(counter: Sequence[int], key: Sequence[int]) -> list:
+    """The four 64-bit output words of Philox4x64-10 for one counter block."""
+    u64 = ctypes.c_uint64
+    c = (u64 * 4)(*[int(x) & (2 ** 64 - 1) for x in counter])
+    k = (u64 * 2)(*[int(x) & (2 ** 64 - 1) for x in key])
+    o = (u64 * 4)()
+    lib().mo_philox4x64_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def uniform(seed: int, inst: int, k: int) -> float:
+    return float(lib().mo_uniform(seed, inst, k))
+
+
+def select(variant, r, a, theta=0.5, seed=0, inst=0, k=0):
+    """Run the selection rule once. Returns (i, in_set (bool m), t, T)."""
+    variant = VARIANTS.get(variant, variant)
+    r = _f64(r)
+    a = _f64(a)
+    m = r.shape[0]
+    F_A = float(np.sum(a)) if m else 0.0
+    # F_A must be the ascending sum the solver uses.
+    s = 0.0
+    for x in a:
+        s += float(x)
+    F_A = s
+    in_set = np.zeros(m, dtype=np.uint8)
+    t = ctypes.c_double(0.0)
+    T = ctypes.c_double(0.0)
+    i = lib().mo_select(int(variant), m, _dp(r), _dp(a), F_A, float(theta), seed, inst, k,
+                        in_set.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
+                        ctypes.byref(t), ctypes.byref(T))
+    return int(i), in_set.astype(bool), t.value, T.value
+
+
+def residual(A, X, B, C):
+    A, X, B, C = map(_f64, (A, X, B, C))
+    m, p = A.shape
+    q, n = B.shape
+    R = np.empty((m, n))
+    lib().mo_residual(m, p, q, n, _dp(A), _dp(X), _dp(B), _dp(C), _dp(R))
+    return R
+
+
+def gram_rows(M):
+    M = _f64(M)
+    G = np.empty((M.shape[0], M.shape[0]))
+    lib().mo_gram_rows(M.shape[0], M.shape[1], _dp(M), _dp(G))
+    return G
+
+
+def gram_cols(M):
+    M = _f64(M)
+    G = np.empty((M.shape[1], M.shape[1]))
+    lib().mo_gram_cols(M.shape[0], M.shape[1], _dp(M), _dp(G))
+    return G
+
+
+class Result:
+    def __init__(self, X, iters, status, s_hist, e_hist, idx_hist, set_hist):
+        self.X = X
+        self.iters = iters
+        self.status = status
+        self.s_hist = s_hist
+        self.e_hist = e_hist
+        self.idx = idx_hist
+        self.set_sizes = set_hist
+
+
+def solve(A, B, C, X0=None, variant="grbk", theta=0.5, alpha=None, stop=STOP_NONE, tol=0.0,
+          Xref=None, max_iters=1000, seed=0, inst=0, forced=None, literal=False,
+          diverge=0.0, hist_cap=None) -> Result:
+    """Run the oracle iteration. See mo_solve in mek_oracle.c for semantics."""
+    variant = VARIANTS.get(variant, variant)
+    A, B, C, X0, Xref = map(_f64, (A, B, C, X0, Xref))
+    m, p = A.shape
+    q, n = B.shape
+    assert C.shape == (m, n)
+    if alpha is None:
+        alpha = spectral_alpha(B)
+    X = np.empty((p, q))
+    if hist_cap is None:
+        hist_cap = max_iters + 1
+    s_hist = np.full(hist_cap, np.nan)
+    e_hist = np.full(hist_cap, np.nan)
+    idx_hist = np.full(hist_cap, -1, dtype=np.int64)
+    set_hist = np.zeros(hist_cap, dtype=np.int64)
+    it = ctypes.c_int64(0)
+    st = ctypes.c_int(0)
+    if forced is not None:
+        forced = np.ascontiguousarray(forced, dtype=np.int64)
+        fp = forced.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        nf = forced.shape[0]
+    else:
+        fp, nf = None, 0
+    LP = ctypes.POINTER(ctypes.c_int64)
+    rc = lib().mo_solve(m, p, q, n, _dp(A), _dp(B), _dp(C), _dp(X0), int(variant), float(theta),
+                        float(alpha), int(stop), float(tol), _dp(Xref), int(max_iters), int(seed),
+                        int(inst), fp, nf, 1 if literal else 0, float(diverge), _dp(X),
+                        ctypes.byref(it), ctypes.byref(st), _dp(s_hist), _dp(e_hist),
+                        idx_hist.ctypes.data_as(LP), set_hist.ctypes.data_as(LP), hist_cap)
+    if rc in (EINVAL, ENOMEM) and it.value == 0 and rc != st.value:
+        raise ValueError(f"oracle rejected the arguments (code {rc})")
+    k = it.value
+    return Result(X, k, st.value, s_hist[:k + 1], e_hist[:k + 1], idx_hist[:k], set_hist[:k])
+
+
+# ----------------------------------------------------------------------------
+# Closed forms from the paper, computed with numpy's SVD-based pinv.
+# ----------------------------------------------------------------------------
+
+def least_norm(A, C, B):
+    """X* = A^+ C B^+ (the unique least-norm solution, Sec. 2)."""
+    return np.linalg.pinv(A) @ C @ np.linalg.pinv(B)
+
+
+def bk_limit(A, B, C, X0):
+    """A^+ C B^+ + X0 - A^+ A X0 B B^+ (Theorem 3.3)."""
+    Ap = np.linalg.pinv(A)
+    Bp = np.linalg.pinv(B)
+    return Ap @ C @ Bp + X0 - Ap @ A @ X0 @ B @ Bp
+
+
+def spectral_alpha(B):
+    """alpha = 1 / ||B||_2^2 (Sec. 5)."""
+    return 1.0 / np.linalg.norm(B, 2) ** 2
