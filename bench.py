@@ -1,0 +1,140 @@
+"""Benchmark: time-to-tolerance and iterations per second of ME-GRBK for
+A X B = C on one MI355X.
+
+Workload: A 2000 x 500 and B 500 x 2000 with iid N(0,1) entries, X* 500 x 500
+iid N(0,1), C = A X* B (data seed 2), X0 = 0, ME-GRBK (theta = 1/2), alpha =
+1/||B||_2^2, stop at ||X - X*||_F/||X*||_F <= 1e-6. One step = the whole hot
+path for that instance: plan set-up (row norms, A A^T, B^T B, alpha) and the
+solve to tolerance. `value` is the job's updates per second over the timed
+steps; `ms_per_step` is the time to tolerance. The same instance is also
+solved in the FP32 and mixed forms (reported under "forms").
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_update(m, p, q, n, elem):
+    # One update of the paper's form: read and write R (2 m n), read and
+    # write X (2 p q), read B for R_i B^T and again for (R_i B^T) B (2 q n),
+    # plus the selection / update vectors (m + n + p).
+    return (2 * m * n + 2 * p * q + 2 * q * n + m + n + p) * elem
+
+
+def cpu_baseline(inst, seed, updates=600):
+    import oracle
+    alpha = oracle.spectral_alpha(inst.B)
+    t0 = time.perf_counter()
+    oracle.solve(inst.A, inst.B, inst.C, variant="grbk", alpha=alpha, max_iters=0, seed=seed)
+    t1 = time.perf_counter()
+    oracle.solve(inst.A, inst.B, inst.C, variant="grbk", alpha=alpha, max_iters=updates, seed=seed)
+    t2 = time.perf_counter()
+    iter_time = max((t2 - t1) - (t1 - t0), 1e-9)
+    return {"value": updates / iter_time, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{updates} ME-GRBK updates of the same 2000x500/500x2000 FP64 instance "
+                      f"on one host core (set-up of {t1 - t0:.1f} s excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--variant", default="grbk")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2408_05444_amd as mek
+    import workloads
+
+    inst = workloads.large()
+    m, p, q, n = inst.shape
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    A, B, C, Xs = t(inst.A), t(inst.B), t(inst.C), t(inst.X_star)
+    seed = 2408054440
+    torch.cuda.synchronize()
+
+    def step(precision="fp64"):
+        plan = mek.mek_plan_create(A, B, precision=precision)
+        res = mek.mek_solve(plan, C, variant=args.variant, stop="rel_err", tol=1e-6, X_ref=Xs,
+                            max_iters=5_000_000, seed=seed)
+        mek.mek_plan_destroy(plan)
+        return res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    iters = sum(r.iters for r in results)
+    kernel_ms = sum(r.kernel_ms for r in results)
+    ok = all(r.status == mek.MEK_OK for r in results)
+    bpu = algorithmic_bytes_per_update(m, p, q, n, 8)
+    achieved = bpu * iters / (kernel_ms * 1e-3) / 1e9
+    line = {
+        "metric": "time-to-rel-err 1e-6 & iters/s: ME-GRBK plain GPU vs mixed/batched/warm-start",
+        "value": iters / elapsed,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded iid N(0,1) A, B, X*; C = A X* B)",
+        "config": {"workload": "ME-GRBK theta=1/2, A 2000x500, B 500x2000, X* 500x500, "
+                               "consistent, X0=0, stop ||X-X*||/||X*|| <= 1e-6",
+                   "m": m, "p": p, "q": q, "n": n, "variant": args.variant,
+                   "iters_to_tol": results[-1].iters, "rel_err": results[-1].rel_err,
+                   "converged": ok, "team_wgs": results[-1].team_wgs,
+                   "r_in_lds": results[-1].r_in_lds},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "solve_kernel<double,LDS>",
+                     "kernel_us_per_update": kernel_ms * 1e3 / max(iters, 1),
+                     "algorithmic_bytes_per_update": bpu},
+    }
+    if not args.no_forms:
+        forms = {}
+        for prec in ["fp32", "mixed"]:
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            r = step(prec)
+            torch.cuda.synchronize()
+            te = time.perf_counter() - ts
+            forms[prec] = {"time_to_tol_s": te, "iters": r.iters, "iters_per_s": r.iters / te,
+                           "rel_err": r.rel_err, "status": r.status, "passes": r.passes}
+        forms["fp64"] = {"time_to_tol_s": elapsed / args.steps, "iters": results[-1].iters,
+                         "iters_per_s": iters / elapsed, "rel_err": results[-1].rel_err,
+                         "status": results[-1].status}
+        line["forms"] = forms
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(inst, seed)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * mek.h - C ABI of libmek.so: greedy randomized block Kaczmarz solvers for
+ * the matrix equation A X B = C on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (paper, Sec. 1, eq. 1.1): given A (m x p), B (q x n), C (m x n),
+ * find X (p x q) with A X B = C; for a consistent system the greedy methods
+ * converge to the least-norm solution X* = A^+ C B^+ (Sec. 2; Theorems 4.2,
+ * 4.5, 4.7), ME-BK to A^+ C B^+ + X0 - A^+ A X0 B B^+ (Theorem 3.3).
+ *
+ * Iteration (Algs. 1-5): pick one row index i_k, then
+ *     X^{k+1} = X^k + alpha/||A_i||^2 * A_i^T (R_i^k B^T),
+ *     R^{k+1} = R^k - alpha/||A_i||^2 * (A A^T)_{:,i} (R_i^k B^T B),
+ * where R = C - A X B. The variants differ in how i_k is chosen:
+ *     MEK_BK     cyclic over the rows with nonzero norm      (Alg. 2)
+ *     MEK_RBK    Pr(i) = ||A_i||^2/||A||_F^2                 (Alg. 1)
+ *     MEK_GRBK   greedy threshold set + residual sampling    (Alg. 3)
+ *     MEK_RGRBK  the same with relaxation theta in [0, 1]    (Alg. 4)
+ *     MEK_MWRBK  argmax of ||R_i||^2/||A_i||^2, lowest index (Alg. 5)
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are dense, row-major and contiguous (leading dimension equals
+ *     the number of columns). Element type at the boundary is always double.
+ *   - Pointers documented as "device" must point to memory of the current
+ *     HIP device; the library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Blocking calls synchronise that stream before returning.
+ *   - The return value is a status code (MEK_OK ... below). Negative values
+ *     are errors; on an error, outputs are left untouched unless stated.
+ *   - A plan is not thread-safe; use one plan per stream. Calls on one
+ *     plan must not overlap.
+ */
+#ifndef MEK_H
+#define MEK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MEK_ABI_VERSION 1
+
+/* Selection rules (Algs. 1-5). */
+#define MEK_BK 0
+#define MEK_RBK 1
+#define MEK_GRBK 2
+#define MEK_RGRBK 3
+#define MEK_MWRBK 4
+
+/* Stop rules, evaluated before every update (so 0 updates when X0 already
+ * passes). REL_ERR: ||X^k - X_ref||_F <= tol ||X_ref||_F (Sec. 5's RRN is
+ * the square of this ratio). REL_RESID: ||R^k||_F <= tol ||C||_F. */
+#define MEK_STOP_NONE 0
+#define MEK_STOP_REL_ERR 1
+#define MEK_STOP_REL_RESID 2
+
+/* Arithmetic of the iteration. FP64: everything in double. FP32: residual,
+ * iterate and Gram matrices in float, norms / selection / stop test in
+ * double. MIXED: FP64 outer refinement (true residual by FP64 GEMM), FP32
+ * inner iterations on the correction equation A D B = R_true. */
+#define MEK_FP64 0
+#define MEK_FP32 1
+#define MEK_MIXED 2
+
+/* Status codes. */
+#define MEK_OK 0            /* stop rule met */
+#define MEK_MAXITER 1       /* max_iters updates made, rule not met */
+#define MEK_EXACT 2         /* ||R^k||_F = 0 exactly */
+#define MEK_EINVAL (-1)     /* bad argument (sizes, NULL, theta, alpha, ...) */
+#define MEK_ENOMEM (-2)     /* device allocation failed */
+#define MEK_EHIP (-3)       /* a HIP runtime call failed */
+#define MEK_ENONFINITE (-4) /* NaN or Inf in an input */
+#define MEK_EDIVERGED (-5)  /* ||R^k||_F^2 not finite or above diverge * ||R^0||_F^2 */
+#define MEK_EUNSUPPORTED (-6) /* valid request this build cannot run */
+#define MEK_ETIMEOUT (-7)   /* a cross-work-group wait exceeded its spin limit */
+
+/* Opaque plan: device copies of A and B plus everything precomputed from
+ * them (row norms ||A_i||^2, ||A||_F^2, A A^T, B^T B, alpha). */
+typedef struct mek_plan_s* mek_plan;
+
+typedef struct {
+    int precision;   /* MEK_FP64 / MEK_FP32 / MEK_MIXED */
+    double alpha;    /* > 0: the step alpha; <= 0: alpha = 1/||B||_2^2 (Sec. 5),
+                        ||B||_2^2 from power iteration on B B^T */
+    int team_wgs;    /* 0: automatic; > 0: number of work-groups that share one
+                        solve (testing and tuning hook) */
+    int r_in_lds;    /* -1: automatic; 0: keep R in device memory; 1: require R
+                        resident in LDS (MEK_EUNSUPPORTED if it does not fit) */
+} mek_plan_opts;
+
+typedef struct {
+    int variant;          /* MEK_BK ... MEK_MWRBK */
+    double theta;         /* relaxation of Alg. 4, in [0, 1]; GRBK uses 1/2 */
+    double alpha;         /* > 0 overrides the plan's alpha; values outside
+                             (0, 2/||B||_2^2), the range of the convergence
+                             theorems, are rejected with MEK_EINVAL */
+    int stop;             /* MEK_STOP_* */
+    double tol;           /* tolerance of the stop rule */
+    const double* X_ref;  /* device, p x q; needed for MEK_STOP_REL_ERR and for
+                             err_hist, else may be NULL */
+    int64_t max_iters;    /* cap on the number of updates (>= 0) */
+    uint64_t seed;        /* Philox4x64-10 key word 0 */
+    uint64_t instance;    /* Philox4x64-10 key word 1 */
+    const int32_t* replay_idx; /* device, optional: forced row indices for
+                             updates k < replay_len (test hook) */
+    int64_t replay_len;
+    double diverge;       /* > 0: stop with MEK_EDIVERGED once ||R^k||^2 >
+                             diverge * ||R^0||^2; <= 0: off */
+    /* Histories, device, caller-owned, each of capacity hist_cap entries
+     * (entries past the capacity are dropped; NULL = not recorded):
+     *   resid_hist[k] = ||R^k||_F^2 for k = 0..iters,
+     *   err_hist[k]   = ||X^k - X_ref||_F / ||X_ref||_F for k = 0..iters,
+     *   idx_hist[k]   = i_k (0-based) for k = 0..iters-1,
+     *   set_hist[k]   = size of the index set of update k (greedy variants). */
+    double* resid_hist;
+    double* err_hist;
+    int32_t* idx_hist;
+    int32_t* set_hist;
+    int64_t hist_cap;
+    /* MEK_MIXED only: FP32 updates per refinement pass (0: automatic). */
+    int64_t inner_iters;
+} mek_solve_opts;
+
+typedef struct {
+    int64_t iters;       /* updates made */
+    int status;          /* MEK_OK / MEK_MAXITER / MEK_EXACT / MEK_EDIVERGED / MEK_ETIMEOUT */
+    double resid2;       /* ||R||_F^2 of the returned iterate (as tracked) */
+    double rel_err;      /* ||X - X_ref||_F/||X_ref||_F, NaN without X_ref */
+    double alpha;        /* step used */
+    int team_wgs;        /* work-groups per solve */
+    int r_in_lds;        /* 1 if R stayed in LDS */
+    int passes;          /* MEK_MIXED refinement passes (1 otherwise) */
+    double kernel_ms;    /* time of the persistent solver launch(es), measured
+                            with HIP events on `stream` around each launch */
+} mek_report;
+
+/* ABI version (MEK_ABI_VERSION). */
+int mek_version(void);
+
+/* Static string naming a status code. */
+const char* mek_status_string(int status);
+
+/* Build a plan for A (m x p) and B (q x n), both device pointers. The plan
+ * copies A and B, so they may be freed after the call. Precomputes
+ * ||A_i||^2, ||A||_F^2, the Gram matrices A A^T and B^T B (the remark after
+ * Alg. 3) and alpha. Errors: MEK_EINVAL (sizes <= 0, NULL pointers, bad
+ * options), MEK_ENONFINITE (NaN/Inf in A or B), MEK_EINVAL if A or B is
+ * all zero, MEK_ENOMEM, MEK_EHIP. Blocking. `opts` may be NULL (defaults:
+ * FP64, alpha = 1/||B||_2^2, automatic layout). */
+int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n,
+                    const double* A, const double* B, const mek_plan_opts* opts, void* stream);
+
+/* Release a plan and its device memory. NULL is accepted. */
+int mek_plan_destroy(mek_plan plan);
+
+/* Copy plan data to caller memory (device pointers, each may be NULL):
+ * row_norms (m) = ||A_i||^2, gram_a (m x m) = A A^T, gram_b (n x n) =
+ * B^T B; *alpha (host) = the plan's step. Blocking. */
+int mek_plan_query(mek_plan plan, double* row_norms, double* gram_a, double* gram_b,
+                   double* alpha, void* stream);
+
+/* Solve A X B = C with the plan's A and B. C (m x n), X0 (p x q, NULL means
+ * zero) and X (p x q, output) are device pointers; X may alias X0. Runs
+ * the whole iteration on the GPU in one persistent launch (MIXED: one per
+ * refinement pass) and synchronises `stream` before returning. The report
+ * (host struct) may be NULL. Returns the final status (>= 0: X written). */
+int mek_solve(mek_plan plan, const double* C, const double* X0, const mek_solve_opts* opts,
+              double* X, mek_report* report, void* stream);
+
+/* ---- Unit entry points: the hot path's stages run on their own. ---- */
+
+/* out[j] = u_{k0+j} for j < count: the uniform draw of update k0+j,
+ * (w0 >> 11) * 2^-53 with w0 the first word of Philox4x64-10 under key
+ * (seed, instance) and counter (k+1, 0, 0, 0). `out` is device memory. */
+int mek_philox_uniform(uint64_t seed, uint64_t instance, int64_t k0, int64_t count,
+                       double* out, void* stream);
+
+/* Run the selection step of update k (k0 <= k < k0+count) on fixed weights:
+ * r (m, device) = ||R_i^k||^2, a (m, device) = ||A_i||^2, F_A = ||A||_F^2.
+ * Writes idx[j] (device, count) = the row chosen for update k0+j. If
+ * in_set (device, m bytes) is not NULL it receives the index set of
+ * Algs. 3/4 (for MWRBK the chosen row), and if set_list (device, m int32)
+ * is not NULL the set's rows compacted in ascending order; stats (device,
+ * 4 doubles, optional) = {threshold t, set weight T, ||R||_F^2, set size}. */
+int mek_select(int variant, int64_t m, const double* r, const double* a, double F_A,
+               double theta, uint64_t seed, uint64_t instance, int64_t k0, int64_t count,
+               int32_t* idx, uint8_t* in_set, int32_t* set_list, double* stats, void* stream);
+
+/* Residual engine: R = C - A X B for A (m x p), X (p x q), B (q x n),
+ * C (m x n), all device double, computed as two FP64 MFMA GEMMs
+ * (T = A X, then R = C - T B). R must not alias the inputs. Blocking. */
+int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, const double* X,
+                 const double* B, const double* C, double* R, void* stream);
+
+/* Gram products by the FP64 MFMA GEMM: G = M M^T (transpose_first = 0,
+ * G rows x rows) or G = M^T M (transpose_first = 1, G cols x cols) for M
+ * (rows x cols), all device double. Blocking. */
+int mek_gram(int64_t rows, int64_t cols, const double* M, int transpose_first, double* G,
+             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MEK_H */

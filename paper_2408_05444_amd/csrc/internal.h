@@ -1,0 +1,135 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace mek {
+
+// Status codes (mirror the public header's MEK_* values).
+enum : int {
+    kOK = 0,
+    kMaxIter = 1,
+    kExact = 2,
+    kEInval = -1,
+    kENoMem = -2,
+    kEHip = -3,
+    kENonFinite = -4,
+    kEDiverged = -5,
+    kEUnsupported = -6,
+    kETimeout = -7,
+};
+
+enum : int { kBK = 0, kRBK = 1, kGRBK = 2, kRGRBK = 3, kMWRBK = 4 };
+enum : int { kStopNone = 0, kStopRelErr = 1, kStopRelResid = 2 };
+
+// Result of a solve as written by the kernel (device memory).
+struct DevReport {
+    long long iters;
+    int status;
+    int last_set;
+    double S;       // ||R||_F^2 at exit
+    double err;     // relative error at exit (NaN without a reference)
+};
+
+// Everything the persistent solver kernel needs for one instance. T is the
+// storage/update type of R, X and the Gram matrices (double or float);
+// norms, selection and the stop test are always double.
+template <typename T>
+struct SolveParams {
+    int m, p, q, n;
+    // Plan data.
+    const T* A;        // m x p
+    const T* B;        // q x n
+    const T* GA;       // m x m, A A^T
+    const T* GB;       // n x n, B^T B
+    const double* a;   // m, ||A_i||^2
+    double F_A;        // ||A||_F^2
+    const int* active; // rows with ||A_i|| > 0, ascending
+    int n_active;
+    // State.
+    T* R;              // m x n residual (initial value in, storage if not in LDS)
+    T* Xt;             // q x p, the iterate transposed
+    const double* Xref_t;  // q x p or null
+    double ref2;       // ||X_ref||_F^2
+    double C2;         // ||C||_F^2 (REL_RESID denominator, squared)
+    double* r;         // m row norms of R
+    T* rowbuf;         // n, the published row R_{i_k}
+    T* wbuf;           // n, w = R_{i_k} B^T B
+    double* errpart;   // 2 * W partial ||X - X_ref||^2
+    TeamSync* sync;
+    DevReport* report;
+    // Options.
+    int variant;
+    double theta;
+    double alpha;
+    int stop;
+    double tol;
+    long long max_iters;
+    unsigned long long seed, inst;
+    long long k_offset;          // Philox counter offset (refinement passes)
+    const int32_t* replay;
+    long long replay_len;
+    double diverge;
+    double* resid_hist;
+    double* err_hist;
+    int32_t* idx_hist;
+    int32_t* set_hist;
+    long long hist_cap;
+    long long hist_offset;       // history index of this launch's k = 0
+    double S_target;             // > 0: also stop (OK) once ||R||_F^2 <= S_target
+    unsigned long long* phase;   // optional: per-phase wall-clock ticks (3 timed work-groups)
+    int a_in_lds;                // keep ||A_i||^2 for all rows in LDS
+    // Team layout.
+    int W;      // work-groups in the team
+    int rpw;    // rows of R per work-group
+    int xpw;    // columns of X (rows of X^T) per work-group
+    int wpw;    // entries of w per work-group
+};
+
+// Launchers (solver.hip).
+hipError_t launch_solve(const SolveParams<double>& P, bool r_in_lds, size_t lds_bytes,
+                        hipStream_t s);
+hipError_t launch_solve(const SolveParams<float>& P, bool r_in_lds, size_t lds_bytes,
+                        hipStream_t s);
+size_t solve_lds_bytes(int rpw, int n, int xpw, int wpw, size_t elem, bool r_in_lds);
+size_t solve_lds_budget();
+size_t solve_lds_bytes_a(int m);
+
+hipError_t launch_select(int variant, int m, const double* r, const double* a, double F_A,
+                         double theta, uint64_t seed, uint64_t inst, long long k0,
+                         long long count, int32_t* idx, uint8_t* in_set, int32_t* set_list,
+                         double* stats, const int* active, int n_active, hipStream_t s);
+hipError_t launch_philox(uint64_t seed, uint64_t inst, long long k0, long long count,
+                         double* out, hipStream_t s);
+
+// Dense kernels (gemm.hip).
+// D = beta * C + alpha * A B, A(i,k) = A[i*a_i + k*a_k], B(k,j) = B[k*b_k + j*b_j],
+// C, D row-major with leading dimensions ldc, ldd (C may be null when beta == 0).
+hipError_t gemm_f64(int M, int N, int K, double alpha, const double* A, long long a_i,
+                    long long a_k, const double* B, long long b_k, long long b_j, double beta,
+                    const double* C, long long ldc, double* D, long long ldd, hipStream_t s);
+
+// Utility kernels (util.hip).
+hipError_t row_sq_norms(const double* A, int m, int p, double* out, hipStream_t s);
+hipError_t sum_reduce(const double* x, long long len, double* out, hipStream_t s);
+hipError_t sq_norm(const double* x, long long len, double* out, hipStream_t s);
+hipError_t sq_diff_norm(const double* x, const double* y, long long len, double* out,
+                        hipStream_t s);
+hipError_t nonfinite_count(const double* x, long long len, int* out, hipStream_t s);
+hipError_t active_rows(const double* a, int m, int* list, int* count, hipStream_t s);
+template <typename T>
+hipError_t transpose_to(const double* X, int rows, int cols, T* Xt, hipStream_t s);
+template <typename T>
+hipError_t transpose_from(const T* Xt, int rows, int cols, double* X, hipStream_t s);
+hipError_t convert_f64_f32(const double* x, long long len, float* y, hipStream_t s);
+hipError_t copy_f64(const double* x, long long len, double* y, hipStream_t s);
+hipError_t fill_zero_bytes(void* x, long long bytes, hipStream_t s);
+// out = a x + b y elementwise (out may alias x or y).
+hipError_t lincomb_f64(double a, const double* x, double b, const double* y, long long len,
+                       double* out, hipStream_t s);
+hipError_t power_iteration_max_eig(const double* G, int q, double* out, hipStream_t s);
+
+}  // namespace mek

@@ -1,0 +1,729 @@
+// Persistent solver kernel for the greedy block Kaczmarz family (Algs. 1-5 of
+// the paper) on gfx950.
+//
+// One launch runs the whole iteration for one instance. The instance is
+// split over a *team* of W co-resident work-groups (a cooperative launch):
+//   - work-group g owns rows [g*rpw, (g+1)*rpw) of the residual R. When they
+//     fit, those rows live in LDS for the whole solve, so R never travels to
+//     HBM inside the loop; otherwise they stay in device memory.
+//   - it owns rows [g*xpw, ...) of X^T (columns of X) and entries
+//     [g*wpw, ...) of the vector w = R_{i_k} B^T B.
+// Per update k every work-group
+//   1. reads all row norms r_i = ||R_i||^2 and computes ||R||_F^2, the
+//      maximum ratio max_i r_i/||A_i||^2 and the stop test, then runs the
+//      selection rule itself (redundantly, in a fixed reduction order, so all
+//      work-groups pick the same i_k without another exchange);
+//   2. gets the selected row R_{i_k} (published by its owner when R is in
+//      LDS; read directly otherwise) and computes its share of
+//      v = R_{i_k} B^T (the X update, Alg. 3's X^{k+1}) and of
+//      w = R_{i_k} (B^T B) (the residual update, Alg. 3's R^{k+1});
+//   3. after a team barrier, updates its own rows
+//      R_i -= alpha/||A_i_k||^2 (A A^T)_{i,i_k} w and recomputes their norms
+//      in the same pass; another barrier closes the update.
+#include "internal.h"
+
+#include <float.h>
+#include <limits.h>
+#include <math.h>
+
+namespace mek {
+
+// ---------------------------------------------------------------------------
+// Cross-work-group exchange. The few values that work-groups hand to each
+// other every update (row norms, the published row, slices of w, error
+// partials) are written and read with relaxed agent-scope atomics, which
+// the compiler turns into plain stores/loads that go to the device-wide
+// coherence point (cache policy sc1). Before a work-group signals a team
+// barrier or flag it waits for its own outstanding stores (s_waitcnt), so
+// its data is in place before the signal can be seen; a reader only loads
+// after it has seen the signal. No L2 write-back or invalidate is needed,
+// so read-only operands (A, B, A A^T, B^T B, ||A_i||^2) stay cached in L2.
+// ---------------------------------------------------------------------------
+template <typename U>
+__device__ __forceinline__ U xload(const U* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename U>
+__device__ __forceinline__ void xstore(U* p, U v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct SelectOut {
+    int idx;
+    int setsize;
+    double t;
+    double T;
+};
+
+// Inverse-CDF draw over a row set held in registers (thread t owns the rows
+// [b, b + cnt)). GREEDY: the set is {i : a_i > 0, r_i / a_i >= t} with
+// weights r_i (Algs. 3/4); otherwise every row with a_i > 0, weight a_i
+// (Alg. 1). A block-wide exclusive scan of the chunk sums and counts gives
+// each chunk its starting prefix and each member its position in the
+// compacted set. The chosen row is the first whose running sum exceeds
+// u * T (T the set's total weight), else the set's last row.
+template <bool GREEDY, int SR>
+__device__ __forceinline__ SelectOut sample_set(int b, int cnt, const double (&rr)[SR],
+                                                const double (&aa)[SR], const double (&rho)[SR],
+                                                double t, double u, BlockScratch& sc,
+                                                int32_t* set_list, uint8_t* in_set) {
+    unsigned int mask = 0;
+    double ws = 0.0;
+    int c = 0, lastm = -1;
+#pragma unroll
+    for (int j = 0; j < SR; ++j) {
+        const bool mem = j < cnt && aa[j] > 0.0 && (!GREEDY || rho[j] >= t);
+        if (mem) {
+            mask |= 1u << j;
+            ws += rr[j];
+            ++c;
+            lastm = b + j;
+        }
+    }
+    if (threadIdx.x == 0) {
+        sc.out_i[2] = INT_MAX;   // first crossing row
+        sc.out_i[3] = -1;        // last row of the set
+    }
+    double pre_w, T;
+    int pre_c, tot_c;
+    block_excl_scan(ws, c, pre_w, pre_c, T, tot_c, sc);
+    const double target = u * T;
+    int cand = INT_MAX;
+    double run = pre_w;
+    int pos = pre_c;
+#pragma unroll
+    for (int j = 0; j < SR; ++j) {
+        if ((mask >> j) & 1u) {
+            if (set_list) set_list[pos] = b + j;
+            if (in_set) in_set[b + j] = 1;
+            ++pos;
+            run += rr[j];
+            if (cand == INT_MAX && run > target) cand = b + j;
+        }
+    }
+    // Integer min / max in LDS: the result does not depend on arrival order.
+    if (cand != INT_MAX) atomicMin(&sc.out_i[2], cand);
+    if (lastm >= 0) atomicMax(&sc.out_i[3], lastm);
+    __syncthreads();
+    SelectOut o;
+    o.idx = (sc.out_i[2] != INT_MAX) ? sc.out_i[2] : sc.out_i[3];
+    o.setsize = tot_c;
+    o.t = t;
+    o.T = T;
+    __syncthreads();
+    return o;
+}
+
+// The selection step of update k for Algs. 1-5, run by one whole work-group.
+// Thread t holds rows [b, b + cnt) (cnt <= SR, contiguous chunks in
+// thread order) with rr[j] = ||R_i||^2 and aa[j] = ||A_i||^2 in registers.
+// S = sum of all r, M = max over rows with a_i > 0 of r_i / a_i; the greedy
+// threshold is t = min(M, theta M + (1 - theta) S / F_A).
+template <int SR>
+__device__ __forceinline__ SelectOut select_rows(int variant, int b, int cnt,
+                                                 const double (&rr)[SR], const double (&aa)[SR],
+                                                 const double (&rho)[SR], double S, double M,
+                                                 double F_A, double theta, double u, long long k,
+                                                 const int* __restrict__ active, int n_active,
+                                                 BlockScratch& sc, int32_t* set_list,
+                                                 uint8_t* in_set) {
+    SelectOut o;
+    o.setsize = 0;
+    o.t = 0.0;
+    o.T = 0.0;
+    if (variant == kBK) {
+        o.idx = active[k % n_active];
+        return o;
+    }
+    if (variant == kMWRBK) {
+        int cand = INT_MAX;
+#pragma unroll
+        for (int j = 0; j < SR; ++j)
+            if (j < cnt && aa[j] > 0.0 && rho[j] == M) cand = min(cand, b + j);
+        if (threadIdx.x == 0) sc.out_i[2] = INT_MAX;
+        __syncthreads();
+        if (cand != INT_MAX) atomicMin(&sc.out_i[2], cand);
+        __syncthreads();
+        o.idx = sc.out_i[2];
+        __syncthreads();
+        o.setsize = 1;
+        o.t = M;
+        if (threadIdx.x == 0) {
+            if (in_set) in_set[o.idx] = 1;
+            if (set_list) set_list[0] = o.idx;
+        }
+        return o;
+    }
+    if (variant == kGRBK || variant == kRGRBK) {
+        // Evaluated as written (no fused multiply-add): each operation is
+        // rounded in turn, as in a plain evaluation of the formula.
+#pragma clang fp contract(off)
+        const double th = (variant == kGRBK) ? 0.5 : theta;
+        double t = th * M + (1.0 - th) * (S / F_A);
+        if (t > M) t = M;
+        return sample_set<true, SR>(b, cnt, rr, aa, rho, t, u, sc, set_list, in_set);
+    }
+    return sample_set<false, SR>(b, cnt, aa, aa, rho, 0.0, u, sc, set_list, in_set);
+}
+
+// ---------------------------------------------------------------------------
+// Tagged exchange words. Work-groups of a team hand each other four kinds of
+// values every update: row norms r_i, error partials, the selected row
+// R_{i_k} and the slices of w. Each value travels in one 64-bit word that
+// also carries a 2-bit sequence tag, so a reader polls the data itself
+// until the tags show the current update: the signal and the data arrive
+// together, and no team-wide barrier is needed. A double keeps the tag in its
+// two lowest mantissa bits (a change of at most 3 units in the last place,
+// the size of one rounding; an exact zero stays zero); a float keeps its 32
+// bits and the tag sits in the upper half of the word. Words are written
+// and read with agent-scope relaxed atomics (aligned 64-bit, so a reader
+// never sees half of a word).
+//
+// One buffer per kind suffices: every rewrite of a word is causally after
+// every work-group has read its previous contents (the next r needs every
+// slice of w, each slice of w needs the published row, and the next row
+// needs every r), so a reader waiting for tag t can only see tag t or the
+// tag of the update before.
+// ---------------------------------------------------------------------------
+typedef unsigned long long xword;
+
+__device__ __forceinline__ unsigned int seq_tag(long long k) { return (unsigned int)((k + 1) & 3); }
+
+__device__ __forceinline__ xword pack_word(double v, unsigned int tag) {
+    return ((xword)__double_as_longlong(v) & ~3ull) | tag;
+}
+__device__ __forceinline__ xword pack_word(float v, unsigned int tag) {
+    return ((xword)tag << 32) | (xword)__float_as_uint(v);
+}
+template <typename T> __device__ __forceinline__ T word_value(xword w);
+template <> __device__ __forceinline__ double word_value<double>(xword w) {
+    return ((w & 0x7FFFFFFFFFFFFFFCull) == 0) ? 0.0 : __longlong_as_double((long long)w);
+}
+template <> __device__ __forceinline__ float word_value<float>(xword w) {
+    return __uint_as_float((unsigned int)w);
+}
+template <typename T> __device__ __forceinline__ unsigned int word_tag(xword w);
+template <> __device__ __forceinline__ unsigned int word_tag<double>(xword w) {
+    return (unsigned int)(w & 3);
+}
+template <> __device__ __forceinline__ unsigned int word_tag<float>(xword w) {
+    return (unsigned int)(w >> 32) & 3;
+}
+
+// Read cnt (<= N) words p[0..cnt) until every one carries `tag`. Returns
+// false if the wait gives up (spin limit, or another work-group aborted).
+template <typename T, int N>
+__device__ __forceinline__ bool poll_words(const xword* p, int cnt, unsigned int tag, T (&out)[N],
+                                           TeamSync* ts) {
+    long long spins = 0;
+    for (;;) {
+        xword w[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) w[j] = (j < cnt) ? xload(p + j) : 0ull;
+        bool ready = true;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (j < cnt) {
+                ready = ready && (word_tag<T>(w[j]) == tag);
+                out[j] = word_value<T>(w[j]);
+            }
+        }
+        if (ready) return true;
+        if ((++spins & 63) == 0 &&
+            (spins > kSpinLimit ||
+             __hip_atomic_load(&ts->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            __hip_atomic_store(&ts->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Strided variant: words p[j * stride] for j < cnt.
+template <typename T, int N>
+__device__ __forceinline__ bool poll_strided(const xword* p, int stride, int cnt, unsigned int tag,
+                                             T (&out)[N], TeamSync* ts) {
+    long long spins = 0;
+    for (;;) {
+        xword w[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) w[j] = (j < cnt) ? xload(p + (size_t)j * stride) : 0ull;
+        bool ready = true;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (j < cnt) {
+                ready = ready && (word_tag<T>(w[j]) == tag);
+                out[j] = word_value<T>(w[j]);
+            }
+        }
+        if (ready) return true;
+        if ((++spins & 63) == 0 &&
+            (spins > kSpinLimit ||
+             __hip_atomic_load(&ts->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            __hip_atomic_store(&ts->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Optional phase timing (work-group 0, thread 0): ticks of the constant-rate
+// wall clock spent in each phase of an update, summed over the solve.
+enum { kPhReduce, kPhSelect, kPhRow, kPhDots, kPhWait, kPhX, kPhUpdate, kPhEnd, kPhCount };
+#define MEK_PHASE(id)                                                   \
+    do {                                                                \
+        if (timing) {                                                   \
+            const unsigned long long now_ = wall_clock64();             \
+            ph[id] += now_ - t_last;                                    \
+            t_last = now_;                                              \
+        }                                                               \
+    } while (0)
+
+template <typename T, bool LDS, int SR>
+__global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
+    extern __shared__ __align__(16) unsigned char dyn_smem[];
+    __shared__ BlockScratch sc;
+    __shared__ int s_fail;   // set once a cross-work-group wait gives up
+    __shared__ double s_err[kWaves];
+    if (threadIdx.x == 0) s_fail = 0;
+
+    const int W = P.W;
+    const bool team = W > 1;
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int m = P.m, n = P.n, p = P.p, q = P.q;
+    const int row0 = g * P.rpw;
+    const int nrow = max(0, min(P.rpw, m - row0));
+    const int xc0 = g * P.xpw;
+    const int nx = max(0, min(P.xpw, q - xc0));
+    const int wc0 = g * P.wpw;
+    const int nw = max(0, min(P.wpw, n - wc0));
+    xword* const r_x = reinterpret_cast<xword*>(P.r);
+    xword* const e_x = reinterpret_cast<xword*>(P.errpart);
+    xword* const row_x = reinterpret_cast<xword*>(P.rowbuf);
+    xword* const w_x = reinterpret_cast<xword*>(P.wbuf);
+
+    // LDS: [own rows of R (LDS mode)] [n-vector staging] [v for own X rows]
+    // [dot-product partial sums] [row norms when the team is one work-group]
+    // [||A_i||^2 for all rows, when P.a_in_lds].
+    const size_t r_bytes = LDS ? (((size_t)P.rpw * n * sizeof(T) + 15) & ~(size_t)15) : 0;
+    const size_t v_bytes = ((size_t)n * sizeof(T) + 15) & ~(size_t)15;
+    const int nseg = (n + kDotSeg - 1) / kDotSeg;
+    T* Rl = reinterpret_cast<T*>(dyn_smem);
+    T* vec = reinterpret_cast<T*>(dyn_smem + r_bytes);
+    double* vl = reinterpret_cast<double*>(dyn_smem + r_bytes + v_bytes);
+    double* part = vl + P.xpw;
+    double* r_local = part + (size_t)(P.xpw + P.wpw) * nseg;
+    double* a_lds = r_local + P.rpw;
+    T* Rown = LDS ? Rl : P.R + (size_t)row0 * n;
+    if (P.a_in_lds)
+        for (int i = tid; i < m; i += kThreads) a_lds[i] = P.a[i];
+    const double* asrc = P.a_in_lds ? a_lds : P.a;
+
+    // ---- Set-up: own rows into LDS, their norms, the first error partial.
+    if (LDS) {
+        const T* src = P.R + (size_t)row0 * n;
+        const size_t tot = (size_t)nrow * n;
+        for (size_t e = tid; e < tot; e += kThreads) Rl[e] = src[e];
+        __syncthreads();
+    }
+    for (int ii = wv; ii < nrow; ii += kWaves) {
+        const T* rp = Rown + (size_t)ii * n;
+        double acc = 0.0;
+        for (int j = lane; j < n; j += kWave) {
+            const double v = (double)rp[j];
+            acc += v * v;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            if (team) xstore(&r_x[row0 + ii], pack_word(acc, seq_tag(0)));
+            else r_local[ii] = acc;
+        }
+    }
+    {
+        double ep = 0.0;
+        if (P.Xref_t) {
+            const size_t base = (size_t)xc0 * p, total = (size_t)nx * p;
+            for (size_t e = tid; e < total; e += kThreads) {
+                const double d = (double)P.Xt[base + e] - P.Xref_t[base + e];
+                ep += d * d;
+            }
+        }
+        double v[1] = {ep};
+        block_sum<1>(v, sc);
+        if (tid == 0) {
+            if (team) xstore(&e_x[g], pack_word(v[0], seq_tag(0)));
+            else s_err[0] = v[0];
+        }
+    }
+    __syncthreads();
+
+    // Timed work-groups: the first, the middle and the last of the team.
+    const int tslot = (g == 0) ? 0 : (g == W / 2) ? 1 : (g == W - 1) ? 2 : -1;
+    const bool timing = P.phase != nullptr && tslot >= 0 && threadIdx.x == 0;
+    unsigned long long ph[kPhCount] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long t_last = timing ? wall_clock64() : 0;
+    const int cs = (m + kThreads - 1) / kThreads;
+    const int sb = min(m, tid * cs);
+    const int scnt = min(m, sb + cs) - sb;
+    double S0 = -1.0, S = 0.0, err = NAN;
+    long long k = 0;
+    int status = kMaxIter, last_set = 0;
+    bool ok = true;
+    const bool has_ref = P.Xref_t != nullptr;
+    while (ok) {
+        const unsigned int tag = seq_tag(k);
+        // The draw of this update depends only on (seed, instance, k): compute
+        // it before waiting for the norms so it overlaps that wait.
+        const double u_k = philox_uniform(P.seed, P.inst, P.k_offset + k);
+        // ---- 1. Global quantities: this thread's chunk of r (polled until
+        // current), its chunk of ||A_i||^2, and one error partial.
+        double rr[SR], aa[SR], rho[SR];
+#pragma unroll
+        for (int j = 0; j < SR; ++j) aa[j] = (j < scnt) ? asrc[sb + j] : 0.0;
+        double Ep = 0.0;
+        if (team) {
+            if (!poll_words<double, SR>(r_x + sb, scnt, tag, rr, P.sync)) s_fail = 1;
+            double e1[1];
+            if (tid < W && !poll_words<double, 1>(e_x + tid, 1, tag, e1, P.sync)) s_fail = 1;
+            if (tid < W) Ep = e1[0];
+        } else {
+#pragma unroll
+            for (int j = 0; j < SR; ++j) rr[j] = (j < scnt) ? r_local[sb + j] : 0.0;
+            if (tid == 0) Ep = s_err[0];
+        }
+        double Sp = 0.0, Mp = -1.0;
+#pragma unroll
+        for (int j = 0; j < SR; ++j) {
+            if (j >= scnt) rr[j] = 0.0;
+            // rho_i = ||R_i||^2 / ||A_i||^2, computed once per update and row.
+            rho[j] = (j < scnt && aa[j] > 0.0) ? rr[j] / aa[j] : -1.0;
+            Sp += rr[j];
+            Mp = fmax(Mp, rho[j]);
+        }
+        block_sum_max_sum(Sp, Mp, Ep, sc);
+        if (s_fail) { ok = false; break; }
+        MEK_PHASE(kPhReduce);
+        S = Sp;
+        const double M = Mp;
+        if (S0 < 0.0) S0 = S;
+        err = has_ref ? sqrt(Ep / P.ref2) : NAN;
+        const long long hk = P.hist_offset + k;
+        if (g == 0 && tid == 0 && hk < P.hist_cap) {
+            if (P.resid_hist) P.resid_hist[hk] = S;
+            if (P.err_hist) P.err_hist[hk] = err;
+        }
+        // Stop tests, in a fixed order (every work-group decides the same).
+        if (P.stop == kStopRelErr && err <= P.tol) { status = kOK; break; }
+        if (P.stop == kStopRelResid && sqrt(S) <= P.tol * sqrt(P.C2)) { status = kOK; break; }
+        if (P.S_target > 0.0 && S <= P.S_target) { status = kOK; break; }
+        if (S == 0.0) { status = kExact; break; }
+        if (!isfinite(S) || (P.diverge > 0.0 && S > P.diverge * S0)) { status = kEDiverged; break; }
+        if (k >= P.max_iters) { status = kMaxIter; break; }
+
+        // ---- Selection.
+        int ik;
+        if (P.replay && k < P.replay_len) {
+            ik = P.replay[k];
+            last_set = 0;
+        } else {
+            const SelectOut so = select_rows<SR>(P.variant, sb, scnt, rr, aa, rho, S, M, P.F_A,
+                                                 P.theta, u_k, k, P.active, P.n_active, sc,
+                                                 nullptr, nullptr);
+            ik = so.idx;
+            last_set = so.setsize;
+        }
+        if (g == 0 && tid == 0 && hk < P.hist_cap) {
+            if (P.idx_hist) P.idx_hist[hk] = ik;
+            if (P.set_hist) P.set_hist[hk] = last_set;
+        }
+        const double c = P.alpha / asrc[ik];
+        MEK_PHASE(kPhSelect);
+
+        // ---- 2. The selected row: its owner publishes it, the others poll
+        // their part of it into the LDS staging vector.
+        const T* rowsrc;
+        if (!team) {
+            rowsrc = Rown + (size_t)(ik - row0) * n;
+        } else {
+            if (ik / P.rpw == g) {
+                const T* src = Rown + (size_t)(ik - row0) * n;
+                for (int j = tid; j < n; j += kThreads) xstore(&row_x[j], pack_word(src[j], tag));
+            }
+            T rv[kVecRegs];
+            const int nreg = max(0, min(kVecRegs, (n - tid + kThreads - 1) / kThreads));
+            if (!poll_strided<T, kVecRegs>(row_x + tid, kThreads, nreg, tag, rv, P.sync)) s_fail = 1;
+#pragma unroll
+            for (int u = 0; u < kVecRegs; ++u)
+                if (u < nreg) vec[tid + u * kThreads] = rv[u];
+            for (int j = tid + kVecRegs * kThreads; j < n; j += kThreads) {
+                T one[1];
+                if (!poll_words<T, 1>(row_x + j, 1, tag, one, P.sync)) s_fail = 1;
+                vec[j] = one[0];
+            }
+            __syncthreads();
+            if (s_fail) { ok = false; break; }
+            rowsrc = vec;
+        }
+        MEK_PHASE(kPhRow);
+        // Dot products of the row with rows d < nx of B (giving v, for the X
+        // update) and rows of B^T B (this work-group's slice of w, by symmetry
+        // of B^T B). Each (dot, segment of kDotSeg entries) is one wave task
+        // with kDotUnroll loads in flight per lane; the partial sums are added
+        // in segment order, so the result does not depend on scheduling.
+        {
+            const int ntask = (nx + nw) * nseg;
+            for (int task = wv; task < ntask; task += kWaves) {
+                const int d = task / nseg, sg = task - d * nseg;
+                const T* mrow = (d < nx) ? P.B + (size_t)(xc0 + d) * n
+                                         : P.GB + (size_t)(wc0 + d - nx) * n;
+                const int j0 = sg * kDotSeg + lane;
+                T yv[kDotUnroll];
+#pragma unroll
+                for (int u = 0; u < kDotUnroll; ++u) {
+                    const int j = j0 + u * kWave;
+                    yv[u] = (j < n) ? mrow[j] : (T)0;
+                }
+                double acc = 0.0;
+#pragma unroll
+                for (int u = 0; u < kDotUnroll; ++u) {
+                    const int j = j0 + u * kWave;
+                    if (j < n) acc += (double)rowsrc[j] * (double)yv[u];
+                }
+                acc = wave_sum(acc);
+                if (lane == 0) part[task] = acc;
+            }
+            __syncthreads();
+            for (int d = tid; d < nx + nw; d += kThreads) {
+                double acc = 0.0;
+                for (int sg = 0; sg < nseg; ++sg) acc += part[d * nseg + sg];
+                if (d < nx)
+                    vl[d] = acc;
+                else if (!team)
+                    vec[d - nx] = (T)acc;
+                else
+                    xstore(&w_x[wc0 + d - nx], pack_word((T)acc, tag));
+            }
+        }
+        __syncthreads();
+        MEK_PHASE(kPhDots);
+        // Poll w (all slices) into registers; the X update below runs while
+        // the first loads are in flight.
+        T wreg[kVecRegs];
+        int wcnt = 0;
+        if (team) {
+            wcnt = max(0, min(kVecRegs, (n - tid + kThreads - 1) / kThreads));
+            if (!poll_strided<T, kVecRegs>(w_x + tid, kThreads, wcnt, tag, wreg, P.sync)) s_fail = 1;
+        }
+        MEK_PHASE(kPhWait);
+        // X^T rows l: X^T[l, :] += (c A_{i_k, :}) v_l, one wave per row, with
+        // the squared error against the reference in the same pass.
+        {
+            const T* arow = P.A + (size_t)ik * p;
+            double ep = 0.0;
+            for (int l = wv; l < nx; l += kWaves) {
+                T* xr = P.Xt + (size_t)(xc0 + l) * p;
+                const double* rr_ = has_ref ? P.Xref_t + (size_t)(xc0 + l) * p : nullptr;
+                const T vlT = (T)vl[l];
+                for (int s2 = lane; s2 < p; s2 += kWave) {
+                    const T nv = xr[s2] + (T)(c * (double)arow[s2]) * vlT;
+                    xr[s2] = nv;
+                    if (has_ref) {
+                        const double d = (double)nv - rr_[s2];
+                        ep += d * d;
+                    }
+                }
+            }
+            ep = wave_sum(ep);
+            if (lane == 0) s_err[wv] = ep;
+        }
+        if (team) {
+#pragma unroll
+            for (int u = 0; u < kVecRegs; ++u)
+                if (u < wcnt) vec[tid + u * kThreads] = wreg[u];
+            for (int j = tid + kVecRegs * kThreads; j < n; j += kThreads) {
+                T one[1];
+                if (!poll_words<T, 1>(w_x + j, 1, tag, one, P.sync)) s_fail = 1;
+                vec[j] = one[0];
+            }
+        }
+        __syncthreads();
+        if (s_fail) { ok = false; break; }
+        MEK_PHASE(kPhX);
+        // ---- 3. Own rows: R_i -= (c (A A^T)_{i_k, i}) w and r_i = ||R_i||^2,
+        // one wave per row; publish the norms and the error partial with the
+        // next update's tag.
+        {
+            const unsigned int ntag = seq_tag(k + 1);
+            const T* garow = P.GA + (size_t)ik * m + row0;
+            for (int ii = wv; ii < nrow; ii += kWaves) {
+                const T sc_i = (T)(c * (double)garow[ii]);
+                T* rp = Rown + (size_t)ii * n;
+                double acc = 0.0;
+                for (int j = lane; j < n; j += kWave) {
+                    const T v = rp[j] - sc_i * vec[j];
+                    rp[j] = v;
+                    acc += (double)v * (double)v;
+                }
+                acc = wave_sum(acc);
+                if (lane == 0) {
+                    if (team) xstore(&r_x[row0 + ii], pack_word(acc, ntag));
+                    else r_local[ii] = acc;
+                }
+            }
+            if (tid == 0) {
+                double e = 0.0;
+                for (int w2 = 0; w2 < kWaves; ++w2) e += s_err[w2];
+                if (team) xstore(&e_x[g], pack_word(e, ntag));
+                else s_err[0] = e;
+            }
+        }
+        __syncthreads();
+        MEK_PHASE(kPhUpdate);
+        ++k;
+    }
+    if (s_fail) status = kETimeout;
+    if (timing)
+        for (int i = 0; i < kPhCount; ++i) P.phase[tslot * kPhCount + i] += ph[i];
+    if (g == 0 && tid == 0) {
+        P.report->iters = k;
+        P.report->status = status;
+        P.report->last_set = last_set;
+        P.report->S = S;
+        P.report->err = err;
+    }
+}
+
+size_t solve_lds_budget() { return 160 * 1024 - 1024; }
+
+size_t solve_lds_bytes(int rpw, int n, int xpw, int wpw, size_t elem, bool r_in_lds) {
+    size_t b = r_in_lds ? (((size_t)rpw * n * elem + 15) & ~(size_t)15) : 0;
+    b += ((size_t)n * elem + 15) & ~(size_t)15;
+    const size_t nseg = ((size_t)n + kDotSeg - 1) / kDotSeg;
+    b += (size_t)xpw * sizeof(double) + (size_t)(xpw + wpw) * nseg * sizeof(double);
+    return b + (size_t)rpw * sizeof(double);   // row norms of a one-work-group team
+}
+
+size_t solve_lds_bytes_a(int m) { return (size_t)m * sizeof(double); }
+
+template <typename T, bool LDS, int SR>
+static hipError_t launch_one(const SolveParams<T>& P, size_t lds_bytes, hipStream_t s) {
+    auto kern = solve_kernel<T, LDS, SR>;
+    // Raise the dynamic LDS cap for this kernel; if the runtime refuses, the
+    // launch below reports the error.
+    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes) != hipSuccess)
+        (void)hipGetLastError();
+    SolveParams<T> copy = P;
+    void* args[] = {&copy};
+    if (P.W == 1)
+        return hipLaunchKernel((const void*)kern, dim3(1), dim3(kThreads), args, lds_bytes, s);
+    return hipLaunchCooperativeKernel((const void*)kern, dim3(P.W), dim3(kThreads), args,
+                                      (unsigned int)lds_bytes, s);
+}
+
+// Rows of the selection chunk per thread, rounded up to a power of two.
+int sel_rows_for(int m) {
+    const int cs = (m + kThreads - 1) / kThreads;
+    return cs <= 1 ? 1 : cs <= 2 ? 2 : cs <= 4 ? 4 : cs <= 8 ? 8 : 16;
+}
+
+template <typename T, bool LDS>
+static hipError_t launch_sr(const SolveParams<T>& P, size_t lds_bytes, hipStream_t s) {
+    switch (sel_rows_for(P.m)) {
+        case 1: return launch_one<T, LDS, 1>(P, lds_bytes, s);
+        case 2: return launch_one<T, LDS, 2>(P, lds_bytes, s);
+        case 4: return launch_one<T, LDS, 4>(P, lds_bytes, s);
+        case 8: return launch_one<T, LDS, 8>(P, lds_bytes, s);
+        default: return launch_one<T, LDS, 16>(P, lds_bytes, s);
+    }
+}
+
+hipError_t launch_solve(const SolveParams<double>& P, bool r_in_lds, size_t lds_bytes,
+                        hipStream_t s) {
+    return r_in_lds ? launch_sr<double, true>(P, lds_bytes, s)
+                    : launch_sr<double, false>(P, lds_bytes, s);
+}
+hipError_t launch_solve(const SolveParams<float>& P, bool r_in_lds, size_t lds_bytes,
+                        hipStream_t s) {
+    return r_in_lds ? launch_sr<float, true>(P, lds_bytes, s)
+                    : launch_sr<float, false>(P, lds_bytes, s);
+}
+
+// ---------------------------------------------------------------------------
+// Unit kernels: the selection step and the Philox draws on their own.
+// ---------------------------------------------------------------------------
+template <int SR>
+__global__ void __launch_bounds__(kThreads, 1)
+select_kernel(int variant, int m, const double* r, const double* a, double F_A, double theta,
+              uint64_t seed, uint64_t inst, long long k0, long long count, int32_t* idx,
+              uint8_t* in_set, int32_t* set_list, double* stats, const int* active,
+              int n_active) {
+    __shared__ BlockScratch sc;
+    const int cs = (m + kThreads - 1) / kThreads;
+    const int b = min(m, (int)threadIdx.x * cs);
+    const int cnt = min(m, b + cs) - b;
+    double rr[SR], aa[SR], rho[SR];
+    double Sp = 0.0, Mp = -1.0, dummy = 0.0;
+#pragma unroll
+    for (int j = 0; j < SR; ++j) {
+        rr[j] = (j < cnt) ? r[b + j] : 0.0;
+        aa[j] = (j < cnt) ? a[b + j] : 0.0;
+        rho[j] = (j < cnt && aa[j] > 0.0) ? rr[j] / aa[j] : -1.0;
+        Sp += rr[j];
+        Mp = fmax(Mp, rho[j]);
+    }
+    block_sum_max_sum(Sp, Mp, dummy, sc);
+    for (long long j = 0; j < count; ++j) {
+        const bool first = (j == 0);
+        const SelectOut o = select_rows<SR>(variant, b, cnt, rr, aa, rho, Sp, Mp, F_A, theta,
+                                            philox_uniform(seed, inst, k0 + j), k0 + j, active,
+                                            n_active, sc, first ? set_list : nullptr,
+                                            first ? in_set : nullptr);
+        if (threadIdx.x == 0) {
+            idx[j] = o.idx;
+            if (first && stats) {
+                stats[0] = o.t;
+                stats[1] = (variant == kMWRBK) ? r[o.idx] : o.T;
+                stats[2] = Sp;
+                stats[3] = (double)o.setsize;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_select(int variant, int m, const double* r, const double* a, double F_A,
+                         double theta, uint64_t seed, uint64_t inst, long long k0,
+                         long long count, int32_t* idx, uint8_t* in_set, int32_t* set_list,
+                         double* stats, const int* active, int n_active, hipStream_t s) {
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(1), dim3(kThreads), 0, s, variant, m, r, a, F_A, theta,
+                           seed, inst, k0, count, idx, in_set, set_list, stats, active, n_active);
+        return hipGetLastError();
+    };
+    switch (sel_rows_for(m)) {
+        case 1: return go(select_kernel<1>);
+        case 2: return go(select_kernel<2>);
+        case 4: return go(select_kernel<4>);
+        case 8: return go(select_kernel<8>);
+        default: return go(select_kernel<16>);
+    }
+}
+
+__global__ void philox_kernel(uint64_t seed, uint64_t inst, long long k0, long long count,
+                              double* out) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < count) out[j] = philox_uniform(seed, inst, k0 + j);
+}
+
+hipError_t launch_philox(uint64_t seed, uint64_t inst, long long k0, long long count,
+                         double* out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const long long blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(philox_kernel, dim3((unsigned)blocks), dim3(256), 0, s, seed, inst, k0,
+                       count, out);
+    return hipGetLastError();
+}
+
+}  // namespace mek

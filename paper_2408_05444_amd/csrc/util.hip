@@ -1,0 +1,255 @@
+// Small dense kernels around the solver: norms, transposes, conversions,
+// the active-row list and the power iteration for ||B||_2^2.
+#include "internal.h"
+
+#include <math.h>
+
+namespace mek {
+
+// ||A_i||^2 for every row: one wave per row, lanes stride over the columns.
+__global__ void row_sq_norms_kernel(const double* __restrict__ A, int m, int p,
+                                    double* __restrict__ out) {
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (wave >= m) return;
+    const double* row = A + (size_t)wave * p;
+    double s = 0.0;
+    for (int j = lane; j < p; j += kWave) s += row[j] * row[j];
+    s = wave_sum(s);
+    if (lane == 0) out[wave] = s;
+}
+
+hipError_t row_sq_norms(const double* A, int m, int p, double* out, hipStream_t s) {
+    const int waves_per_block = 4;
+    const int blocks = (m + waves_per_block - 1) / waves_per_block;
+    hipLaunchKernelGGL(row_sq_norms_kernel, dim3(blocks), dim3(waves_per_block * kWave), 0, s, A,
+                       m, p, out);
+    return hipGetLastError();
+}
+
+// Single-work-group reductions: a fixed order, so the result does not depend
+// on scheduling. mode 0: sum x; 1: sum x^2; 2: sum (x - y)^2.
+__global__ void __launch_bounds__(kThreads, 1)
+reduce_kernel(const double* __restrict__ x, const double* __restrict__ y, long long len, int mode,
+              double* out) {
+    __shared__ BlockScratch sc;
+    double acc[1] = {0.0};
+    for (long long e = threadIdx.x; e < len; e += kThreads) {
+        const double v = x[e];
+        if (mode == 0) acc[0] += v;
+        else if (mode == 1) acc[0] += v * v;
+        else {
+            const double d = v - y[e];
+            acc[0] += d * d;
+        }
+    }
+    block_sum<1>(acc, sc);
+    if (threadIdx.x == 0) *out = acc[0];
+}
+
+hipError_t sum_reduce(const double* x, long long len, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, x, nullptr, len, 0, out);
+    return hipGetLastError();
+}
+hipError_t sq_norm(const double* x, long long len, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, x, nullptr, len, 1, out);
+    return hipGetLastError();
+}
+hipError_t sq_diff_norm(const double* x, const double* y, long long len, double* out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, x, y, len, 2, out);
+    return hipGetLastError();
+}
+
+__global__ void nonfinite_kernel(const double* __restrict__ x, long long len, int* out) {
+    int bad = 0;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+         e += (long long)gridDim.x * blockDim.x)
+        bad |= !isfinite(x[e]);
+    if (__any(bad) && (threadIdx.x & (kWave - 1)) == 0) atomicAdd(out, 1);
+}
+
+hipError_t nonfinite_count(const double* x, long long len, int* out, hipStream_t s) {
+    hipError_t e = fill_zero_bytes(out, sizeof(int), s);
+    if (e != hipSuccess) return e;
+    long long blocks = (len + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, len, out);
+    return hipGetLastError();
+}
+
+// List of rows with a_i > 0 in ascending order (chunk per thread + scan).
+__global__ void __launch_bounds__(kThreads, 1)
+active_rows_kernel(const double* __restrict__ a, int m, int* list, int* count) {
+    __shared__ BlockScratch sc;
+    const int cs = (m + kThreads - 1) / kThreads;
+    const int b = min(m, (int)threadIdx.x * cs), e = min(m, b + cs);
+    int cnt = 0;
+    for (int i = b; i < e; ++i) cnt += (a[i] > 0.0);
+    double pre_v, tot_v;
+    int pre_c, tot_c;
+    block_excl_scan(0.0, cnt, pre_v, pre_c, tot_v, tot_c, sc);
+    int pos = pre_c;
+    for (int i = b; i < e; ++i)
+        if (a[i] > 0.0) list[pos++] = i;
+    if (threadIdx.x == 0) *count = tot_c;
+}
+
+hipError_t active_rows(const double* a, int m, int* list, int* count, hipStream_t s) {
+    hipLaunchKernelGGL(active_rows_kernel, dim3(1), dim3(kThreads), 0, s, a, m, list, count);
+    return hipGetLastError();
+}
+
+// Xt (cols x rows, type T) = transpose of X (rows x cols, double); 32x32 LDS tiles.
+template <typename T>
+__global__ void transpose_to_kernel(const double* __restrict__ X, int rows, int cols,
+                                    T* __restrict__ Xt) {
+    __shared__ double tile[32][33];
+    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+    for (int y = threadIdx.y; y < 32; y += blockDim.y) {
+        const int i = bi + y, j = bj + threadIdx.x;
+        if (i < rows && j < cols) tile[y][threadIdx.x] = X[(size_t)i * cols + j];
+    }
+    __syncthreads();
+    for (int y = threadIdx.y; y < 32; y += blockDim.y) {
+        const int j = bj + y, i = bi + threadIdx.x;
+        if (i < rows && j < cols) Xt[(size_t)j * rows + i] = (T)tile[threadIdx.x][y];
+    }
+}
+
+template <typename T>
+__global__ void transpose_from_kernel(const T* __restrict__ Xt, int rows, int cols,
+                                      double* __restrict__ X) {
+    __shared__ double tile[32][33];
+    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;   // bi over rows of X, bj over cols
+    for (int y = threadIdx.y; y < 32; y += blockDim.y) {
+        const int j = bj + y, i = bi + threadIdx.x;
+        if (i < rows && j < cols) tile[y][threadIdx.x] = (double)Xt[(size_t)j * rows + i];
+    }
+    __syncthreads();
+    for (int y = threadIdx.y; y < 32; y += blockDim.y) {
+        const int i = bi + y, j = bj + threadIdx.x;
+        if (i < rows && j < cols) X[(size_t)i * cols + j] = tile[threadIdx.x][y];
+    }
+}
+
+template <typename T>
+hipError_t transpose_to(const double* X, int rows, int cols, T* Xt, hipStream_t s) {
+    dim3 grid((cols + 31) / 32, (rows + 31) / 32), block(32, 8);
+    hipLaunchKernelGGL(transpose_to_kernel<T>, grid, block, 0, s, X, rows, cols, Xt);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t transpose_from(const T* Xt, int rows, int cols, double* X, hipStream_t s) {
+    dim3 grid((cols + 31) / 32, (rows + 31) / 32), block(32, 8);
+    hipLaunchKernelGGL(transpose_from_kernel<T>, grid, block, 0, s, Xt, rows, cols, X);
+    return hipGetLastError();
+}
+template hipError_t transpose_to<double>(const double*, int, int, double*, hipStream_t);
+template hipError_t transpose_to<float>(const double*, int, int, float*, hipStream_t);
+template hipError_t transpose_from<double>(const double*, int, int, double*, hipStream_t);
+template hipError_t transpose_from<float>(const float*, int, int, double*, hipStream_t);
+
+__global__ void convert_kernel(const double* __restrict__ x, long long len, float* __restrict__ y) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+         e += (long long)gridDim.x * blockDim.x)
+        y[e] = (float)x[e];
+}
+__global__ void copy_kernel(const double* __restrict__ x, long long len, double* __restrict__ y) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+         e += (long long)gridDim.x * blockDim.x)
+        y[e] = x[e];
+}
+__global__ void zero_kernel(unsigned int* __restrict__ x, long long words) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < words;
+         e += (long long)gridDim.x * blockDim.x)
+        x[e] = 0u;
+}
+__global__ void lincomb_kernel(double a, const double* x, double b, const double* y,
+                               long long len, double* out) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+         e += (long long)gridDim.x * blockDim.x)
+        out[e] = a * x[e] + b * y[e];
+}
+
+static dim3 ew_grid(long long len) {
+    long long b = (len + 255) / 256;
+    if (b > 2048) b = 2048;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+hipError_t convert_f64_f32(const double* x, long long len, float* y, hipStream_t s) {
+    hipLaunchKernelGGL(convert_kernel, ew_grid(len), dim3(256), 0, s, x, len, y);
+    return hipGetLastError();
+}
+hipError_t copy_f64(const double* x, long long len, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(copy_kernel, ew_grid(len), dim3(256), 0, s, x, len, y);
+    return hipGetLastError();
+}
+// Zero a buffer whose size is a multiple of 4 bytes with a kernel (not a
+// memset node, so the call is safe inside captured graphs).
+hipError_t fill_zero_bytes(void* x, long long bytes, hipStream_t s) {
+    const long long words = (bytes + 3) / 4;
+    hipLaunchKernelGGL(zero_kernel, ew_grid(words), dim3(256), 0, s, (unsigned int*)x, words);
+    return hipGetLastError();
+}
+hipError_t lincomb_f64(double a, const double* x, double b, const double* y, long long len,
+                       double* out, hipStream_t s) {
+    hipLaunchKernelGGL(lincomb_kernel, ew_grid(len), dim3(256), 0, s, a, x, b, y, len, out);
+    return hipGetLastError();
+}
+
+// Largest eigenvalue of the symmetric positive semidefinite q x q matrix G by
+// power iteration with the Rayleigh quotient, one work-group. Stops when the
+// quotient changes by less than 1e-15 relative for 8 steps in a row, or after
+// 50000 steps.
+__global__ void __launch_bounds__(kThreads, 1)
+power_kernel(const double* __restrict__ G, int q, double* out, double* vbuf) {
+    __shared__ BlockScratch sc;
+    // vbuf: 2 * q doubles of scratch (device memory).
+    double* v = vbuf;
+    double* w = vbuf + q;
+    for (int i = threadIdx.x; i < q; i += kThreads) v[i] = 1.0 + 0.125 * (double)(i % 7);
+    __syncthreads();
+    double nv[1] = {0.0};
+    for (int i = threadIdx.x; i < q; i += kThreads) nv[0] += v[i] * v[i];
+    block_sum<1>(nv, sc);
+    double inv = 1.0 / sqrt(nv[0]);
+    for (int i = threadIdx.x; i < q; i += kThreads) v[i] *= inv;
+    __syncthreads();
+    double lam = 0.0;
+    int stable = 0;
+    for (int it = 0; it < 50000 && stable < 8; ++it) {
+        double acc[2] = {0.0, 0.0};   // v.w and w.w
+        for (int i = threadIdx.x; i < q; i += kThreads) {
+            const double* gr = G + (size_t)i * q;
+            double s = 0.0;
+            for (int j = 0; j < q; ++j) s += gr[j] * v[j];
+            w[i] = s;
+            acc[0] += v[i] * s;
+            acc[1] += s * s;
+        }
+        block_sum<2>(acc, sc);
+        const double nl = acc[0];
+        stable = (fabs(nl - lam) <= 1e-15 * fabs(nl)) ? stable + 1 : 0;
+        lam = nl;
+        const double invw = acc[1] > 0.0 ? 1.0 / sqrt(acc[1]) : 0.0;
+        for (int i = threadIdx.x; i < q; i += kThreads) v[i] = w[i] * invw;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = lam;
+}
+
+hipError_t power_iteration_max_eig(const double* G, int q, double* out, hipStream_t s) {
+    double* vbuf = nullptr;
+    hipError_t e = hipMallocAsync((void**)&vbuf, sizeof(double) * 2 * (size_t)q, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(power_kernel, dim3(1), dim3(kThreads), 0, s, G, q, out, vbuf);
+    e = hipGetLastError();
+    hipError_t f = hipFreeAsync(vbuf, s);
+    return e != hipSuccess ? e : f;
+}
+
+}  // namespace mek

@@ -1,0 +1,116 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, its structs match the Python binding byte for byte, and
+argument validation rejects bad calls before touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+import paper_2408_05444_amd as mek
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mek.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(mek_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for want in ["mek_version", "mek_status_string", "mek_plan_create", "mek_plan_destroy",
+                 "mek_plan_query", "mek_solve", "mek_philox_uniform", "mek_select",
+                 "mek_residual", "mek_gram"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = mek.lib()
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", mek.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(mek_\w+)", out))
+    assert set(_declared_functions()) <= exported
+
+
+def test_version_and_status_strings():
+    hdr = open(HEADER).read()
+    ver = int(re.search(r"#define MEK_ABI_VERSION (\d+)", hdr).group(1))
+    assert mek.mek_version() == ver
+    for code in [0, 1, 2, -1, -2, -3, -4, -5, -6, -7]:
+        assert mek.mek_status_string(code) != "unknown status"
+    assert mek.mek_status_string(99) == "unknown status"
+
+
+def test_constants_match_header():
+    hdr = open(HEADER).read()
+    consts = dict((k, int(v.strip("()"))) for k, v in
+                  re.findall(r"#define (MEK_[A-Z0-9_]+) \(?(-?\d+)\)?", hdr))
+    for k, v in consts.items():
+        if hasattr(mek, k):
+            assert getattr(mek, k) == v, k
+
+
+def test_struct_layouts_match_c():
+    src = r"""
+    #include <stdio.h>
+    #include <stddef.h>
+    #include "mek.h"
+    #define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+    int main(void) {
+      printf("mek_plan_opts %zu\nmek_solve_opts %zu\nmek_report %zu\n",
+             sizeof(mek_plan_opts), sizeof(mek_solve_opts), sizeof(mek_report));
+      F(mek_solve_opts, X_ref) F(mek_solve_opts, max_iters) F(mek_solve_opts, replay_len)
+      F(mek_solve_opts, hist_cap) F(mek_solve_opts, inner_iters) F(mek_solve_opts, set_hist)
+      F(mek_report, passes) F(mek_report, alpha) F(mek_plan_opts, r_in_lds)
+      return 0;
+    }
+    """
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    vals = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    assert int(vals["mek_plan_opts"]) == ctypes.sizeof(mek.mek_plan_opts)
+    assert int(vals["mek_solve_opts"]) == ctypes.sizeof(mek.mek_solve_opts)
+    assert int(vals["mek_report"]) == ctypes.sizeof(mek.mek_report)
+    for key, v in vals.items():
+        if "." in key:
+            T, f = key.split(".")
+            assert getattr(getattr(mek, T), f).offset == int(v), key
+
+
+def test_host_validation_rejects_before_any_gpu_work():
+    L = mek.lib()
+    h = ctypes.c_void_p()
+    vp = ctypes.c_void_p
+    EINVAL = mek.MEK_EINVAL
+    assert L.mek_plan_create(None, 1, 1, 1, 1, vp(1), vp(1), None, None) == EINVAL
+    assert L.mek_plan_create(ctypes.byref(h), 0, 1, 1, 1, vp(1), vp(1), None, None) == EINVAL
+    assert L.mek_plan_create(ctypes.byref(h), 2, 2, 2, -3, vp(1), vp(1), None, None) == EINVAL
+    assert L.mek_plan_create(ctypes.byref(h), 2, 2, 2, 2, None, vp(1), None, None) == EINVAL
+    bad = mek.mek_plan_opts(7, 0.0, 0, -1)
+    assert L.mek_plan_create(ctypes.byref(h), 2, 2, 2, 2, vp(1), vp(1), ctypes.byref(bad), None) == EINVAL
+    bad = mek.mek_plan_opts(0, float("nan"), 0, -1)
+    assert L.mek_plan_create(ctypes.byref(h), 2, 2, 2, 2, vp(1), vp(1), ctypes.byref(bad), None) == EINVAL
+    assert L.mek_solve(None, vp(1), None, None, vp(1), None, None) == EINVAL
+    assert L.mek_select(9, 10, vp(1), vp(1), 1.0, 0.5, 0, 0, 0, 1, vp(1), None, None, None, None) == EINVAL
+    assert L.mek_select(2, 10, vp(1), vp(1), 1.0, 1.5, 0, 0, 0, 1, vp(1), None, None, None, None) == EINVAL
+    assert L.mek_select(2, 10, vp(1), vp(1), 0.0, 0.5, 0, 0, 0, 1, vp(1), None, None, None, None) == EINVAL
+    assert L.mek_select(2, 0, vp(1), vp(1), 1.0, 0.5, 0, 0, 0, 1, vp(1), None, None, None, None) == EINVAL
+    assert L.mek_philox_uniform(0, 0, 0, -1, vp(1), None) == EINVAL
+    assert L.mek_philox_uniform(0, 0, -5, 3, vp(1), None) == EINVAL
+    assert L.mek_philox_uniform(0, 0, 0, 0, None, None) == mek.MEK_OK
+    assert L.mek_residual(0, 1, 1, 1, vp(1), vp(1), vp(1), vp(1), vp(2), None) == EINVAL
+    assert L.mek_residual(1, 1, 1, 1, vp(1), vp(1), vp(1), vp(1), vp(1), None) == EINVAL  # R aliases
+    assert L.mek_gram(3, 3, vp(1), 2, vp(2), None) == EINVAL
+    assert L.mek_gram(3, 3, vp(1), 0, vp(1), None) == EINVAL
+    assert L.mek_plan_destroy(None) == mek.MEK_OK
