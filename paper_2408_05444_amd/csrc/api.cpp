@@ -32,6 +32,7 @@ struct Workspace {
     double* r = nullptr;       // m
     void* rowbuf = nullptr;    // n * 8 bytes
     void* wbuf = nullptr;      // n * 8 bytes
+    void* vbuf = nullptr;      // q * 8 bytes
     double* errpart = nullptr; // 2 * 256
     TeamSync* sync = nullptr;
     DevReport* report = nullptr;
@@ -53,9 +54,9 @@ struct mek_plan_s {
     int n_active = 0;
     int cus = 0;
     int device = 0;
-    double *A = nullptr, *B = nullptr, *GA = nullptr, *GB = nullptr, *a = nullptr;
+    double *A = nullptr, *B = nullptr, *BT = nullptr, *GA = nullptr, *GB = nullptr, *a = nullptr;
     int* active = nullptr;
-    float *A32 = nullptr, *B32 = nullptr, *GA32 = nullptr, *GB32 = nullptr;
+    float *A32 = nullptr, *B32 = nullptr, *BT32 = nullptr, *GA32 = nullptr, *GB32 = nullptr;
     Workspace ws;
 };
 
@@ -128,6 +129,7 @@ int ensure_workspace(mek_plan_s* P) {
     add(m * 8);
     add(n * 8);
     add(n * 8);
+    add(q * 8);
     add(2 * 256 * 8);
     add(sizeof(TeamSync));
     add(sizeof(DevReport));
@@ -151,6 +153,7 @@ int ensure_workspace(mek_plan_s* P) {
     w.r = carve<double>(cur, m);
     w.rowbuf = carve<double>(cur, n);
     w.wbuf = carve<double>(cur, n);
+    w.vbuf = carve<double>(cur, q);
     w.errpart = carve<double>(cur, 2 * 256);
     w.sync = carve<TeamSync>(cur, 1);
     w.report = carve<DevReport>(cur, 1);
@@ -162,8 +165,8 @@ int ensure_workspace(mek_plan_s* P) {
 
 void free_plan(mek_plan_s* P) {
     if (!P) return;
-    void* ptrs[] = {P->A, P->B, P->GA, P->GB, P->a, P->active, P->A32, P->B32, P->GA32, P->GB32,
-                    P->ws.base};
+    void* ptrs[] = {P->A, P->B, P->BT, P->GA, P->GB, P->a, P->active, P->A32, P->B32, P->BT32,
+                    P->GA32, P->GB32, P->ws.base};
     for (void* x : ptrs)
         if (x) (void)hipFree(x);
     delete P;
@@ -187,7 +190,7 @@ int choose_layout(const mek_plan_s* P, size_t elem, Layout* L) {
     // The selection keeps at most kSelRows row norms per thread in registers,
     // and the n-vector staging buffer must fit in LDS.
     if (m > (int64_t)kSelRows * kThreads) return MEK_EUNSUPPORTED;
-    if ((size_t)n * elem + 4096 > solve_lds_budget()) return MEK_EUNSUPPORTED;
+    if ((size_t)std::max(n, q) * elem + 4096 > solve_lds_budget()) return MEK_EUNSUPPORTED;
     const int cus = std::max(1, P->cus);
     const size_t budget = solve_lds_budget();
     int W;
@@ -195,7 +198,8 @@ int choose_layout(const mek_plan_s* P, size_t elem, Layout* L) {
     auto fits = [&](int Wc) {
         const int rpw = ceil_div(m, Wc);
         const int Wr = ceil_div(m, rpw);
-        return solve_lds_bytes(rpw, (int)n, ceil_div(q, Wr), ceil_div(n, Wr), elem, true) <= budget;
+        return solve_lds_bytes(rpw, (int)n, (int)q, ceil_div(q, Wr), ceil_div(n, Wr), elem, true) <=
+               budget;
     };
     if (P->team_wgs > 0) {
         W = (int)std::min<int64_t>({(int64_t)P->team_wgs, (int64_t)cus, m});
@@ -209,7 +213,10 @@ int choose_layout(const mek_plan_s* P, size_t elem, Layout* L) {
         for (int Wc = 1; Wc <= std::min<int64_t>(cus, m); ++Wc)
             if (fits(Wc)) { Wl = Wc; break; }
         if (P->r_in_lds != 0 && Wl > 0) {
+            // With R in LDS, spread the rows over as many CUs as there are
+            // (fewer rows per work-group, even load): the LDS fits any W >= Wl.
             W = std::max(Wt, Wl);
+            if (work >= (int64_t)cus * 4096) W = std::max(W, (int)std::min<int64_t>(cus, m));
             lds = true;
         } else {
             if (P->r_in_lds == 1) return MEK_EUNSUPPORTED;
@@ -224,7 +231,7 @@ int choose_layout(const mek_plan_s* P, size_t elem, Layout* L) {
     L->xpw = ceil_div(q, W);
     L->wpw = ceil_div(n, W);
     L->lds = lds && fits(W);
-    L->lds_bytes = solve_lds_bytes(L->rpw, (int)n, L->xpw, L->wpw, elem, L->lds);
+    L->lds_bytes = solve_lds_bytes(L->rpw, (int)n, (int)q, L->xpw, L->wpw, elem, L->lds);
     if (L->lds_bytes > budget || W > kMaxTeam) return MEK_EUNSUPPORTED;
     // ||A_i||^2 of all rows goes to LDS too when there is room.
     L->a_lds = L->lds_bytes + solve_lds_bytes_a((int)m) <= budget;
@@ -262,6 +269,7 @@ void fill_common(SolveParams<T>& K, const mek_plan_s* P, const mek_solve_opts* o
     K.n_active = P->n_active;
     K.r = P->ws.r;
     K.rowbuf = (T*)P->ws.rowbuf;
+    K.vbuf = (T*)P->ws.vbuf;
     K.wbuf = (T*)P->ws.wbuf;
     K.errpart = P->ws.errpart;
     K.sync = P->ws.sync;
@@ -307,11 +315,13 @@ int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double a
     if (sizeof(T) == 8) {
         K.A = (const T*)P->A;
         K.B = (const T*)P->B;
+        K.BT = (const T*)P->BT;
         K.GA = (const T*)P->GA;
         K.GB = (const T*)P->GB;
     } else {
         K.A = (const T*)P->A32;
         K.B = (const T*)P->B32;
+        K.BT = (const T*)P->BT32;
         K.GA = (const T*)P->GA32;
         K.GB = (const T*)P->GB32;
     }
@@ -329,6 +339,9 @@ int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double a
     static const bool phases = getenv("MEK_PHASES") && getenv("MEK_PHASES")[0] == '1';
     K.phase = phases ? P->ws.phase : nullptr;
     K.a_in_lds = L.a_lds ? 1 : 0;
+    // Pause between polls of exchange words (tuning knob MEK_POLL_SLEEP).
+    static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
+    K.poll_sleep = poll_sleep;
     if (phases) MEK_TRY(fill_zero_bytes(P->ws.phase, 32 * 8, s));
     // Exchange words start with tag 0, which no update waits for.
     MEK_TRY(fill_zero_bytes(P->ws.sync, sizeof(TeamSync), s));
@@ -336,6 +349,7 @@ int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double a
     MEK_TRY(fill_zero_bytes(P->ws.r, (long long)P->m * 8, s));
     MEK_TRY(fill_zero_bytes(P->ws.rowbuf, (long long)P->n * 8, s));
     MEK_TRY(fill_zero_bytes(P->ws.wbuf, (long long)P->n * 8, s));
+    MEK_TRY(fill_zero_bytes(P->ws.vbuf, (long long)P->q * 8, s));
     hipEvent_t ev[2];
     MEK_TRY(hipEventCreate(&ev[0]));
     if (hipEventCreate(&ev[1]) != hipSuccess) {
@@ -431,12 +445,15 @@ int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n, c
     auto fail = [&](int code) { free_plan(P); return code; };
     auto alloc = [&](void** ptr, size_t bytes) { return hipMalloc(ptr, bytes); };
     if (alloc((void**)&P->A, (size_t)(m * p) * 8) || alloc((void**)&P->B, (size_t)(q * n) * 8) ||
+        alloc((void**)&P->BT, (size_t)(q * n) * 8) ||
         alloc((void**)&P->GA, (size_t)(m * m) * 8) || alloc((void**)&P->GB, (size_t)(n * n) * 8) ||
         alloc((void**)&P->a, (size_t)m * 8) || alloc((void**)&P->active, (size_t)m * 4) ||
         ensure_workspace(P))
         return fail(MEK_ENOMEM);
     Workspace& w = P->ws;
-    if (copy_f64(A, m * p, P->A, s) || copy_f64(B, q * n, P->B, s)) return fail(MEK_EHIP);
+    if (copy_f64(A, m * p, P->A, s) || copy_f64(B, q * n, P->B, s) ||
+        transpose_to<double>(P->B, (int)q, (int)n, P->BT, s))
+        return fail(MEK_EHIP);
     if ((st = finite_check(P->A, m * p, w.iscal, s))) return fail(st);
     if ((st = finite_check(P->B, q * n, w.iscal, s))) return fail(st);
     // ||A_i||^2, ||A||_F^2 and the rows that can be selected.
@@ -470,9 +487,11 @@ int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n, c
     if (!(P->alpha < 2.0 / P->b2 * (1.0 + 1e-9))) return fail(MEK_EINVAL);
     if (P->precision != MEK_FP64) {
         if (alloc((void**)&P->A32, (size_t)(m * p) * 4) || alloc((void**)&P->B32, (size_t)(q * n) * 4) ||
+            alloc((void**)&P->BT32, (size_t)(q * n) * 4) ||
             alloc((void**)&P->GA32, (size_t)(m * m) * 4) || alloc((void**)&P->GB32, (size_t)(n * n) * 4))
             return fail(MEK_ENOMEM);
         if (convert_f64_f32(P->A, m * p, P->A32, s) || convert_f64_f32(P->B, q * n, P->B32, s) ||
+            convert_f64_f32(P->BT, q * n, P->BT32, s) ||
             convert_f64_f32(P->GA, m * m, P->GA32, s) || convert_f64_f32(P->GB, n * n, P->GB32, s))
             return fail(MEK_EHIP);
     }

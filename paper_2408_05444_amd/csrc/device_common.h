@@ -15,6 +15,16 @@ constexpr int kSelRows = 16;      // rows of the selection chunk per thread (m <
 constexpr int kDotUnroll = 16;    // loads in flight per lane in a dot-product task
 constexpr int kDotSeg = kDotUnroll * kWave;   // entries per dot-product task
 constexpr int kVecRegs = 8;       // n-vector entries per thread held in registers
+constexpr int kUTable = 128;      // Philox draws computed ahead, per refill
+
+// LDS doubles for dot-product partial sums: the larger of the two dot
+// batches of an update (xpw dots over n entries, wpw dots over q entries),
+// plus n more for w when the team is a single work-group.
+__host__ __device__ inline int dot_parts(int xpw, int n, int wpw, int q) {
+    const int seg = kDotUnroll * kWave;
+    const int a = xpw * ((n + seg - 1) / seg), b = wpw * ((q + seg - 1) / seg);
+    return (a > b ? a : b) + n;
+}
 
 // ---------------------------------------------------------------------------
 // Wave-level reductions and scans on DPP row permutations (register-level
@@ -113,9 +123,9 @@ struct BlockScratch {
 };
 
 // Sum of NV values per thread over the block; every thread receives the
-// totals. The reduction order is fixed (lane butterfly, then waves in
-// order), so identical inputs give bit-identical results in every
-// work-group.
+// totals. Waves reduce on DPP, then every thread adds the wave totals in
+// wave order from LDS, so identical inputs give bit-identical results in
+// every work-group.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], BlockScratch& s) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
@@ -126,18 +136,17 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], BlockScratch& s) {
         for (int j = 0; j < NV; ++j) s.d[wv][j] = v[j];
     }
     __syncthreads();
-    if (threadIdx.x < NV) {
-        double t = 0.0;
-        for (int w = 0; w < kWaves; ++w) t += s.d[w][threadIdx.x];
-        s.out_d[threadIdx.x] = t;
-    }
-    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = s.out_d[j];
+    for (int j = 0; j < NV; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) t += s.d[w][j];
+        v[j] = t;
+    }
     __syncthreads();
 }
 
-// Sum (slot 0, 2) and max (slot 1) in one pass.
+// Sum (a, b) and max (mx) in one pass.
 __device__ __forceinline__ void block_sum_max_sum(double& a, double& mx, double& b,
                                                   BlockScratch& s) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
@@ -150,21 +159,16 @@ __device__ __forceinline__ void block_sum_max_sum(double& a, double& mx, double&
         s.d[wv][2] = b;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double ta = 0.0, tm = s.d[0][1], tb = 0.0;
-        for (int w = 0; w < kWaves; ++w) {
-            ta += s.d[w][0];
-            tm = fmax(tm, s.d[w][1]);
-            tb += s.d[w][2];
-        }
-        s.out_d[0] = ta;
-        s.out_d[1] = tm;
-        s.out_d[2] = tb;
+    double ta = 0.0, tm = s.d[0][1], tb = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        ta += s.d[w][0];
+        tm = fmax(tm, s.d[w][1]);
+        tb += s.d[w][2];
     }
-    __syncthreads();
-    a = s.out_d[0];
-    mx = s.out_d[1];
-    b = s.out_d[2];
+    a = ta;
+    mx = tm;
+    b = tb;
     __syncthreads();
 }
 
@@ -177,52 +181,47 @@ __device__ __forceinline__ void block_min_max_int(int& mn, int& mx, BlockScratch
         s.i[wv][1] = mx;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int a = s.i[0][0], b = s.i[0][1];
-        for (int w = 1; w < kWaves; ++w) {
-            a = min(a, s.i[w][0]);
-            b = max(b, s.i[w][1]);
-        }
-        s.out_i[0] = a;
-        s.out_i[1] = b;
+    int a = s.i[0][0], b = s.i[0][1];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) {
+        a = min(a, s.i[w][0]);
+        b = max(b, s.i[w][1]);
     }
-    __syncthreads();
-    mn = s.out_i[0];
-    mx = s.out_i[1];
+    mn = a;
+    mx = b;
     __syncthreads();
 }
 
 // Exclusive scan of one double and one int per thread (thread order).
-// Returns the exclusive prefixes; the block totals land in tot_d / tot_i.
+// Returns the exclusive prefixes and the block totals. Each thread adds the
+// totals of the waves before its own in wave order.
 __device__ __forceinline__ void block_excl_scan(double v, int c, double& pre_v, int& pre_c,
                                                 double& tot_v, int& tot_c, BlockScratch& s) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    double iv = wave_incl_scan(v);
-    int ic = wave_incl_scan_int(c);
+    const double iv = wave_incl_scan(v);
+    const int ic = wave_incl_scan_int(c);
     if (lane == kWave - 1) {
-        s.d[wv][0] = iv;
-        s.i[wv][0] = ic;
+        s.d[wv][3] = iv;
+        s.i[wv][2] = ic;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double run = 0.0;
-        int runc = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            double t = s.d[w][0];
-            int tc = s.i[w][0];
-            s.d[w][1] = run;
-            s.i[w][1] = runc;
-            run += t;
-            runc += tc;
+    double off = 0.0, tot = 0.0;
+    int offc = 0, totc = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const double t = s.d[w][3];
+        const int tc = s.i[w][2];
+        if (w < wv) {
+            off += t;
+            offc += tc;
         }
-        s.out_d[0] = run;
-        s.out_i[0] = runc;
+        tot += t;
+        totc += tc;
     }
-    __syncthreads();
-    pre_v = s.d[wv][1] + (iv - v);
-    pre_c = s.i[wv][1] + (ic - c);
-    tot_v = s.out_d[0];
-    tot_c = s.out_i[0];
+    pre_v = off + (iv - v);
+    pre_c = offc + (ic - c);
+    tot_v = tot;
+    tot_c = totc;
     __syncthreads();
 }
 

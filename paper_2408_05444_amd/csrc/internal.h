@@ -43,6 +43,7 @@ struct SolveParams {
     // Plan data.
     const T* A;        // m x p
     const T* B;        // q x n
+    const T* BT;       // n x q, B transposed
     const T* GA;       // m x m, A A^T
     const T* GB;       // n x n, B^T B
     const double* a;   // m, ||A_i||^2
@@ -57,6 +58,7 @@ struct SolveParams {
     double C2;         // ||C||_F^2 (REL_RESID denominator, squared)
     double* r;         // m row norms of R
     T* rowbuf;         // n, the published row R_{i_k}
+    T* vbuf;           // q, v = R_{i_k} B^T
     T* wbuf;           // n, w = R_{i_k} B^T B
     double* errpart;   // 2 * W partial ||X - X_ref||^2
     TeamSync* sync;
@@ -82,6 +84,7 @@ struct SolveParams {
     double S_target;             // > 0: also stop (OK) once ||R||_F^2 <= S_target
     unsigned long long* phase;   // optional: per-phase wall-clock ticks (3 timed work-groups)
     int a_in_lds;                // keep ||A_i||^2 for all rows in LDS
+    int poll_sleep;              // s_sleep length between polls of exchange words
     // Team layout.
     int W;      // work-groups in the team
     int rpw;    // rows of R per work-group
@@ -94,7 +97,7 @@ hipError_t launch_solve(const SolveParams<double>& P, bool r_in_lds, size_t lds_
                         hipStream_t s);
 hipError_t launch_solve(const SolveParams<float>& P, bool r_in_lds, size_t lds_bytes,
                         hipStream_t s);
-size_t solve_lds_bytes(int rpw, int n, int xpw, int wpw, size_t elem, bool r_in_lds);
+size_t solve_lds_bytes(int rpw, int n, int q, int xpw, int wpw, size_t elem, bool r_in_lds);
 size_t solve_lds_budget();
 size_t solve_lds_bytes_a(int m);
 

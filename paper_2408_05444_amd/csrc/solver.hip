@@ -101,9 +101,14 @@ __device__ __forceinline__ SelectOut sample_set(int b, int cnt, const double (&r
             if (cand == INT_MAX && run > target) cand = b + j;
         }
     }
-    // Integer min / max in LDS: the result does not depend on arrival order.
-    if (cand != INT_MAX) atomicMin(&sc.out_i[2], cand);
-    if (lastm >= 0) atomicMax(&sc.out_i[3], lastm);
+    // First crossing and last member: wave min / max on DPP, then one LDS
+    // atomic per wave (integer min / max do not depend on arrival order).
+    cand = wave_min_int(cand);
+    lastm = wave_max_int(lastm);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (cand != INT_MAX) atomicMin(&sc.out_i[2], cand);
+        if (lastm >= 0) atomicMax(&sc.out_i[3], lastm);
+    }
     __syncthreads();
     SelectOut o;
     o.idx = (sc.out_i[2] != INT_MAX) ? sc.out_i[2] : sc.out_i[3];
@@ -141,8 +146,9 @@ __device__ __forceinline__ SelectOut select_rows(int variant, int b, int cnt,
         for (int j = 0; j < SR; ++j)
             if (j < cnt && aa[j] > 0.0 && rho[j] == M) cand = min(cand, b + j);
         if (threadIdx.x == 0) sc.out_i[2] = INT_MAX;
+        cand = wave_min_int(cand);
         __syncthreads();
-        if (cand != INT_MAX) atomicMin(&sc.out_i[2], cand);
+        if ((threadIdx.x & (kWave - 1)) == 0 && cand != INT_MAX) atomicMin(&sc.out_i[2], cand);
         __syncthreads();
         o.idx = sc.out_i[2];
         __syncthreads();
@@ -210,11 +216,24 @@ template <> __device__ __forceinline__ unsigned int word_tag<float>(xword w) {
     return (unsigned int)(w >> 32) & 3;
 }
 
+// Pause between two polls: s_sleep takes an immediate, so the few allowed
+// lengths are dispatched on a (wave-uniform) runtime value.
+__device__ __forceinline__ void poll_pause(int sleep) {
+    switch (sleep) {
+        case 0: break;
+        case 2: __builtin_amdgcn_s_sleep(2); break;
+        case 4: __builtin_amdgcn_s_sleep(4); break;
+        case 8: __builtin_amdgcn_s_sleep(8); break;
+        case 16: __builtin_amdgcn_s_sleep(16); break;
+        default: __builtin_amdgcn_s_sleep(1); break;
+    }
+}
+
 // Read cnt (<= N) words p[0..cnt) until every one carries `tag`. Returns
 // false if the wait gives up (spin limit, or another work-group aborted).
 template <typename T, int N>
 __device__ __forceinline__ bool poll_words(const xword* p, int cnt, unsigned int tag, T (&out)[N],
-                                           TeamSync* ts) {
+                                           TeamSync* ts, int sleep) {
     long long spins = 0;
     for (;;) {
         xword w[N];
@@ -235,14 +254,14 @@ __device__ __forceinline__ bool poll_words(const xword* p, int cnt, unsigned int
             __hip_atomic_store(&ts->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
-        __builtin_amdgcn_s_sleep(1);
+        poll_pause(sleep);
     }
 }
 
 // Strided variant: words p[j * stride] for j < cnt.
 template <typename T, int N>
 __device__ __forceinline__ bool poll_strided(const xword* p, int stride, int cnt, unsigned int tag,
-                                             T (&out)[N], TeamSync* ts) {
+                                             T (&out)[N], TeamSync* ts, int sleep) {
     long long spins = 0;
     for (;;) {
         xword w[N];
@@ -263,8 +282,83 @@ __device__ __forceinline__ bool poll_strided(const xword* p, int stride, int cnt
             __hip_atomic_store(&ts->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
-        __builtin_amdgcn_s_sleep(1);
+        poll_pause(sleep);
     }
+}
+
+// Sum over each row of 16 lanes (DPP): every lane of a row gets the row total.
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_d<kDppSwap1>(v);
+    v += dpp_d<kDppSwap2>(v);
+    v += dpp_d<kDppHalfMirror>(v);
+    v += dpp_d<kDppMirror>(v);
+    return v;
+}
+
+// D dot products sink(d, sum_j x[j] * row(d)[j]) over len entries, x in LDS,
+// the rows in device memory, run by the whole work-group. Short vectors
+// (len <= 16 * kDotUnroll) take 16 lanes per dot, four dots per wave;
+// longer ones are cut into segments of kDotSeg entries, one wave task per
+// (dot, segment), with kDotUnroll loads in flight per lane. Partial sums
+// go to `part` (LDS) and are added in segment order, so the result does
+// not depend on scheduling. Ends with a barrier.
+template <typename T, typename RowFn, typename SinkFn>
+__device__ __forceinline__ void block_dots(const T* x, int len, int D, RowFn row_of, SinkFn sink,
+                                           double* part) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    int nseg = 1;
+    if (len <= 16 * kDotUnroll) {
+        const int sub = lane >> 4, l16 = lane & 15;
+        for (int d0 = wv * 4; d0 < D; d0 += kWaves * 4) {
+            const int d = d0 + sub;
+            double acc = 0.0;
+            if (d < D) {
+                const T* mr = row_of(d);
+                T yv[kDotUnroll];
+#pragma unroll
+                for (int u = 0; u < kDotUnroll; ++u) {
+                    const int j = l16 + 16 * u;
+                    yv[u] = (j < len) ? mr[j] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < kDotUnroll; ++u) {
+                    const int j = l16 + 16 * u;
+                    if (j < len) acc += (double)x[j] * (double)yv[u];
+                }
+            }
+            acc = row16_sum(acc);
+            if (l16 == 0 && d < D) part[d] = acc;
+        }
+    } else {
+        nseg = (len + kDotSeg - 1) / kDotSeg;
+        const int ntask = D * nseg;
+        for (int task = wv; task < ntask; task += kWaves) {
+            const int d = task / nseg, sg = task - d * nseg;
+            const T* mr = row_of(d);
+            const int j0 = sg * kDotSeg + lane;
+            T yv[kDotUnroll];
+#pragma unroll
+            for (int u = 0; u < kDotUnroll; ++u) {
+                const int j = j0 + u * kWave;
+                yv[u] = (j < len) ? mr[j] : (T)0;
+            }
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < kDotUnroll; ++u) {
+                const int j = j0 + u * kWave;
+                if (j < len) acc += (double)x[j] * (double)yv[u];
+            }
+            acc = wave_sum(acc);
+            if (lane == 0) part[task] = acc;
+        }
+    }
+    __syncthreads();
+    for (int d = tid; d < D; d += kThreads) {
+        double acc = 0.0;
+        for (int sg = 0; sg < nseg; ++sg) acc += part[d * nseg + sg];
+        sink(d, acc);
+    }
+    __syncthreads();
 }
 
 // Optional phase timing (work-group 0, thread 0): ticks of the constant-rate
@@ -305,16 +399,16 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
 
     // LDS: [own rows of R (LDS mode)] [n-vector staging] [v for own X rows]
     // [dot-product partial sums] [row norms when the team is one work-group]
-    // [||A_i||^2 for all rows, when P.a_in_lds].
+    // [Philox draws of the next kUTable updates] [||A_i||^2, when P.a_in_lds].
     const size_t r_bytes = LDS ? (((size_t)P.rpw * n * sizeof(T) + 15) & ~(size_t)15) : 0;
-    const size_t v_bytes = ((size_t)n * sizeof(T) + 15) & ~(size_t)15;
-    const int nseg = (n + kDotSeg - 1) / kDotSeg;
+    const size_t v_bytes = ((size_t)max(n, q) * sizeof(T) + 15) & ~(size_t)15;
     T* Rl = reinterpret_cast<T*>(dyn_smem);
     T* vec = reinterpret_cast<T*>(dyn_smem + r_bytes);
     double* vl = reinterpret_cast<double*>(dyn_smem + r_bytes + v_bytes);
     double* part = vl + P.xpw;
-    double* r_local = part + (size_t)(P.xpw + P.wpw) * nseg;
-    double* a_lds = r_local + P.rpw;
+    double* r_local = part + dot_parts(P.xpw, n, P.wpw, q);
+    double* u_tab = r_local + P.rpw;
+    double* a_lds = u_tab + kUTable;
     T* Rown = LDS ? Rl : P.R + (size_t)row0 * n;
     if (P.a_in_lds)
         for (int i = tid; i < m; i += kThreads) a_lds[i] = P.a[i];
@@ -373,9 +467,14 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     const bool has_ref = P.Xref_t != nullptr;
     while (ok) {
         const unsigned int tag = seq_tag(k);
-        // The draw of this update depends only on (seed, instance, k): compute
-        // it before waiting for the norms so it overlaps that wait.
-        const double u_k = philox_uniform(P.seed, P.inst, P.k_offset + k);
+        // Draws depend only on (seed, instance, k): every kUTable updates the
+        // threads compute the next kUTable of them in parallel (one each), so
+        // the ten dependent Philox rounds stay off the per-update path.
+        if ((k % kUTable) == 0) {
+            if (tid < kUTable) u_tab[tid] = philox_uniform(P.seed, P.inst, P.k_offset + k + tid);
+            __syncthreads();
+        }
+        const double u_k = u_tab[k % kUTable];
         // ---- 1. Global quantities: this thread's chunk of r (polled until
         // current), its chunk of ||A_i||^2, and one error partial.
         double rr[SR], aa[SR], rho[SR];
@@ -383,9 +482,9 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         for (int j = 0; j < SR; ++j) aa[j] = (j < scnt) ? asrc[sb + j] : 0.0;
         double Ep = 0.0;
         if (team) {
-            if (!poll_words<double, SR>(r_x + sb, scnt, tag, rr, P.sync)) s_fail = 1;
+            if (!poll_words<double, SR>(r_x + sb, scnt, tag, rr, P.sync, P.poll_sleep)) s_fail = 1;
             double e1[1];
-            if (tid < W && !poll_words<double, 1>(e_x + tid, 1, tag, e1, P.sync)) s_fail = 1;
+            if (tid < W && !poll_words<double, 1>(e_x + tid, 1, tag, e1, P.sync, P.poll_sleep)) s_fail = 1;
             if (tid < W) Ep = e1[0];
         } else {
 #pragma unroll
@@ -452,13 +551,13 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             }
             T rv[kVecRegs];
             const int nreg = max(0, min(kVecRegs, (n - tid + kThreads - 1) / kThreads));
-            if (!poll_strided<T, kVecRegs>(row_x + tid, kThreads, nreg, tag, rv, P.sync)) s_fail = 1;
+            if (!poll_strided<T, kVecRegs>(row_x + tid, kThreads, nreg, tag, rv, P.sync, P.poll_sleep)) s_fail = 1;
 #pragma unroll
             for (int u = 0; u < kVecRegs; ++u)
                 if (u < nreg) vec[tid + u * kThreads] = rv[u];
             for (int j = tid + kVecRegs * kThreads; j < n; j += kThreads) {
                 T one[1];
-                if (!poll_words<T, 1>(row_x + j, 1, tag, one, P.sync)) s_fail = 1;
+                if (!poll_words<T, 1>(row_x + j, 1, tag, one, P.sync, P.poll_sleep)) s_fail = 1;
                 vec[j] = one[0];
             }
             __syncthreads();
@@ -466,58 +565,19 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             rowsrc = vec;
         }
         MEK_PHASE(kPhRow);
-        // Dot products of the row with rows d < nx of B (giving v, for the X
-        // update) and rows of B^T B (this work-group's slice of w, by symmetry
-        // of B^T B). Each (dot, segment of kDotSeg entries) is one wave task
-        // with kDotUnroll loads in flight per lane; the partial sums are added
-        // in segment order, so the result does not depend on scheduling.
-        {
-            const int ntask = (nx + nw) * nseg;
-            for (int task = wv; task < ntask; task += kWaves) {
-                const int d = task / nseg, sg = task - d * nseg;
-                const T* mrow = (d < nx) ? P.B + (size_t)(xc0 + d) * n
-                                         : P.GB + (size_t)(wc0 + d - nx) * n;
-                const int j0 = sg * kDotSeg + lane;
-                T yv[kDotUnroll];
-#pragma unroll
-                for (int u = 0; u < kDotUnroll; ++u) {
-                    const int j = j0 + u * kWave;
-                    yv[u] = (j < n) ? mrow[j] : (T)0;
-                }
-                double acc = 0.0;
-#pragma unroll
-                for (int u = 0; u < kDotUnroll; ++u) {
-                    const int j = j0 + u * kWave;
-                    if (j < n) acc += (double)rowsrc[j] * (double)yv[u];
-                }
-                acc = wave_sum(acc);
-                if (lane == 0) part[task] = acc;
-            }
-            __syncthreads();
-            for (int d = tid; d < nx + nw; d += kThreads) {
-                double acc = 0.0;
-                for (int sg = 0; sg < nseg; ++sg) acc += part[d * nseg + sg];
-                if (d < nx)
-                    vl[d] = acc;
-                else if (!team)
-                    vec[d - nx] = (T)acc;
-                else
-                    xstore(&w_x[wc0 + d - nx], pack_word((T)acc, tag));
-            }
-        }
-        __syncthreads();
+        // v = R_{i_k} B^T: this work-group's entries (rows xc0.. of B), into
+        // LDS and, in a team, published for the others.
+        xword* const v_x = reinterpret_cast<xword*>(P.vbuf);
+        block_dots<T>(rowsrc, n, nx, [&](int d) { return P.B + (size_t)(xc0 + d) * n; },
+                      [&](int d, double val) {
+                          vl[d] = val;
+                          if (team) xstore(&v_x[xc0 + d], pack_word((T)val, tag));
+                      },
+                      part);
         MEK_PHASE(kPhDots);
-        // Poll w (all slices) into registers; the X update below runs while
-        // the first loads are in flight.
-        T wreg[kVecRegs];
-        int wcnt = 0;
-        if (team) {
-            wcnt = max(0, min(kVecRegs, (n - tid + kThreads - 1) / kThreads));
-            if (!poll_strided<T, kVecRegs>(w_x + tid, kThreads, wcnt, tag, wreg, P.sync)) s_fail = 1;
-        }
-        MEK_PHASE(kPhWait);
         // X^T rows l: X^T[l, :] += (c A_{i_k, :}) v_l, one wave per row, with
-        // the squared error against the reference in the same pass.
+        // the squared error against the reference in the same pass. In a team
+        // this runs while the other slices of v are on their way.
         {
             const T* arow = P.A + (size_t)ik * p;
             double ep = 0.0;
@@ -537,19 +597,50 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             ep = wave_sum(ep);
             if (lane == 0) s_err[wv] = ep;
         }
+        MEK_PHASE(kPhX);
+        // All of v, as the left factor of w = v B.
+        const T* vfull;
         if (team) {
+            for (int l0 = 0; l0 < q; l0 += kThreads * kVecRegs) {
+                T tv[kVecRegs];
+                const int cnt = max(0, min(kVecRegs, (q - l0 - tid + kThreads - 1) / kThreads));
+                if (!poll_strided<T, kVecRegs>(v_x + l0 + tid, kThreads, cnt, tag, tv, P.sync, P.poll_sleep)) s_fail = 1;
 #pragma unroll
-            for (int u = 0; u < kVecRegs; ++u)
-                if (u < wcnt) vec[tid + u * kThreads] = wreg[u];
-            for (int j = tid + kVecRegs * kThreads; j < n; j += kThreads) {
-                T one[1];
-                if (!poll_words<T, 1>(w_x + j, 1, tag, one, P.sync)) s_fail = 1;
-                vec[j] = one[0];
+                for (int u = 0; u < kVecRegs; ++u)
+                    if (u < cnt) vec[l0 + tid + u * kThreads] = tv[u];
             }
+            __syncthreads();
+            if (s_fail) { ok = false; break; }
+            vfull = vec;
+        } else {
+            for (int l = tid; l < q; l += kThreads) vec[l] = (T)vl[l];
+            __syncthreads();
+            vfull = vec;
+        }
+        // w = v B for this work-group's entries (rows wc0.. of B^T).
+        block_dots<T>(vfull, q, nw, [&](int d) { return P.BT + (size_t)(wc0 + d) * q; },
+                      [&](int d, double val) {
+                          if (team) xstore(&w_x[wc0 + d], pack_word((T)val, tag));
+                          else part[dot_parts(P.xpw, n, P.wpw, q) - n + d] = val;
+                      },
+                      part);
+        // w into the staging vector.
+        if (team) {
+            for (int j0 = 0; j0 < n; j0 += kThreads * kVecRegs) {
+                T tw[kVecRegs];
+                const int cnt = max(0, min(kVecRegs, (n - j0 - tid + kThreads - 1) / kThreads));
+                if (!poll_strided<T, kVecRegs>(w_x + j0 + tid, kThreads, cnt, tag, tw, P.sync, P.poll_sleep)) s_fail = 1;
+#pragma unroll
+                for (int u = 0; u < kVecRegs; ++u)
+                    if (u < cnt) vec[j0 + tid + u * kThreads] = tw[u];
+            }
+        } else {
+            const double* wl = part + dot_parts(P.xpw, n, P.wpw, q) - n;
+            for (int j = tid; j < n; j += kThreads) vec[j] = (T)wl[j];
         }
         __syncthreads();
         if (s_fail) { ok = false; break; }
-        MEK_PHASE(kPhX);
+        MEK_PHASE(kPhWait);
         // ---- 3. Own rows: R_i -= (c (A A^T)_{i_k, i}) w and r_i = ||R_i||^2,
         // one wave per row; publish the norms and the error partial with the
         // next update's tag.
@@ -596,12 +687,12 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
 
 size_t solve_lds_budget() { return 160 * 1024 - 1024; }
 
-size_t solve_lds_bytes(int rpw, int n, int xpw, int wpw, size_t elem, bool r_in_lds) {
+size_t solve_lds_bytes(int rpw, int n, int q, int xpw, int wpw, size_t elem, bool r_in_lds) {
     size_t b = r_in_lds ? (((size_t)rpw * n * elem + 15) & ~(size_t)15) : 0;
-    b += ((size_t)n * elem + 15) & ~(size_t)15;
-    const size_t nseg = ((size_t)n + kDotSeg - 1) / kDotSeg;
-    b += (size_t)xpw * sizeof(double) + (size_t)(xpw + wpw) * nseg * sizeof(double);
-    return b + (size_t)rpw * sizeof(double);   // row norms of a one-work-group team
+    b += ((size_t)(n > q ? n : q) * elem + 15) & ~(size_t)15;
+    b += (size_t)xpw * sizeof(double) + (size_t)dot_parts(xpw, n, wpw, q) * sizeof(double);
+    b += (size_t)rpw * sizeof(double);   // row norms of a one-work-group team
+    return b + kUTable * sizeof(double); // Philox draws of the coming updates
 }
 
 size_t solve_lds_bytes_a(int m) { return (size_t)m * sizeof(double); }
