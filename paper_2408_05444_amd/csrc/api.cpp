@@ -37,6 +37,7 @@ struct Workspace {
     TeamSync* sync = nullptr;
     DevReport* report = nullptr;
     double* scal = nullptr;    // 8 scalars
+    double* red = nullptr;     // 256 partial sums of the reductions
     int* iscal = nullptr;      // 8 ints
     unsigned long long* phase = nullptr;   // 16 phase-timing counters
 };
@@ -136,6 +137,7 @@ int ensure_workspace(mek_plan_s* P) {
     add(8 * 8);
     add(8 * 4);
     add(32 * 8);
+    add(256 * 8);
     void* base = nullptr;
     MEK_TRY(hipMalloc(&base, need));
     char* cur = (char*)base;
@@ -160,6 +162,7 @@ int ensure_workspace(mek_plan_s* P) {
     w.scal = carve<double>(cur, 8);
     w.iscal = carve<int>(cur, 8);
     w.phase = carve<unsigned long long>(cur, 32);
+    w.red = carve<double>(cur, 256);
     return MEK_OK;
 }
 
@@ -457,7 +460,7 @@ int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n, c
     if ((st = finite_check(P->A, m * p, w.iscal, s))) return fail(st);
     if ((st = finite_check(P->B, q * n, w.iscal, s))) return fail(st);
     // ||A_i||^2, ||A||_F^2 and the rows that can be selected.
-    if (row_sq_norms(P->A, (int)m, (int)p, P->a, s) || sum_reduce(P->a, m, w.scal, s) ||
+    if (row_sq_norms(P->A, (int)m, (int)p, P->a, s) || sum_reduce(P->a, m, w.scal, w.red, s) ||
         active_rows(P->a, (int)m, P->active, w.iscal + 1, s))
         return fail(MEK_EHIP);
     if ((st = read_scalar(w.scal, &P->F_A, s))) return fail(st);
@@ -570,10 +573,10 @@ int mek_solve(mek_plan P, const double* C, const double* X0, const mek_solve_opt
 
     // ||C||_F^2 and ||X_ref||_F^2.
     double C2 = 0.0, ref2 = 0.0;
-    MEK_TRY(sq_norm(C, m * n, w.scal + 2, s));
+    MEK_TRY(sq_norm(C, m * n, w.scal + 2, w.red, s));
     if ((st = read_scalar(w.scal + 2, &C2, s))) return st;
     if (o->X_ref) {
-        MEK_TRY(sq_norm(o->X_ref, p * q, w.scal + 3, s));
+        MEK_TRY(sq_norm(o->X_ref, p * q, w.scal + 3, w.red, s));
         if ((st = read_scalar(w.scal + 3, &ref2, s))) return st;
         if (!(ref2 > 0.0)) ref2 = 1.0;
     }
@@ -632,12 +635,12 @@ int mek_solve(mek_plan P, const double* C, const double* X0, const mek_solve_opt
         for (;;) {
             if ((st = residual_into_R64(w.Xacc))) return st;
             double S = 0.0, err2 = NAN;
-            MEK_TRY(sq_norm(w.R64, m * n, w.scal + 4, s));
+            MEK_TRY(sq_norm(w.R64, m * n, w.scal + 4, w.red, s));
             if ((st = read_scalar(w.scal + 4, &S, s))) return st;
             if (S0 < 0.0) S0 = S;
             double err = NAN;
             if (o->X_ref) {
-                MEK_TRY(sq_diff_norm(w.Xacc, o->X_ref, p * q, w.scal + 5, s));
+                MEK_TRY(sq_diff_norm(w.Xacc, o->X_ref, p * q, w.scal + 5, w.red, s));
                 if ((st = read_scalar(w.scal + 5, &err2, s))) return st;
                 err = sqrt(err2 / ref2);
             }

@@ -117,10 +117,11 @@ hipError_t gemm_f64(int M, int N, int K, double alpha, const double* A, long lon
 
 // Utility kernels (util.hip).
 hipError_t row_sq_norms(const double* A, int m, int p, double* out, hipStream_t s);
-hipError_t sum_reduce(const double* x, long long len, double* out, hipStream_t s);
-hipError_t sq_norm(const double* x, long long len, double* out, hipStream_t s);
+// Fixed-order reductions; scratch holds 256 doubles of partial sums.
+hipError_t sum_reduce(const double* x, long long len, double* out, double* scratch, hipStream_t s);
+hipError_t sq_norm(const double* x, long long len, double* out, double* scratch, hipStream_t s);
 hipError_t sq_diff_norm(const double* x, const double* y, long long len, double* out,
-                        hipStream_t s);
+                        double* scratch, hipStream_t s);
 hipError_t nonfinite_count(const double* x, long long len, int* out, hipStream_t s);
 hipError_t active_rows(const double* a, int m, int* list, int* count, hipStream_t s);
 template <typename T>

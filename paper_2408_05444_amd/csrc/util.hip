@@ -27,14 +27,19 @@ hipError_t row_sq_norms(const double* A, int m, int p, double* out, hipStream_t 
     return hipGetLastError();
 }
 
-// Single-work-group reductions: a fixed order, so the result does not depend
-// on scheduling. mode 0: sum x; 1: sum x^2; 2: sum (x - y)^2.
+// Reductions in two fixed-order stages: kReduceBlocks work-groups each sum
+// a strided share into a partial, then one work-group adds the partials in
+// block order. The result does not depend on scheduling.
+// mode 0: sum x; 1: sum x^2; 2: sum (x - y)^2.
+constexpr int kReduceBlocks = 256;
+
 __global__ void __launch_bounds__(kThreads, 1)
-reduce_kernel(const double* __restrict__ x, const double* __restrict__ y, long long len, int mode,
-              double* out) {
+reduce_partial_kernel(const double* __restrict__ x, const double* __restrict__ y, long long len,
+                      int mode, double* partial) {
     __shared__ BlockScratch sc;
     double acc[1] = {0.0};
-    for (long long e = threadIdx.x; e < len; e += kThreads) {
+    const long long stride = (long long)gridDim.x * kThreads;
+    for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < len; e += stride) {
         const double v = x[e];
         if (mode == 0) acc[0] += v;
         else if (mode == 1) acc[0] += v * v;
@@ -44,21 +49,35 @@ reduce_kernel(const double* __restrict__ x, const double* __restrict__ y, long l
         }
     }
     block_sum<1>(acc, sc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
+}
+
+__global__ void __launch_bounds__(kThreads, 1)
+reduce_final_kernel(const double* __restrict__ partial, int nparts, double* out) {
+    __shared__ BlockScratch sc;
+    double acc[1] = {threadIdx.x < nparts ? partial[threadIdx.x] : 0.0};
+    block_sum<1>(acc, sc);
     if (threadIdx.x == 0) *out = acc[0];
 }
 
-hipError_t sum_reduce(const double* x, long long len, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, x, nullptr, len, 0, out);
+static hipError_t reduce2(const double* x, const double* y, long long len, int mode, double* out,
+                          double* scratch, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partial_kernel, dim3(kReduceBlocks), dim3(kThreads), 0, s, x, y, len,
+                       mode, scratch);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kThreads), 0, s, scratch, kReduceBlocks,
+                       out);
     return hipGetLastError();
 }
-hipError_t sq_norm(const double* x, long long len, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, x, nullptr, len, 1, out);
-    return hipGetLastError();
+
+hipError_t sum_reduce(const double* x, long long len, double* out, double* scratch, hipStream_t s) {
+    return reduce2(x, nullptr, len, 0, out, scratch, s);
+}
+hipError_t sq_norm(const double* x, long long len, double* out, double* scratch, hipStream_t s) {
+    return reduce2(x, nullptr, len, 1, out, scratch, s);
 }
 hipError_t sq_diff_norm(const double* x, const double* y, long long len, double* out,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, x, y, len, 2, out);
-    return hipGetLastError();
+                        double* scratch, hipStream_t s) {
+    return reduce2(x, y, len, 2, out, scratch, s);
 }
 
 __global__ void nonfinite_kernel(const double* __restrict__ x, long long len, int* out) {
@@ -202,9 +221,10 @@ hipError_t lincomb_f64(double a, const double* x, double b, const double* y, lon
 }
 
 // Largest eigenvalue of the symmetric positive semidefinite q x q matrix G by
-// power iteration with the Rayleigh quotient, one work-group. Stops when the
-// quotient changes by less than 1e-15 relative for 8 steps in a row, or after
-// 50000 steps.
+// power iteration with the Rayleigh quotient, one work-group. Thread i forms
+// (G v)_i from column i of G (equal to row i by symmetry), so the loads of a
+// wave are contiguous. Stops when the quotient changes by less than 1e-14
+// relative for 4 steps in a row, or after 20000 steps.
 __global__ void __launch_bounds__(kThreads, 1)
 power_kernel(const double* __restrict__ G, int q, double* out, double* vbuf) {
     __shared__ BlockScratch sc;
@@ -221,19 +241,24 @@ power_kernel(const double* __restrict__ G, int q, double* out, double* vbuf) {
     __syncthreads();
     double lam = 0.0;
     int stable = 0;
-    for (int it = 0; it < 50000 && stable < 8; ++it) {
+    for (int it = 0; it < 20000 && stable < 4; ++it) {
         double acc[2] = {0.0, 0.0};   // v.w and w.w
         for (int i = threadIdx.x; i < q; i += kThreads) {
-            const double* gr = G + (size_t)i * q;
-            double s = 0.0;
-            for (int j = 0; j < q; ++j) s += gr[j] * v[j];
-            w[i] = s;
-            acc[0] += v[i] * s;
-            acc[1] += s * s;
+            double s0 = 0.0, s1 = 0.0;
+            int j = 0;
+            for (; j + 1 < q; j += 2) {
+                s0 += G[(size_t)j * q + i] * v[j];
+                s1 += G[(size_t)(j + 1) * q + i] * v[j + 1];
+            }
+            if (j < q) s0 += G[(size_t)j * q + i] * v[j];
+            const double sum = s0 + s1;
+            w[i] = sum;
+            acc[0] += v[i] * sum;
+            acc[1] += sum * sum;
         }
         block_sum<2>(acc, sc);
         const double nl = acc[0];
-        stable = (fabs(nl - lam) <= 1e-15 * fabs(nl)) ? stable + 1 : 0;
+        stable = (fabs(nl - lam) <= 1e-14 * fabs(nl)) ? stable + 1 : 0;
         lam = nl;
         const double invw = acc[1] > 0.0 ? 1.0 / sqrt(acc[1]) : 0.0;
         for (int i = threadIdx.x; i < q; i += kThreads) v[i] = w[i] * invw;

@@ -92,7 +92,9 @@ def test_index_set_matches_paper_definition(theta, seed):
     a = rng.uniform(0.5, 3.0, m)
     a[rng.integers(0, m, 3)] = 0.0          # void rows: never in the set
     r = rng.exponential(1.0, m) * a
-    r[a == 0] = rng.uniform(0, 0.1, (a == 0).sum())
+    # Void rows of an inconsistent system keep their residual; it still
+    # counts in ||R||_F^2 (the paper's S is over all rows).
+    r[a == 0] = rng.uniform(0, 20.0, (a == 0).sum())
     variant = "grbk" if theta == 0.5 and seed % 2 == 0 else "rgrbk"
     i, in_set, t, T = oracle.select(variant, r, a, theta=theta, seed=seed, k=seed)
     exact, margin = _exact_set_relaxed(r, a, theta)
@@ -138,6 +140,31 @@ def test_remark_4_1_set_nonempty_and_holds_argmax(theta):
         for k in range(3):
             i, in_set, t, T = oracle.select("rgrbk", r, a, theta=theta, seed=1, k=k)
             assert in_set.any() and in_set[amax] and in_set[i]
+
+
+def test_remark_4_1_under_rounding_of_equal_ratios():
+    # Remark 4.1: the set is never empty. With ||R_i||^2 = c ||A_i||^2 every
+    # ratio equals ||R||_F^2/||A||_F^2 in exact arithmetic, but the rounded
+    # sums can put the threshold one ulp above every rounded ratio; the set
+    # must still hold the maximiser.
+    rng = np.random.default_rng(0)
+    hit = 0
+    for trial in range(400):
+        m = int(rng.integers(2, 9))
+        a = rng.uniform(0.1, 3.0, m)
+        r = a * rng.uniform(0.5, 2.0)
+        ratio = r / a
+        S, F = 0.0, 0.0
+        for x in r:
+            S += x
+        for x in a:
+            F += x
+        hit += (S / F) > ratio.max()
+        for theta in (0.0, 0.5):
+            i, in_set, t, T = oracle.select("rgrbk", r, a, theta=theta, seed=3, k=trial)
+            assert in_set.any() and in_set[i] and in_set[int(np.argmax(ratio))]
+            assert t <= ratio.max()
+    assert hit > 20   # the adversarial rounding case does occur in this sample
 
 
 def test_theta_one_is_mwrbk_when_argmax_unique():
