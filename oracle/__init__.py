@@ -23,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mek_oracle.c")
+_SRC_BLOCK = os.path.join(_HERE, "mek_oracle_block.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 BK, RBK, GRBK, RGRBK, MWRBK = 0, 1, 2, 3, 4
@@ -36,7 +37,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-fPIC", "-shared", "-o", tmp, _SRC, _SRC_BLOCK, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -69,6 +70,13 @@ def lib():
                                ctypes.c_int, d, dp, i64, u64, u64, lp, i64, ctypes.c_int, d,
                                dp, lp, P(ctypes.c_int), dp, dp, lp, lp, i64]
         L.mo_solve.restype = ctypes.c_int
+        L.mo_select_2s.argtypes = [i64, i64, dp, dp, dp, d, d, d, i64, i64, dp, dp, d, lp,
+                                   P(i64), lp, P(i64), P(d), P(d)]
+        L.mo_select_2s.restype = ctypes.c_int
+        L.mo_solve_2s.argtypes = [i64, i64, i64, i64, dp, dp, dp, dp, d, i64, i64, d,
+                                  ctypes.c_int, d, dp, i64, d, dp, lp, P(ctypes.c_int), dp, dp,
+                                  lp, lp, lp, lp, i64]
+        L.mo_solve_2s.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -189,6 +197,74 @@ def solve(A, B, C, X0=None, variant="grbk", theta=0.5, alpha=None, stop=STOP_NON
         raise ValueError(f"oracle rejected the arguments (code {rc})")
     k = it.value
     return Result(X, k, st.value, s_hist[:k + 1], e_hist[:k + 1], idx_hist[:k], set_hist[:k])
+
+
+# ----------------------------------------------------------------------------
+# Two-sided block projection (mek_oracle_block.c).
+# ----------------------------------------------------------------------------
+
+TAU_DEFAULT = 1e-10
+
+
+def select_2s(R, a, b, F_A, F_B, GA, GB, theta=0.5, s_max=32, t_max=32, tau=TAU_DEFAULT):
+    """One selection: returns (I, J, eps, Omega), I and J in the order taken."""
+    R, a, b, GA, GB = map(_f64, (R, a, b, GA, GB))
+    m, n = R.shape
+    I = np.full(s_max, -1, dtype=np.int64)
+    J = np.full(t_max, -1, dtype=np.int64)
+    nI, nJ = ctypes.c_int64(0), ctypes.c_int64(0)
+    eps, Om = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    LP = ctypes.POINTER(ctypes.c_int64)
+    rc = lib().mo_select_2s(m, n, _dp(R), _dp(a), _dp(b), float(F_A), float(F_B), float(theta),
+                            int(s_max), int(t_max), _dp(GA), _dp(GB), float(tau),
+                            I.ctypes.data_as(LP), ctypes.byref(nI), J.ctypes.data_as(LP),
+                            ctypes.byref(nJ), ctypes.byref(eps), ctypes.byref(Om))
+    if rc != 0:
+        raise ValueError("no entry with a_i > 0 and b_j > 0")
+    return I[:nI.value], J[:nJ.value], eps.value, Om.value
+
+
+class Result2s:
+    def __init__(self, X, iters, status, s_hist, e_hist, I_hist, J_hist, nI, nJ):
+        self.X = X
+        self.iters = iters
+        self.status = status
+        self.s_hist = s_hist
+        self.e_hist = e_hist
+        self.I = [I_hist[k, :nI[k]] for k in range(iters)]
+        self.J = [J_hist[k, :nJ[k]] for k in range(iters)]
+
+
+def solve_2s(A, B, C, X0=None, theta=0.5, s_max=32, t_max=32, tau=TAU_DEFAULT, stop=STOP_NONE,
+             tol=0.0, Xref=None, max_iters=100, diverge=0.0, hist_cap=None) -> Result2s:
+    """Run the two-sided block iteration. See mo_solve_2s in mek_oracle_block.c."""
+    A, B, C, X0, Xref = map(_f64, (A, B, C, X0, Xref))
+    m, p = A.shape
+    q, n = B.shape
+    assert C.shape == (m, n)
+    X = np.empty((p, q))
+    if hist_cap is None:
+        hist_cap = max_iters + 1
+    s_hist = np.full(hist_cap, np.nan)
+    e_hist = np.full(hist_cap, np.nan)
+    I_hist = np.full((hist_cap, s_max), -1, dtype=np.int64)
+    J_hist = np.full((hist_cap, t_max), -1, dtype=np.int64)
+    nI = np.zeros(hist_cap, dtype=np.int64)
+    nJ = np.zeros(hist_cap, dtype=np.int64)
+    it = ctypes.c_int64(0)
+    st = ctypes.c_int(0)
+    LP = ctypes.POINTER(ctypes.c_int64)
+    rc = lib().mo_solve_2s(m, p, q, n, _dp(A), _dp(B), _dp(C), _dp(X0), float(theta),
+                           int(s_max), int(t_max), float(tau), int(stop), float(tol), _dp(Xref),
+                           int(max_iters), float(diverge), _dp(X), ctypes.byref(it),
+                           ctypes.byref(st), _dp(s_hist), _dp(e_hist), I_hist.ctypes.data_as(LP),
+                           J_hist.ctypes.data_as(LP), nI.ctypes.data_as(LP),
+                           nJ.ctypes.data_as(LP), hist_cap)
+    if rc in (EINVAL, ENOMEM) and it.value == 0:
+        raise ValueError(f"oracle rejected the arguments (code {rc})")
+    k = it.value
+    kk = min(k, hist_cap)
+    return Result2s(X, kk, st.value, s_hist[:k + 1], e_hist[:k + 1], I_hist, J_hist, nI, nJ)
 
 
 # ----------------------------------------------------------------------------
