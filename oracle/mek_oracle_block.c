@@ -19,11 +19,11 @@
  * where S / (F_A F_B) is the mean of omega weighted by a_i b_j, so the
  * largest entry always passes (the argument of Remark 4.1). A row (column)
  * is a candidate when its largest omega passes; rows are ranked by that
- * largest omega (ties: lower index first) and taken greedily, a row being
- * skipped when the part of A_i orthogonal to the rows already taken has
- * squared norm at most tau * a_i (the pivot of a Cholesky factorisation of
- * A_I A_I^T in that order), until s rows are taken; columns likewise with
- * B^T B, up to t columns. The step projects X onto {X : A_I X B_J = C_IJ}:
+ * largest omega (ties: lower index first); of the first s ranked rows, a row
+ * is dropped when the part of A_i orthogonal to the higher-ranked rows kept
+ * has squared norm at most tau * a_i (the pivot of a Cholesky factorisation
+ * of A_I A_I^T in rank order), so at most s rows are kept; columns likewise
+ * with B^T B, of the first t ranked columns. The step projects X onto {X : A_I X B_J = C_IJ}:
  *     W = (A_I A_I^T)^{-1} R_IJ (B_J^T B_J)^{-1},
  *     X += A_I^T W B_J^T,
  *     R -= (A A^T)_{:,I} W (B^T B)_{J,:},
@@ -63,13 +63,13 @@ static int64_t rank_candidates(int64_t len, const double* score, const unsigned 
     return cnt;
 }
 
-/* Greedy pivoted Cholesky over the ranked candidates: take candidate c when
- * G_cc - sum_x L[r][x]^2 > tau * G_cc, with L the factor of G restricted to
- * the taken indices (row-major, ld = cap). G is len x len row-major. */
+/* Pivoted Cholesky over the first cap ranked candidates: keep candidate c
+ * when G_cc - sum_x L[r][x]^2 > tau * G_cc, with L the factor of G restricted
+ * to the kept indices (row-major, ld = cap). G is len x len row-major. */
 static int64_t take_independent(int64_t cnt, const int64_t* order, const double* G, int64_t len,
                                 double tau, int64_t cap, int64_t* taken, double* L) {
     int64_t r = 0;
-    for (int64_t c = 0; c < cnt && r < cap; ++c) {
+    for (int64_t c = 0; c < cnt && c < cap; ++c) {
         const int64_t i = order[c];
         double* Lr = L + r * cap;
         for (int64_t x = 0; x < r; ++x) {

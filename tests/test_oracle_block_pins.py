@@ -125,17 +125,16 @@ def test_dependent_rows_and_columns_are_skipped():
 
 
 def _ranked_independent(score, M, cap, by_rows):
-    """Rank by score (descending, lower index first) and keep an index when it
-    raises the exact rank of the rows (columns) kept so far."""
-    order = sorted(range(len(score)), key=lambda i: (-score[i], i))
+    """Rank by score (descending, lower index first); of the first cap ranked
+    indices keep those that raise the exact rank of the rows (columns) kept
+    before them."""
+    order = sorted(range(len(score)), key=lambda i: (-score[i], i))[:cap]
     kept = []
     for i in order:
         trial = kept + [i]
         sub = M[trial] if by_rows else M[:, trial]
         if np.linalg.matrix_rank(sub) == len(trial):
             kept = trial
-        if len(kept) == cap:
-            break
     return kept
 
 
@@ -157,12 +156,18 @@ def test_selection_with_dependent_rows_matches_rank_definition():
     R = np.sqrt(np.outer(a, b)) * rho
     w = R ** 2 / np.outer(a, b)
     GA, GB = grams(A, B)
-    for cap in (2, 4, 7):
+    for cap in (2, 4, 6, 7):
         I, J, _, _ = oracle.select_2s(R, a, b, a.sum(), b.sum(), GA, GB, theta=0.0,
                                       s_max=cap, t_max=cap)
         assert I.tolist() == _ranked_independent(w.max(1), A, cap, True)
         assert J.tolist() == _ranked_independent(w.max(0), B, cap, False)
     assert len(I) == 5 and len(J) == 4           # rank(A) = 5, rank(B) = 4
+    # Dropped rows are not replaced by lower-ranked ones.
+    hr = sorted(range(m), key=lambda i: (-w.max(1)[i], i))
+    first6 = hr[:6]
+    I6, _, _, _ = oracle.select_2s(R, a, b, a.sum(), b.sum(), GA, GB, theta=0.0, s_max=6,
+                                   t_max=6)
+    assert set(I6.tolist()) <= set(first6)
 
 
 def test_ties_take_the_lower_index():
