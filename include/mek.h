@@ -102,7 +102,8 @@ typedef struct {
     uint64_t seed;        /* Philox4x64-10 key word 0 */
     uint64_t instance;    /* Philox4x64-10 key word 1 */
     const int32_t* replay_idx; /* device, optional: forced row indices for
-                             updates k < replay_len (test hook) */
+                             updates k < replay_len (test hook; in MEK_MIXED
+                             k counts updates over all refinement passes) */
     int64_t replay_len;
     double diverge;       /* > 0: stop with MEK_EDIVERGED once ||R^k||^2 >
                              diverge * ||R^0||^2; <= 0: off */
@@ -166,6 +167,23 @@ int mek_plan_query(mek_plan plan, double* row_norms, double* gram_a, double* gra
  * (host struct) may be NULL. Returns the final status (>= 0: X written). */
 int mek_solve(mek_plan plan, const double* C, const double* X0, const mek_solve_opts* opts,
               double* X, mek_report* report, void* stream);
+
+/* Uniform batch: solve A X_b B = C_b for b < batch with the plan's A and B
+ * (for instance the channels of an image) in one persistent launch whose
+ * work-groups are split evenly between the instances. All per-instance
+ * arrays are stacked, instance b at b times the size of one: C (batch x m x
+ * n), X0 (batch x p x q, NULL means zero), X (batch x p x q, may alias X0),
+ * opts->X_ref (batch x p x q) and each history (batch x hist_cap entries).
+ * Instance b draws its random numbers under Philox key (seed, instance + b),
+ * so it follows the same trajectory as a mek_solve call with that key.
+ * replay_idx, when given, forces the same rows in every instance. reports
+ * (host, batch entries) may be NULL; kernel_ms is the time of the shared
+ * launch(es). Returns a negative code if the call failed (nothing written)
+ * or an instance failed; otherwise MEK_OK when every instance met the stop
+ * rule, else the status of the first one that did not. Errors as mek_solve,
+ * and MEK_EUNSUPPORTED when batch exceeds the device's compute units. */
+int mek_solve_batched(mek_plan plan, int64_t batch, const double* C, const double* X0,
+                      const mek_solve_opts* opts, double* X, mek_report* reports, void* stream);
 
 /* ---- Unit entry points: the hot path's stages run on their own. ---- */
 

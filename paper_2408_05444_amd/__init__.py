@@ -87,6 +87,9 @@ def lib() -> ctypes.CDLL:
         L.mek_solve.argtypes = [vp, vp, vp, ctypes.POINTER(mek_solve_opts), vp,
                                 ctypes.POINTER(mek_report), vp]
         L.mek_solve.restype = ci
+        L.mek_solve_batched.argtypes = [vp, i64, vp, vp, ctypes.POINTER(mek_solve_opts), vp,
+                                        ctypes.POINTER(mek_report), vp]
+        L.mek_solve_batched.restype = ci
         L.mek_philox_uniform.argtypes = [u64, u64, i64, i64, vp, vp]
         L.mek_philox_uniform.restype = ci
         L.mek_select.argtypes = [ci, i64, vp, vp, d, d, u64, u64, i64, i64, vp, vp, vp, vp, vp]
@@ -198,28 +201,21 @@ class SolveResult:
     set_hist: Optional[torch.Tensor] = None
 
 
-def mek_solve(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = None, variant="grbk",
-              theta: float = 0.5, alpha: float = 0.0, stop="none", tol: float = 0.0,
-              X_ref: Optional[torch.Tensor] = None, max_iters: int = 100000, seed: int = 0,
-              instance: int = 0, replay_idx: Optional[torch.Tensor] = None, diverge: float = 0.0,
-              hist_cap: int = 0, inner_iters: int = 0, X_out: Optional[torch.Tensor] = None,
-              raise_on_error: bool = True) -> SolveResult:
-    m, p, q, n = plan.m, plan.p, plan.q, plan.n
-    dev = C.device
-    X = X_out if X_out is not None else torch.empty(p, q, dtype=torch.float64, device=dev)
+def _solve_opts(nb, dev, variant, theta, alpha, stop, tol, X_ref_ptr, max_iters, seed, instance,
+                replay_idx, diverge, hist_cap, inner_iters):
     hists = {}
     if hist_cap > 0:
-        hists["resid_hist"] = torch.full((hist_cap,), float("nan"), dtype=torch.float64, device=dev)
-        hists["err_hist"] = torch.full((hist_cap,), float("nan"), dtype=torch.float64, device=dev)
-        hists["idx_hist"] = torch.full((hist_cap,), -1, dtype=torch.int32, device=dev)
-        hists["set_hist"] = torch.zeros((hist_cap,), dtype=torch.int32, device=dev)
+        hists["resid_hist"] = torch.full((nb, hist_cap), float("nan"), dtype=torch.float64, device=dev)
+        hists["err_hist"] = torch.full((nb, hist_cap), float("nan"), dtype=torch.float64, device=dev)
+        hists["idx_hist"] = torch.full((nb, hist_cap), -1, dtype=torch.int32, device=dev)
+        hists["set_hist"] = torch.zeros((nb, hist_cap), dtype=torch.int32, device=dev)
     o = mek_solve_opts()
     o.variant = VARIANTS.get(variant, variant)
     o.theta = float(theta)
     o.alpha = float(alpha)
     o.stop = STOPS.get(stop, stop)
     o.tol = float(tol)
-    o.X_ref = _dev(X_ref, shape=(p, q), name="X_ref")
+    o.X_ref = X_ref_ptr
     o.max_iters = int(max_iters)
     o.seed = int(seed) & (2 ** 64 - 1)
     o.instance = int(instance) & (2 ** 64 - 1)
@@ -231,21 +227,67 @@ def mek_solve(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = None, va
         setattr(o, k, _dev(t, dtype=t.dtype, name=k))
     o.hist_cap = int(hist_cap)
     o.inner_iters = int(inner_iters)
+    return o, hists
+
+
+def _result(X, code, rep, hists, b, hist_cap):
+    res = SolveResult(X, int(code), int(rep.iters), rep.resid2, rep.rel_err, rep.alpha,
+                      int(rep.team_wgs), bool(rep.r_in_lds), int(rep.passes), rep.kernel_ms)
+    if hist_cap > 0:
+        k = min(int(rep.iters), hist_cap - 1)
+        res.resid_hist = hists["resid_hist"][b, :k + 1]
+        res.err_hist = hists["err_hist"][b, :k + 1]
+        res.idx_hist = hists["idx_hist"][b, :min(int(rep.iters), hist_cap)]
+        res.set_hist = hists["set_hist"][b, :min(int(rep.iters), hist_cap)]
+    return res
+
+
+def mek_solve(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = None, variant="grbk",
+              theta: float = 0.5, alpha: float = 0.0, stop="none", tol: float = 0.0,
+              X_ref: Optional[torch.Tensor] = None, max_iters: int = 100000, seed: int = 0,
+              instance: int = 0, replay_idx: Optional[torch.Tensor] = None, diverge: float = 0.0,
+              hist_cap: int = 0, inner_iters: int = 0, X_out: Optional[torch.Tensor] = None,
+              raise_on_error: bool = True) -> SolveResult:
+    m, p, q, n = plan.m, plan.p, plan.q, plan.n
+    dev = C.device
+    X = X_out if X_out is not None else torch.empty(p, q, dtype=torch.float64, device=dev)
+    o, hists = _solve_opts(1, dev, variant, theta, alpha, stop, tol,
+                           _dev(X_ref, shape=(p, q), name="X_ref"), max_iters, seed, instance,
+                           replay_idx, diverge, hist_cap, inner_iters)
     rep = mek_report()
     code = lib().mek_solve(plan.handle, _dev(C, shape=(m, n), name="C"),
                            _dev(X0, shape=(p, q), name="X0"), ctypes.byref(o),
                            _dev(X, shape=(p, q), name="X"), ctypes.byref(rep), _stream())
     if raise_on_error and code < 0:
         raise MekError(code, "mek_solve")
-    res = SolveResult(X, int(code), int(rep.iters), rep.resid2, rep.rel_err, rep.alpha,
-                      int(rep.team_wgs), bool(rep.r_in_lds), int(rep.passes), rep.kernel_ms)
-    if hist_cap > 0:
-        k = min(int(rep.iters), hist_cap - 1)
-        res.resid_hist = hists["resid_hist"][:k + 1]
-        res.err_hist = hists["err_hist"][:k + 1]
-        res.idx_hist = hists["idx_hist"][:min(int(rep.iters), hist_cap)]
-        res.set_hist = hists["set_hist"][:min(int(rep.iters), hist_cap)]
-    return res
+    return _result(X, code, rep, hists, 0, hist_cap)
+
+
+def mek_solve_batched(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = None,
+                      variant="grbk", theta: float = 0.5, alpha: float = 0.0, stop="none",
+                      tol: float = 0.0, X_ref: Optional[torch.Tensor] = None,
+                      max_iters: int = 100000, seed: int = 0, instance: int = 0,
+                      replay_idx: Optional[torch.Tensor] = None, diverge: float = 0.0,
+                      hist_cap: int = 0, inner_iters: int = 0,
+                      raise_on_error: bool = True):
+    """Uniform batch: C (nb, m, n) [, X0, X_ref (nb, p, q)] sharing the plan's A
+    and B. Returns (status, [SolveResult per instance]); instance b draws
+    under Philox key (seed, instance + b)."""
+    m, p, q, n = plan.m, plan.p, plan.q, plan.n
+    nb = C.shape[0]
+    dev = C.device
+    X = torch.empty(nb, p, q, dtype=torch.float64, device=dev)
+    o, hists = _solve_opts(nb, dev, variant, theta, alpha, stop, tol,
+                           _dev(X_ref, shape=(nb, p, q), name="X_ref"), max_iters, seed,
+                           instance, replay_idx, diverge, hist_cap, inner_iters)
+    reps = (mek_report * nb)()
+    code = lib().mek_solve_batched(plan.handle, nb, _dev(C, shape=(nb, m, n), name="C"),
+                                   _dev(X0, shape=(nb, p, q), name="X0"), ctypes.byref(o),
+                                   _dev(X, shape=(nb, p, q), name="X"), reps, _stream())
+    if raise_on_error and code < 0:
+        raise MekError(code, "mek_solve_batched")
+    return int(code), [_result(X[b], reps[b].status, reps[b], hists, b, hist_cap)
+                       for b in range(nb)]
 
 
 def mek_philox_uniform(seed: int, instance: int, k0: int, count: int) -> torch.Tensor:

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "../../include/mek.h"
 #include "internal.h"
@@ -21,9 +22,10 @@ namespace {
 struct Workspace {
     void* base = nullptr;
     size_t bytes = 0;
+    int64_t cap = 0;           // instances the per-instance buffers hold
+    // Per-instance buffers: instance b at b times the size given.
     double* R64 = nullptr;     // m x n
     float* R32 = nullptr;      // m x n (FP32 / MIXED)
-    double* T64 = nullptr;     // m x q, GEMM temporary A X
     double* Xt64 = nullptr;    // q x p
     float* Xt32 = nullptr;     // q x p
     double* Xacc = nullptr;    // p x q, MIXED accumulated iterate
@@ -33,13 +35,16 @@ struct Workspace {
     void* rowbuf = nullptr;    // n * 8 bytes
     void* wbuf = nullptr;      // n * 8 bytes
     void* vbuf = nullptr;      // q * 8 bytes
-    double* errpart = nullptr; // 2 * 256
+    double* errpart = nullptr; // kErrStride
     TeamSync* sync = nullptr;
     DevReport* report = nullptr;
+    InstSlot* slots = nullptr;
+    // Shared scratch.
+    double* T64 = nullptr;     // m x q, GEMM temporary A X
     double* scal = nullptr;    // 8 scalars
     double* red = nullptr;     // 256 partial sums of the reductions
     int* iscal = nullptr;      // 8 ints
-    unsigned long long* phase = nullptr;   // 16 phase-timing counters
+    unsigned long long* phase = nullptr;   // 32 phase-timing counters
 };
 
 }  // namespace
@@ -113,56 +118,65 @@ T* carve(char*& cur, size_t count) {
     return p;
 }
 
-int ensure_workspace(mek_plan_s* P) {
-    if (P->ws.base) return MEK_OK;
-    const size_t m = P->m, p = P->p, q = P->q, n = P->n;
+// Workspace for nb instances; grows (and never shrinks) with the batch size.
+int ensure_workspace(mek_plan_s* P, int64_t nb) {
+    if (P->ws.base && P->ws.cap >= nb) return MEK_OK;
+    if (P->ws.base) {
+        MEK_TRY(hipDeviceSynchronize());
+        (void)hipFree(P->ws.base);
+        P->ws = Workspace();
+    }
+    const size_t m = P->m, p = P->p, q = P->q, n = P->n, B = (size_t)nb;
     const bool f32 = P->precision != MEK_FP64;
     size_t need = 0;
     auto add = [&](size_t bytes) { need += (bytes + 255) & ~(size_t)255; };
-    add(m * n * 8);
-    add(f32 ? m * n * 4 : 0);
+    add(B * m * n * 8);
+    add(f32 ? B * m * n * 4 : 0);
+    add(B * q * p * 8);
+    add(f32 ? B * q * p * 4 : 0);
+    add(B * p * q * 8);
+    add(B * p * q * 8);
+    add(B * q * p * 8);
+    add(B * m * 8);
+    add(B * n * 8);
+    add(B * n * 8);
+    add(B * q * 8);
+    add(B * kErrStride * 8);
+    add(B * sizeof(TeamSync));
+    add(B * sizeof(DevReport));
+    add(B * sizeof(InstSlot));
     add(m * q * 8);
-    add(q * p * 8);
-    add(f32 ? q * p * 4 : 0);
-    add(p * q * 8);
-    add(p * q * 8);
-    add(q * p * 8);
-    add(m * 8);
-    add(n * 8);
-    add(n * 8);
-    add(q * 8);
-    add(2 * 256 * 8);
-    add(sizeof(TeamSync));
-    add(sizeof(DevReport));
     add(8 * 8);
+    add(256 * 8);
     add(8 * 4);
     add(32 * 8);
-    add(256 * 8);
     void* base = nullptr;
     MEK_TRY(hipMalloc(&base, need));
     char* cur = (char*)base;
     Workspace& w = P->ws;
     w.base = base;
     w.bytes = need;
-    w.R64 = carve<double>(cur, m * n);
-    w.R32 = f32 ? carve<float>(cur, m * n) : nullptr;
+    w.cap = nb;
+    w.R64 = carve<double>(cur, B * m * n);
+    w.R32 = f32 ? carve<float>(cur, B * m * n) : nullptr;
+    w.Xt64 = carve<double>(cur, B * q * p);
+    w.Xt32 = f32 ? carve<float>(cur, B * q * p) : nullptr;
+    w.Xacc = carve<double>(cur, B * p * q);
+    w.Xtmp = carve<double>(cur, B * p * q);
+    w.Xref_t = carve<double>(cur, B * q * p);
+    w.r = carve<double>(cur, B * m);
+    w.rowbuf = carve<double>(cur, B * n);
+    w.wbuf = carve<double>(cur, B * n);
+    w.vbuf = carve<double>(cur, B * q);
+    w.errpart = carve<double>(cur, B * kErrStride);
+    w.sync = carve<TeamSync>(cur, B);
+    w.report = carve<DevReport>(cur, B);
+    w.slots = carve<InstSlot>(cur, B);
     w.T64 = carve<double>(cur, m * q);
-    w.Xt64 = carve<double>(cur, q * p);
-    w.Xt32 = f32 ? carve<float>(cur, q * p) : nullptr;
-    w.Xacc = carve<double>(cur, p * q);
-    w.Xtmp = carve<double>(cur, p * q);
-    w.Xref_t = carve<double>(cur, q * p);
-    w.r = carve<double>(cur, m);
-    w.rowbuf = carve<double>(cur, n);
-    w.wbuf = carve<double>(cur, n);
-    w.vbuf = carve<double>(cur, q);
-    w.errpart = carve<double>(cur, 2 * 256);
-    w.sync = carve<TeamSync>(cur, 1);
-    w.report = carve<DevReport>(cur, 1);
     w.scal = carve<double>(cur, 8);
+    w.red = carve<double>(cur, 256);
     w.iscal = carve<int>(cur, 8);
     w.phase = carve<unsigned long long>(cur, 32);
-    w.red = carve<double>(cur, 256);
     return MEK_OK;
 }
 
@@ -188,13 +202,15 @@ int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // of R stay in LDS. Automatic choice: the fewest work-groups whose LDS can
 // hold all of R, but at least one per 32K residual entries (so each
 // work-group's pass stays short), capped by the number of CUs.
-int choose_layout(const mek_plan_s* P, size_t elem, Layout* L) {
+int choose_layout(const mek_plan_s* P, size_t elem, int64_t nb, Layout* L) {
     const int64_t m = P->m, n = P->n, q = P->q;
     // The selection keeps at most kSelRows row norms per thread in registers,
     // and the n-vector staging buffer must fit in LDS.
     if (m > (int64_t)kSelRows * kThreads) return MEK_EUNSUPPORTED;
     if ((size_t)std::max(n, q) * elem + 4096 > solve_lds_budget()) return MEK_EUNSUPPORTED;
-    const int cus = std::max(1, P->cus);
+    // A batch splits the CUs evenly between its instances' teams.
+    if (nb > std::max(1, P->cus)) return MEK_EUNSUPPORTED;
+    const int cus = std::max(1, P->cus / (int)nb);
     const size_t budget = solve_lds_budget();
     int W;
     bool lds;
@@ -295,24 +311,22 @@ void fill_common(SolveParams<T>& K, const mek_plan_s* P, const mek_solve_opts* o
     K.set_hist = o->set_hist;
     K.hist_cap = o->hist_cap;
     K.hist_offset = 0;
+    K.nb = 1;
+    K.slots = nullptr;
     K.W = L.W;
     K.rpw = L.rpw;
     K.xpw = L.xpw;
     K.wpw = L.wpw;
 }
 
-int read_report(mek_plan_s* P, DevReport* h, hipStream_t s) {
-    MEK_TRY(hipMemcpyAsync(h, P->ws.report, sizeof(DevReport), hipMemcpyDeviceToHost, s));
-    MEK_TRY(hipStreamSynchronize(s));
-    return MEK_OK;
-}
-
-// One persistent launch on the residual already stored in ws.R64 / ws.R32.
+// One persistent launch on the residuals already stored in ws.R64 / ws.R32.
+// nb = 1 without slots: one instance, its scalars in `one`. With slots (host
+// array of nb entries): a team per slot, instance slots[j].id's buffers.
+// Each launched instance's report goes to out[id].
 template <typename T>
 int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double alpha,
-               double C2, double ref2, const double* Xref_t, long long max_iters,
-               long long k_offset, long long hist_offset, double S_target, T* R, T* Xt,
-               hipStream_t s, DevReport* out, double* kernel_ms) {
+               const InstSlot& one, const InstSlot* slots, int nb, const double* Xref_t, T* R,
+               T* Xt, hipStream_t s, DevReport* out, double* kernel_ms) {
     SolveParams<T> K;
     fill_common(K, P, o, L, alpha);
     if (sizeof(T) == 8) {
@@ -331,28 +345,45 @@ int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double a
     K.R = R;
     K.Xt = Xt;
     K.Xref_t = Xref_t;
-    K.ref2 = ref2;
-    K.C2 = C2;
-    K.max_iters = max_iters;
-    K.k_offset = k_offset;
-    K.hist_offset = hist_offset;
-    K.S_target = S_target;
+    K.ref2 = one.ref2;
+    K.C2 = one.C2;
+    K.max_iters = one.max_iters;
+    K.k_offset = one.k_offset;
+    K.hist_offset = one.hist_offset;
+    K.S_target = one.S_target;
+    K.inst = one.inst;
+    Workspace& w = P->ws;
+    // Instances touched by this launch: their exchange words start at tag 0,
+    // which no update waits for.
+    int lo = 0, hi = 1;
+    if (slots) {
+        MEK_TRY(hipMemcpyAsync(w.slots, slots, sizeof(InstSlot) * nb, hipMemcpyHostToDevice, s));
+        MEK_TRY(hipStreamSynchronize(s));
+        K.nb = nb;
+        K.slots = w.slots;
+        lo = slots[0].id;
+        hi = slots[0].id + 1;
+        for (int j = 0; j < nb; ++j) {
+            lo = std::min(lo, slots[j].id);
+            hi = std::max(hi, slots[j].id + 1);
+        }
+    }
+    const long long span = hi - lo;
     // MEK_PHASES=1 in the environment: time the phases of each update on
-    // work-group 0 and print the averages to stderr (profiling aid).
+    // three work-groups and print the averages to stderr (profiling aid).
     static const bool phases = getenv("MEK_PHASES") && getenv("MEK_PHASES")[0] == '1';
-    K.phase = phases ? P->ws.phase : nullptr;
+    K.phase = phases ? w.phase : nullptr;
     K.a_in_lds = L.a_lds ? 1 : 0;
     // Pause between polls of exchange words (tuning knob MEK_POLL_SLEEP).
     static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
     K.poll_sleep = poll_sleep;
-    if (phases) MEK_TRY(fill_zero_bytes(P->ws.phase, 32 * 8, s));
-    // Exchange words start with tag 0, which no update waits for.
-    MEK_TRY(fill_zero_bytes(P->ws.sync, sizeof(TeamSync), s));
-    MEK_TRY(fill_zero_bytes(P->ws.errpart, 2 * 256 * 8, s));
-    MEK_TRY(fill_zero_bytes(P->ws.r, (long long)P->m * 8, s));
-    MEK_TRY(fill_zero_bytes(P->ws.rowbuf, (long long)P->n * 8, s));
-    MEK_TRY(fill_zero_bytes(P->ws.wbuf, (long long)P->n * 8, s));
-    MEK_TRY(fill_zero_bytes(P->ws.vbuf, (long long)P->q * 8, s));
+    if (phases) MEK_TRY(fill_zero_bytes(w.phase, 32 * 8, s));
+    MEK_TRY(fill_zero_bytes(w.sync + lo, span * (long long)sizeof(TeamSync), s));
+    MEK_TRY(fill_zero_bytes(w.errpart + lo * kErrStride, span * kErrStride * 8, s));
+    MEK_TRY(fill_zero_bytes(w.r + lo * P->m, span * P->m * 8, s));
+    MEK_TRY(fill_zero_bytes((char*)w.rowbuf + lo * P->n * 8, span * P->n * 8, s));
+    MEK_TRY(fill_zero_bytes((char*)w.wbuf + lo * P->n * 8, span * P->n * 8, s));
+    MEK_TRY(fill_zero_bytes((char*)w.vbuf + lo * P->q * 8, span * P->q * 8, s));
     hipEvent_t ev[2];
     MEK_TRY(hipEventCreate(&ev[0]));
     if (hipEventCreate(&ev[1]) != hipSuccess) {
@@ -362,24 +393,29 @@ int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double a
     hipError_t e = hipEventRecord(ev[0], s);
     if (e == hipSuccess) e = launch_solve(K, L.lds, L.lds_bytes, s);
     if (e == hipSuccess) e = hipEventRecord(ev[1], s);
-    int st = (e == hipSuccess) ? read_report(P, out, s) : hip_status(e);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out + lo, w.report + lo, sizeof(DevReport) * span,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int st = hip_status(e);
     float ms = 0.0f;
     if (st == MEK_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess && kernel_ms)
         *kernel_ms += (double)ms;
-    if (st == MEK_OK && phases && out->iters > 0) {
+    const long long iters0 = out[lo].iters;
+    if (st == MEK_OK && phases && iters0 > 0) {
         unsigned long long h[24];
         int rate_khz = 100000;
         (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, P->device);
-        if (hipMemcpy(h, P->ws.phase, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess) {
+        if (hipMemcpy(h, w.phase, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess) {
             const char* names[8] = {"reduce", "select", "row", "dots", "waitw", "xupd", "update", "end"};
             const int wg[3] = {0, L.W / 2, L.W - 1};
             for (int t = 0; t < (L.W > 1 ? 3 : 1); ++t) {
                 fprintf(stderr, "[mek phases] W=%d lds=%d a_lds=%d wg=%d iters=%lld us/update:", L.W,
-                        (int)L.lds, (int)L.a_lds, wg[t], (long long)out->iters);
+                        (int)L.lds, (int)L.a_lds, wg[t], iters0);
                 for (int i = 0; i < 8; ++i)
                     fprintf(stderr, " %s=%.2f", names[i],
-                            (double)h[t * 8 + i] / (rate_khz * 1e-3) / out->iters);
-                fprintf(stderr, " total_kernel=%.2f\n", ms * 1e3 / out->iters);
+                            (double)h[t * 8 + i] / (rate_khz * 1e-3) / iters0);
+                fprintf(stderr, " total_kernel=%.2f\n", ms * 1e3 / iters0);
             }
         }
     }
@@ -451,7 +487,7 @@ int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n, c
         alloc((void**)&P->BT, (size_t)(q * n) * 8) ||
         alloc((void**)&P->GA, (size_t)(m * m) * 8) || alloc((void**)&P->GB, (size_t)(n * n) * 8) ||
         alloc((void**)&P->a, (size_t)m * 8) || alloc((void**)&P->active, (size_t)m * 4) ||
-        ensure_workspace(P))
+        ensure_workspace(P, 1))
         return fail(MEK_ENOMEM);
     Workspace& w = P->ws;
     if (copy_f64(A, m * p, P->A, s) || copy_f64(B, q * n, P->B, s) ||
@@ -533,28 +569,39 @@ int mek_plan_query(mek_plan P, double* row_norms, double* gram_a, double* gram_b
     return MEK_OK;
 }
 
-int mek_solve(mek_plan P, const double* C, const double* X0, const mek_solve_opts* o, double* X,
-              mek_report* report, void* stream) {
-    if (!P || !C || !X) return MEK_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// The solve of nb instances that share the plan's A and B (nb = 1: mek_solve).
+// C, X0, X, X_ref and the histories are stacked per instance.
+int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
+               const mek_solve_opts* o, double* X, mek_report* reports, hipStream_t s) {
+    if (!P || !C || !X || nb < 1) return MEK_EINVAL;
     int st = validate_opts(P, o);
     if (st) return st;
     const int64_t m = P->m, p = P->p, q = P->q, n = P->n;
-    hipStream_t s = (hipStream_t)stream;
-    if ((st = check_dev(C, (size_t)(m * n) * 8))) return st;
-    if (X0 && (st = check_dev(X0, (size_t)(p * q) * 8))) return st;
-    if ((st = check_dev(X, (size_t)(p * q) * 8))) return st;
-    if (o->X_ref && (st = check_dev(o->X_ref, (size_t)(p * q) * 8))) return st;
+    const size_t mn = (size_t)(m * n), pq = (size_t)(p * q);
+    if ((st = check_dev(C, nb * mn * 8))) return st;
+    if (X0 && (st = check_dev(X0, nb * pq * 8))) return st;
+    if ((st = check_dev(X, nb * pq * 8))) return st;
+    if (o->X_ref && (st = check_dev(o->X_ref, nb * pq * 8))) return st;
     if (o->replay_len > 0 && (st = check_dev(o->replay_idx, (size_t)o->replay_len * 4))) return st;
     if (o->hist_cap > 0) {
-        if (o->resid_hist && (st = check_dev(o->resid_hist, (size_t)o->hist_cap * 8))) return st;
-        if (o->err_hist && (st = check_dev(o->err_hist, (size_t)o->hist_cap * 8))) return st;
-        if (o->idx_hist && (st = check_dev(o->idx_hist, (size_t)o->hist_cap * 4))) return st;
-        if (o->set_hist && (st = check_dev(o->set_hist, (size_t)o->hist_cap * 4))) return st;
+        const size_t hc = (size_t)(nb * o->hist_cap);
+        if (o->resid_hist && (st = check_dev(o->resid_hist, hc * 8))) return st;
+        if (o->err_hist && (st = check_dev(o->err_hist, hc * 8))) return st;
+        if (o->idx_hist && (st = check_dev(o->idx_hist, hc * 4))) return st;
+        if (o->set_hist && (st = check_dev(o->set_hist, hc * 4))) return st;
     }
+    const int prec = P->precision;
+    Layout L;
+    if ((st = choose_layout(P, prec == MEK_FP64 ? 8 : 4, nb, &L))) return st;
+    if ((st = ensure_workspace(P, nb))) return st;
     Workspace& w = P->ws;
-    if ((st = finite_check(C, m * n, w.iscal, s))) return st;
-    if (X0 && (st = finite_check(X0, p * q, w.iscal, s))) return st;
-    if (o->X_ref && (st = finite_check(o->X_ref, p * q, w.iscal, s))) return st;
+    if ((st = finite_check(C, nb * m * n, w.iscal, s))) return st;
+    if (X0 && (st = finite_check(X0, nb * p * q, w.iscal, s))) return st;
+    if (o->X_ref && (st = finite_check(o->X_ref, nb * p * q, w.iscal, s))) return st;
     if (o->replay_len > 0) {
         // Forced indices must name rows that can be projected on.
         int32_t* hidx = (int32_t*)malloc((size_t)o->replay_len * 4);
@@ -571,143 +618,217 @@ int mek_solve(mek_plan P, const double* C, const double* X0, const mek_solve_opt
     }
     const double alpha = (o->alpha > 0.0) ? o->alpha : P->alpha;
 
-    // ||C||_F^2 and ||X_ref||_F^2.
-    double C2 = 0.0, ref2 = 0.0;
-    MEK_TRY(sq_norm(C, m * n, w.scal + 2, w.red, s));
-    if ((st = read_scalar(w.scal + 2, &C2, s))) return st;
-    if (o->X_ref) {
-        MEK_TRY(sq_norm(o->X_ref, p * q, w.scal + 3, w.red, s));
-        if ((st = read_scalar(w.scal + 3, &ref2, s))) return st;
-        if (!(ref2 > 0.0)) ref2 = 1.0;
+    // Per instance: ||C_b||_F^2 and ||X_ref,b||_F^2.
+    std::vector<double> C2(nb, 0.0), ref2(nb, 1.0);
+    for (int64_t b = 0; b < nb; ++b) {
+        MEK_TRY(sq_norm(C + b * mn, m * n, w.scal + 2, w.red, s));
+        if ((st = read_scalar(w.scal + 2, &C2[b], s))) return st;
+        if (o->X_ref) {
+            MEK_TRY(sq_norm(o->X_ref + b * pq, p * q, w.scal + 3, w.red, s));
+            if ((st = read_scalar(w.scal + 3, &ref2[b], s))) return st;
+            if (!(ref2[b] > 0.0)) ref2[b] = 1.0;
+        }
     }
 
-    const int prec = P->precision;
-    Layout L;
-    if ((st = choose_layout(P, prec == MEK_FP64 ? 8 : 4, &L))) return st;
-
-    // R^0 = C - A X^0 B (residual engine), or C when X^0 = 0.
-    auto residual_into_R64 = [&](const double* Xcur) -> int {
+    // R^0_b = C_b - A X^0_b B (residual engine), or C_b when X^0 = 0.
+    auto residual_into_R64 = [&](int64_t b, const double* Xcur) -> int {
+        double* Rb = w.R64 + b * mn;
         if (Xcur) {
             MEK_TRY(gemm_f64((int)m, (int)q, (int)p, 1.0, P->A, p, 1, Xcur, q, 1, 0.0, nullptr, 0,
                              w.T64, q, s));
-            MEK_TRY(gemm_f64((int)m, (int)n, (int)q, -1.0, w.T64, q, 1, P->B, n, 1, 1.0, C, n,
-                             w.R64, n, s));
+            MEK_TRY(gemm_f64((int)m, (int)n, (int)q, -1.0, w.T64, q, 1, P->B, n, 1, 1.0,
+                             C + b * mn, n, Rb, n, s));
         } else {
-            MEK_TRY(copy_f64(C, m * n, w.R64, s));
+            MEK_TRY(copy_f64(C + b * mn, m * n, Rb, s));
         }
         return MEK_OK;
     };
+    auto slot_for = [&](int64_t b) {
+        InstSlot sl;
+        memset(&sl, 0, sizeof(sl));
+        sl.id = (int)b;
+        sl.C2 = C2[b];
+        sl.ref2 = ref2[b];
+        sl.max_iters = o->max_iters;
+        sl.inst = o->instance + (uint64_t)b;
+        return sl;
+    };
 
-    DevReport rep;
-    memset(&rep, 0, sizeof(rep));
-    int passes = 1;
+    std::vector<DevReport> rep(nb);
+    std::vector<int> passes(nb, 1);
+    memset(rep.data(), 0, sizeof(DevReport) * nb);
     double kms = 0.0;
     if (prec == MEK_FP64 || prec == MEK_FP32) {
-        if ((st = residual_into_R64(X0))) return st;
-        if (o->X_ref) MEK_TRY(transpose_to<double>(o->X_ref, (int)p, (int)q, w.Xref_t, s));
+        std::vector<InstSlot> slots(nb);
+        for (int64_t b = 0; b < nb; ++b) {
+            if ((st = residual_into_R64(b, X0 ? X0 + b * pq : nullptr))) return st;
+            if (o->X_ref)
+                MEK_TRY(transpose_to<double>(o->X_ref + b * pq, (int)p, (int)q, w.Xref_t + b * pq, s));
+            slots[b] = slot_for(b);
+        }
+        const double* xr = o->X_ref ? w.Xref_t : nullptr;
+        const InstSlot* sp = nb > 1 ? slots.data() : nullptr;
         if (prec == MEK_FP64) {
-            if (X0) MEK_TRY(transpose_to<double>(X0, (int)p, (int)q, w.Xt64, s));
-            else MEK_TRY(fill_zero_bytes(w.Xt64, (long long)(p * q) * 8, s));
-            st = run_kernel<double>(P, o, L, alpha, C2, ref2, o->X_ref ? w.Xref_t : nullptr,
-                                    o->max_iters, 0, 0, 0.0, w.R64, w.Xt64, s, &rep, &kms);
+            for (int64_t b = 0; b < nb; ++b) {
+                if (X0) MEK_TRY(transpose_to<double>(X0 + b * pq, (int)p, (int)q, w.Xt64 + b * pq, s));
+                else MEK_TRY(fill_zero_bytes(w.Xt64 + b * pq, (long long)pq * 8, s));
+            }
+            st = run_kernel<double>(P, o, L, alpha, slots[0], sp, (int)nb, xr, w.R64, w.Xt64, s,
+                                    rep.data(), &kms);
             if (st) return st;
-            MEK_TRY(transpose_from<double>(w.Xt64, (int)p, (int)q, X, s));
+            for (int64_t b = 0; b < nb; ++b)
+                MEK_TRY(transpose_from<double>(w.Xt64 + b * pq, (int)p, (int)q, X + b * pq, s));
         } else {
-            MEK_TRY(convert_f64_f32(w.R64, m * n, w.R32, s));
-            if (X0) MEK_TRY(transpose_to<float>(X0, (int)p, (int)q, w.Xt32, s));
-            else MEK_TRY(fill_zero_bytes(w.Xt32, (long long)(p * q) * 4, s));
-            st = run_kernel<float>(P, o, L, alpha, C2, ref2, o->X_ref ? w.Xref_t : nullptr,
-                                   o->max_iters, 0, 0, 0.0, w.R32, w.Xt32, s, &rep, &kms);
+            MEK_TRY(convert_f64_f32(w.R64, nb * m * n, w.R32, s));
+            for (int64_t b = 0; b < nb; ++b) {
+                if (X0) MEK_TRY(transpose_to<float>(X0 + b * pq, (int)p, (int)q, w.Xt32 + b * pq, s));
+                else MEK_TRY(fill_zero_bytes(w.Xt32 + b * pq, (long long)pq * 4, s));
+            }
+            st = run_kernel<float>(P, o, L, alpha, slots[0], sp, (int)nb, xr, w.R32, w.Xt32, s,
+                                   rep.data(), &kms);
             if (st) return st;
-            MEK_TRY(transpose_from<float>(w.Xt32, (int)p, (int)q, X, s));
+            for (int64_t b = 0; b < nb; ++b)
+                MEK_TRY(transpose_from<float>(w.Xt32 + b * pq, (int)p, (int)q, X + b * pq, s));
         }
     } else {
-        // MIXED: FP64 refinement around FP32 inner solves of A D B = R_true.
-        if (X0) MEK_TRY(copy_f64(X0, p * q, w.Xacc, s));
-        else MEK_TRY(fill_zero_bytes(w.Xacc, (long long)(p * q) * 8, s));
+        // MIXED: FP64 refinement around FP32 inner solves of A D B = R_true,
+        // for every instance that has not met its stop rule yet.
+        for (int64_t b = 0; b < nb; ++b) {
+            if (X0) MEK_TRY(copy_f64(X0 + b * pq, p * q, w.Xacc + b * pq, s));
+            else MEK_TRY(fill_zero_bytes(w.Xacc + b * pq, (long long)pq * 8, s));
+        }
         // The inner stop is a 1e-3 drop of the residual norm, which FP32 reaches
         // well above its drift floor; the cap only bounds a pass.
         const long long inner_cap = o->inner_iters > 0 ? o->inner_iters
                                                        : std::max<long long>(20000, 200 * m);
-        long long done = 0;
-        passes = 0;
-        double S0 = -1.0;
+        std::vector<long long> done(nb, 0);
+        std::vector<double> S0(nb, -1.0);
+        std::vector<char> running(nb, 1);
+        for (int64_t b = 0; b < nb; ++b) passes[b] = 0;
+        // Replayed indices continue across passes: the kernel reads entry
+        // k_offset + k, with k_offset the updates already made.
+        mek_solve_opts io = *o;
+        io.diverge = 0.0;
+        // Inner stop: the outer rule on the true error when it is REL_ERR, and
+        // in every case a drop of the inner residual by 1e-3 (the range in
+        // which the FP32 incremental residual is still accurate).
+        io.stop = (o->stop == MEK_STOP_REL_ERR) ? MEK_STOP_REL_ERR : MEK_STOP_NONE;
+        io.tol = o->tol;
+        std::vector<DevReport> ir(nb);
         for (;;) {
-            if ((st = residual_into_R64(w.Xacc))) return st;
-            double S = 0.0, err2 = NAN;
-            MEK_TRY(sq_norm(w.R64, m * n, w.scal + 4, w.red, s));
-            if ((st = read_scalar(w.scal + 4, &S, s))) return st;
-            if (S0 < 0.0) S0 = S;
-            double err = NAN;
-            if (o->X_ref) {
-                MEK_TRY(sq_diff_norm(w.Xacc, o->X_ref, p * q, w.scal + 5, w.red, s));
-                if ((st = read_scalar(w.scal + 5, &err2, s))) return st;
-                err = sqrt(err2 / ref2);
+            std::vector<InstSlot> slots;
+            for (int64_t b = 0; b < nb; ++b) {
+                if (!running[b]) continue;
+                double* Xacc = w.Xacc + b * pq;
+                if ((st = residual_into_R64(b, Xacc))) return st;
+                double S = 0.0, err2 = NAN, err = NAN;
+                MEK_TRY(sq_norm(w.R64 + b * mn, m * n, w.scal + 4, w.red, s));
+                if ((st = read_scalar(w.scal + 4, &S, s))) return st;
+                if (S0[b] < 0.0) S0[b] = S;
+                if (o->X_ref) {
+                    MEK_TRY(sq_diff_norm(Xacc, o->X_ref + b * pq, p * q, w.scal + 5, w.red, s));
+                    if ((st = read_scalar(w.scal + 5, &err2, s))) return st;
+                    err = sqrt(err2 / ref2[b]);
+                }
+                DevReport& r = rep[b];
+                r.S = S;
+                r.err = err;
+                r.iters = done[b];
+                const long long hk = done[b];
+                if (o->hist_cap > hk) {
+                    const size_t ho = (size_t)(b * o->hist_cap + hk);
+                    if (o->resid_hist)
+                        MEK_TRY(hipMemcpyAsync(o->resid_hist + ho, &S, 8, hipMemcpyHostToDevice, s));
+                    if (o->err_hist)
+                        MEK_TRY(hipMemcpyAsync(o->err_hist + ho, &err, 8, hipMemcpyHostToDevice, s));
+                    MEK_TRY(hipStreamSynchronize(s));
+                }
+                int fin = 1;
+                if (o->stop == MEK_STOP_REL_ERR && err <= o->tol) r.status = MEK_OK;
+                else if (o->stop == MEK_STOP_REL_RESID && sqrt(S) <= o->tol * sqrt(C2[b])) r.status = MEK_OK;
+                else if (S == 0.0) r.status = MEK_EXACT;
+                else if (!isfinite(S) || (o->diverge > 0.0 && S > o->diverge * S0[b])) r.status = MEK_EDIVERGED;
+                else if (done[b] >= o->max_iters) r.status = MEK_MAXITER;
+                else fin = 0;
+                if (fin) { running[b] = 0; continue; }
+                // Inner problem: A D B = R_true from D = 0, error against
+                // X_ref - X_acc, so that its error is the error of X_acc + D.
+                MEK_TRY(convert_f64_f32(w.R64 + b * mn, m * n, w.R32 + b * mn, s));
+                MEK_TRY(fill_zero_bytes(w.Xt32 + b * pq, (long long)pq * 4, s));
+                if (o->X_ref) {
+                    MEK_TRY(lincomb_f64(1.0, o->X_ref + b * pq, -1.0, Xacc, p * q, w.Xtmp + b * pq, s));
+                    MEK_TRY(transpose_to<double>(w.Xtmp + b * pq, (int)p, (int)q, w.Xref_t + b * pq, s));
+                }
+                InstSlot sl = slot_for(b);
+                sl.C2 = S;
+                sl.S_target = 1e-6 * S;
+                sl.max_iters = std::min<long long>(inner_cap, o->max_iters - done[b]);
+                sl.k_offset = done[b];
+                sl.hist_offset = done[b];
+                slots.push_back(sl);
             }
-            rep.S = S;
-            rep.err = err;
-            rep.iters = done;
-            if (o->hist_cap > done) {
-                if (o->resid_hist)
-                    MEK_TRY(hipMemcpyAsync(o->resid_hist + done, &S, 8, hipMemcpyHostToDevice, s));
-                if (o->err_hist)
-                    MEK_TRY(hipMemcpyAsync(o->err_hist + done, &err, 8, hipMemcpyHostToDevice, s));
-                MEK_TRY(hipStreamSynchronize(s));
-            }
-            if (o->stop == MEK_STOP_REL_ERR && err <= o->tol) { rep.status = MEK_OK; break; }
-            if (o->stop == MEK_STOP_REL_RESID && sqrt(S) <= o->tol * sqrt(C2)) { rep.status = MEK_OK; break; }
-            if (S == 0.0) { rep.status = MEK_EXACT; break; }
-            if (!isfinite(S) || (o->diverge > 0.0 && S > o->diverge * S0)) { rep.status = MEK_EDIVERGED; break; }
-            if (done >= o->max_iters) { rep.status = MEK_MAXITER; break; }
-            // Inner problem: A D B = R_true from D = 0, error against X_ref - X_acc.
-            MEK_TRY(convert_f64_f32(w.R64, m * n, w.R32, s));
-            MEK_TRY(fill_zero_bytes(w.Xt32, (long long)(p * q) * 4, s));
-            mek_solve_opts io = *o;
-            io.replay_idx = nullptr;
-            io.replay_len = 0;
-            io.diverge = 0.0;
-            const double* xref_t = nullptr;
-            if (o->X_ref) {
-                // The inner iterate D is judged against X_ref - X_acc, so its
-                // error is the error of X_acc + D.
-                MEK_TRY(lincomb_f64(1.0, o->X_ref, -1.0, w.Xacc, p * q, w.Xtmp, s));
-                MEK_TRY(transpose_to<double>(w.Xtmp, (int)p, (int)q, w.Xref_t, s));
-                xref_t = w.Xref_t;
-            }
-            // Inner stop: the outer rule on the true error when it is REL_ERR,
-            // and in every case a drop of the inner residual by 1e-3 (the range
-            // in which the FP32 incremental residual is still accurate).
-            io.stop = (o->stop == MEK_STOP_REL_ERR) ? MEK_STOP_REL_ERR : MEK_STOP_NONE;
-            io.tol = o->tol;
-            const double S_target = 1e-6 * S;
-            const long long cap = std::min<long long>(inner_cap, o->max_iters - done);
-            DevReport ir;
-            st = run_kernel<float>(P, &io, L, alpha, S, ref2, xref_t, cap, done, done, S_target,
-                                   w.R32, w.Xt32, s, &ir, &kms);
+            if (slots.empty()) break;
+            const bool batched = nb > 1;
+            st = run_kernel<float>(P, &io, L, alpha, slots[0], batched ? slots.data() : nullptr,
+                                   (int)slots.size(), o->X_ref ? w.Xref_t : nullptr, w.R32, w.Xt32,
+                                   s, ir.data(), &kms);
             if (st) return st;
-            // X_acc += D, accumulated in FP64.
-            MEK_TRY(transpose_from<float>(w.Xt32, (int)p, (int)q, w.Xtmp, s));
-            MEK_TRY(lincomb_f64(1.0, w.Xacc, 1.0, w.Xtmp, p * q, w.Xacc, s));
-            done += ir.iters;
-            ++passes;
-            if (ir.status == MEK_ETIMEOUT || ir.status == MEK_EDIVERGED) { rep.status = ir.status; break; }
-            if (ir.iters == 0 && ir.status != MEK_OK) { rep.status = MEK_MAXITER; break; }
+            for (const InstSlot& sl : slots) {
+                const int64_t b = sl.id;
+                // X_acc += D, accumulated in FP64.
+                MEK_TRY(transpose_from<float>(w.Xt32 + b * pq, (int)p, (int)q, w.Xtmp + b * pq, s));
+                MEK_TRY(lincomb_f64(1.0, w.Xacc + b * pq, 1.0, w.Xtmp + b * pq, p * q, w.Xacc + b * pq, s));
+                done[b] += ir[b].iters;
+                ++passes[b];
+                if (ir[b].status == MEK_ETIMEOUT || ir[b].status == MEK_EDIVERGED) {
+                    rep[b].status = ir[b].status;
+                    rep[b].iters = done[b];
+                    running[b] = 0;
+                } else if (ir[b].iters == 0 && ir[b].status != MEK_OK) {
+                    rep[b].status = MEK_MAXITER;
+                    rep[b].iters = done[b];
+                    running[b] = 0;
+                }
+            }
         }
-        MEK_TRY(copy_f64(w.Xacc, p * q, X, s));
+        for (int64_t b = 0; b < nb; ++b)
+            MEK_TRY(copy_f64(w.Xacc + b * pq, p * q, X + b * pq, s));
     }
     MEK_TRY(hipStreamSynchronize(s));
-    if (report) {
-        report->iters = rep.iters;
-        report->status = rep.status;
-        report->resid2 = rep.S;
-        report->rel_err = o->X_ref ? rep.err : NAN;
-        report->alpha = alpha;
-        report->team_wgs = L.W;
-        report->r_in_lds = L.lds ? 1 : 0;
-        report->passes = passes;
-        report->kernel_ms = kms;
+    int ret = MEK_OK;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (reports) {
+            mek_report& r = reports[b];
+            r.iters = rep[b].iters;
+            r.status = rep[b].status;
+            r.resid2 = rep[b].S;
+            r.rel_err = o->X_ref ? rep[b].err : NAN;
+            r.alpha = alpha;
+            r.team_wgs = L.W;
+            r.r_in_lds = L.lds ? 1 : 0;
+            r.passes = passes[b];
+            r.kernel_ms = kms;
+        }
+        const int sb = rep[b].status;
+        if (ret == MEK_OK && sb != MEK_OK) ret = sb;
+        else if (ret >= 0 && sb < 0) ret = sb;
     }
-    return rep.status;
+    return ret;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mek_solve(mek_plan P, const double* C, const double* X0, const mek_solve_opts* o, double* X,
+              mek_report* report, void* stream) {
+    return solve_impl(P, 1, C, X0, o, X, report, (hipStream_t)stream);
+}
+
+int mek_solve_batched(mek_plan P, int64_t batch, const double* C, const double* X0,
+                      const mek_solve_opts* o, double* X, mek_report* reports, void* stream) {
+    if (batch < 1) return MEK_EINVAL;
+    return solve_impl(P, batch, C, X0, o, X, reports, (hipStream_t)stream);
 }
 
 int mek_philox_uniform(uint64_t seed, uint64_t instance, int64_t k0, int64_t count, double* out,

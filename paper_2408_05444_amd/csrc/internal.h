@@ -34,6 +34,18 @@ struct DevReport {
     double err;     // relative error at exit (NaN without a reference)
 };
 
+// Per-instance scalars of a batched launch (instances share A and B).
+struct InstSlot {
+    int id;                      // instance index: strides of its buffers
+    int pad;
+    double C2, ref2, S_target;
+    long long max_iters, k_offset, hist_offset;
+    unsigned long long inst;     // Philox key word 1
+};
+
+// Per-instance strides of the exchange and error buffers (words).
+constexpr int kErrStride = 512;
+
 // Everything the persistent solver kernel needs for one instance. T is the
 // storage/update type of R, X and the Gram matrices (double or float);
 // norms, selection and the stop test are always double.
@@ -71,7 +83,7 @@ struct SolveParams {
     double tol;
     long long max_iters;
     unsigned long long seed, inst;
-    long long k_offset;          // Philox counter offset (refinement passes)
+    long long k_offset;          // updates made before this launch (Philox counter and replay offset)
     const int32_t* replay;
     long long replay_len;
     double diverge;
@@ -85,6 +97,12 @@ struct SolveParams {
     unsigned long long* phase;   // optional: per-phase wall-clock ticks (3 timed work-groups)
     int a_in_lds;                // keep ||A_i||^2 for all rows in LDS
     int poll_sleep;              // s_sleep length between polls of exchange words
+    // Batch: with slots set, nb teams of W work-groups, team b on instance
+    // slots[b].id, whose R, X^T, X_ref^T, r, rowbuf, vbuf, wbuf, errpart,
+    // sync, report and histories sit at that index times their size from the
+    // pointers above; its scalars come from the slot.
+    int nb;
+    const InstSlot* slots;
     // Team layout.
     int W;      // work-groups in the team
     int rpw;    // rows of R per work-group

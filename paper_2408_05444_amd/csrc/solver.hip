@@ -1,25 +1,29 @@
 // Persistent solver kernel for the greedy block Kaczmarz family (Algs. 1-5 of
 // the paper) on gfx950.
 //
-// One launch runs the whole iteration for one instance. The instance is
-// split over a *team* of W co-resident work-groups (a cooperative launch):
+// One launch runs the whole iteration for one instance (or, batched, one
+// team per instance). The instance is split over a *team* of W co-resident
+// work-groups (a cooperative launch):
 //   - work-group g owns rows [g*rpw, (g+1)*rpw) of the residual R. When they
 //     fit, those rows live in LDS for the whole solve, so R never travels to
 //     HBM inside the loop; otherwise they stay in device memory.
 //   - it owns rows [g*xpw, ...) of X^T (columns of X) and entries
-//     [g*wpw, ...) of the vector w = R_{i_k} B^T B.
+//     [g*wpw, ...) of the vector w = (R_{i_k} B^T) B.
 // Per update k every work-group
 //   1. reads all row norms r_i = ||R_i||^2 and computes ||R||_F^2, the
 //      maximum ratio max_i r_i/||A_i||^2 and the stop test, then runs the
 //      selection rule itself (redundantly, in a fixed reduction order, so all
 //      work-groups pick the same i_k without another exchange);
-//   2. gets the selected row R_{i_k} (published by its owner when R is in
-//      LDS; read directly otherwise) and computes its share of
-//      v = R_{i_k} B^T (the X update, Alg. 3's X^{k+1}) and of
-//      w = R_{i_k} (B^T B) (the residual update, Alg. 3's R^{k+1});
-//   3. after a team barrier, updates its own rows
-//      R_i -= alpha/||A_i_k||^2 (A A^T)_{i,i_k} w and recomputes their norms
-//      in the same pass; another barrier closes the update.
+//   2. takes the selected row R_{i_k} (published by its owner), computes its
+//      entries of v = R_{i_k} B^T and publishes them, updates its columns of
+//      X (Alg. 3's X^{k+1}) while the rest of v arrives, then computes and
+//      publishes its entries of w = v B;
+//   3. with all of w, updates its own rows
+//      R_i -= alpha/||A_i_k||^2 (A A^T)_{i,i_k} w (Alg. 3's R^{k+1}) and
+//      publishes their new norms, which start update k + 1.
+// The hand-overs go through tagged exchange words (exchange.h), with no
+// team-wide barrier.
+#include "exchange.h"
 #include "internal.h"
 
 #include <float.h>
@@ -27,26 +31,6 @@
 #include <math.h>
 
 namespace mek {
-
-// ---------------------------------------------------------------------------
-// Cross-work-group exchange. The few values that work-groups hand to each
-// other every update (row norms, the published row, slices of w, error
-// partials) are written and read with relaxed agent-scope atomics, which
-// the compiler turns into plain stores/loads that go to the device-wide
-// coherence point (cache policy sc1). Before a work-group signals a team
-// barrier or flag it waits for its own outstanding stores (s_waitcnt), so
-// its data is in place before the signal can be seen; a reader only loads
-// after it has seen the signal. No L2 write-back or invalidate is needed,
-// so read-only operands (A, B, A A^T, B^T B, ||A_i||^2) stay cached in L2.
-// ---------------------------------------------------------------------------
-template <typename U>
-__device__ __forceinline__ U xload(const U* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename U>
-__device__ __forceinline__ void xstore(U* p, U v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 struct SelectOut {
     int idx;
@@ -172,120 +156,6 @@ __device__ __forceinline__ SelectOut select_rows(int variant, int b, int cnt,
     return sample_set<false, SR>(b, cnt, aa, aa, rho, 0.0, u, sc, set_list, in_set);
 }
 
-// ---------------------------------------------------------------------------
-// Tagged exchange words. Work-groups of a team hand each other four kinds of
-// values every update: row norms r_i, error partials, the selected row
-// R_{i_k} and the slices of w. Each value travels in one 64-bit word that
-// also carries a 2-bit sequence tag, so a reader polls the data itself
-// until the tags show the current update: the signal and the data arrive
-// together, and no team-wide barrier is needed. A double keeps the tag in its
-// two lowest mantissa bits (a change of at most 3 units in the last place,
-// the size of one rounding; an exact zero stays zero); a float keeps its 32
-// bits and the tag sits in the upper half of the word. Words are written
-// and read with agent-scope relaxed atomics (aligned 64-bit, so a reader
-// never sees half of a word).
-//
-// One buffer per kind suffices: every rewrite of a word is causally after
-// every work-group has read its previous contents (the next r needs every
-// slice of w, each slice of w needs the published row, and the next row
-// needs every r), so a reader waiting for tag t can only see tag t or the
-// tag of the update before.
-// ---------------------------------------------------------------------------
-typedef unsigned long long xword;
-
-__device__ __forceinline__ unsigned int seq_tag(long long k) { return (unsigned int)((k + 1) & 3); }
-
-__device__ __forceinline__ xword pack_word(double v, unsigned int tag) {
-    return ((xword)__double_as_longlong(v) & ~3ull) | tag;
-}
-__device__ __forceinline__ xword pack_word(float v, unsigned int tag) {
-    return ((xword)tag << 32) | (xword)__float_as_uint(v);
-}
-template <typename T> __device__ __forceinline__ T word_value(xword w);
-template <> __device__ __forceinline__ double word_value<double>(xword w) {
-    return ((w & 0x7FFFFFFFFFFFFFFCull) == 0) ? 0.0 : __longlong_as_double((long long)w);
-}
-template <> __device__ __forceinline__ float word_value<float>(xword w) {
-    return __uint_as_float((unsigned int)w);
-}
-template <typename T> __device__ __forceinline__ unsigned int word_tag(xword w);
-template <> __device__ __forceinline__ unsigned int word_tag<double>(xword w) {
-    return (unsigned int)(w & 3);
-}
-template <> __device__ __forceinline__ unsigned int word_tag<float>(xword w) {
-    return (unsigned int)(w >> 32) & 3;
-}
-
-// Pause between two polls: s_sleep takes an immediate, so the few allowed
-// lengths are dispatched on a (wave-uniform) runtime value.
-__device__ __forceinline__ void poll_pause(int sleep) {
-    switch (sleep) {
-        case 0: break;
-        case 2: __builtin_amdgcn_s_sleep(2); break;
-        case 4: __builtin_amdgcn_s_sleep(4); break;
-        case 8: __builtin_amdgcn_s_sleep(8); break;
-        case 16: __builtin_amdgcn_s_sleep(16); break;
-        default: __builtin_amdgcn_s_sleep(1); break;
-    }
-}
-
-// Read cnt (<= N) words p[0..cnt) until every one carries `tag`. Returns
-// false if the wait gives up (spin limit, or another work-group aborted).
-template <typename T, int N>
-__device__ __forceinline__ bool poll_words(const xword* p, int cnt, unsigned int tag, T (&out)[N],
-                                           TeamSync* ts, int sleep) {
-    long long spins = 0;
-    for (;;) {
-        xword w[N];
-#pragma unroll
-        for (int j = 0; j < N; ++j) w[j] = (j < cnt) ? xload(p + j) : 0ull;
-        bool ready = true;
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            if (j < cnt) {
-                ready = ready && (word_tag<T>(w[j]) == tag);
-                out[j] = word_value<T>(w[j]);
-            }
-        }
-        if (ready) return true;
-        if ((++spins & 63) == 0 &&
-            (spins > kSpinLimit ||
-             __hip_atomic_load(&ts->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-            __hip_atomic_store(&ts->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        poll_pause(sleep);
-    }
-}
-
-// Strided variant: words p[j * stride] for j < cnt.
-template <typename T, int N>
-__device__ __forceinline__ bool poll_strided(const xword* p, int stride, int cnt, unsigned int tag,
-                                             T (&out)[N], TeamSync* ts, int sleep) {
-    long long spins = 0;
-    for (;;) {
-        xword w[N];
-#pragma unroll
-        for (int j = 0; j < N; ++j) w[j] = (j < cnt) ? xload(p + (size_t)j * stride) : 0ull;
-        bool ready = true;
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            if (j < cnt) {
-                ready = ready && (word_tag<T>(w[j]) == tag);
-                out[j] = word_value<T>(w[j]);
-            }
-        }
-        if (ready) return true;
-        if ((++spins & 63) == 0 &&
-            (spins > kSpinLimit ||
-             __hip_atomic_load(&ts->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-            __hip_atomic_store(&ts->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        poll_pause(sleep);
-    }
-}
-
 // Sum over each row of 16 lanes (DPP): every lane of a row gets the row total.
 __device__ __forceinline__ double row16_sum(double v) {
     v += dpp_d<kDppSwap1>(v);
@@ -373,6 +243,38 @@ enum { kPhReduce, kPhSelect, kPhRow, kPhDots, kPhWait, kPhX, kPhUpdate, kPhEnd, 
         }                                                               \
     } while (0)
 
+// Point the per-instance fields of P at instance slot b of a batch.
+template <typename T>
+__device__ __forceinline__ void bind_instance(SolveParams<T>& P, int b) {
+    const InstSlot sl = P.slots[b];
+    const size_t id = (size_t)sl.id;
+    const size_t mn = (size_t)P.m * P.n, pq = (size_t)P.p * P.q;
+    P.R += id * mn;
+    P.Xt += id * pq;
+    if (P.Xref_t) P.Xref_t += id * pq;
+    P.r += id * P.m;
+    // Exchange buffers hold one 64-bit word per entry whatever T is.
+    P.rowbuf = reinterpret_cast<T*>(reinterpret_cast<char*>(P.rowbuf) + id * P.n * 8);
+    P.vbuf = reinterpret_cast<T*>(reinterpret_cast<char*>(P.vbuf) + id * P.q * 8);
+    P.wbuf = reinterpret_cast<T*>(reinterpret_cast<char*>(P.wbuf) + id * P.n * 8);
+    P.errpart += id * kErrStride;
+    P.sync += id;
+    P.report += id;
+    const size_t hc = (size_t)P.hist_cap;
+    if (P.resid_hist) P.resid_hist += id * hc;
+    if (P.err_hist) P.err_hist += id * hc;
+    if (P.idx_hist) P.idx_hist += id * hc;
+    if (P.set_hist) P.set_hist += id * hc;
+    if (b != 0) P.phase = nullptr;
+    P.C2 = sl.C2;
+    P.ref2 = sl.ref2;
+    P.S_target = sl.S_target;
+    P.max_iters = sl.max_iters;
+    P.k_offset = sl.k_offset;
+    P.hist_offset = sl.hist_offset;
+    P.inst = sl.inst;
+}
+
 template <typename T, bool LDS, int SR>
 __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
@@ -383,7 +285,12 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
 
     const int W = P.W;
     const bool team = W > 1;
-    const int g = blockIdx.x;
+    int g = blockIdx.x;
+    if (P.slots) {
+        const int b = g / W;
+        g -= b * W;
+        bind_instance(P, b);
+    }
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int m = P.m, n = P.n, p = P.p, q = P.q;
     const int row0 = g * P.rpw;
@@ -522,8 +429,8 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
 
         // ---- Selection.
         int ik;
-        if (P.replay && k < P.replay_len) {
-            ik = P.replay[k];
+        if (P.replay && P.k_offset + k < P.replay_len) {
+            ik = P.replay[P.k_offset + k];
             last_set = 0;
         } else {
             const SelectOut so = select_rows<SR>(P.variant, sb, scnt, rr, aa, rho, S, M, P.F_A,
@@ -707,9 +614,12 @@ static hipError_t launch_one(const SolveParams<T>& P, size_t lds_bytes, hipStrea
         (void)hipGetLastError();
     SolveParams<T> copy = P;
     void* args[] = {&copy};
-    if (P.W == 1)
+    const int blocks = P.W * (P.slots ? P.nb : 1);
+    if (blocks == 1)
         return hipLaunchKernel((const void*)kern, dim3(1), dim3(kThreads), args, lds_bytes, s);
-    return hipLaunchCooperativeKernel((const void*)kern, dim3(P.W), dim3(kThreads), args,
+    // Teams wait on each other's words, so every work-group of the grid must
+    // be resident at once: a cooperative launch guarantees it (or fails).
+    return hipLaunchCooperativeKernel((const void*)kern, dim3(blocks), dim3(kThreads), args,
                                       (unsigned int)lds_bytes, s);
 }
 

@@ -128,6 +128,19 @@ def with_zero_rows(inst: Instance, rows) -> Instance:
                     _c(C), None if inst.X_star is None else inst.X_star.copy())
 
 
+def shared_ab_batch(inst: Instance, nb: int, seed: int):
+    """nb consistent instances sharing inst's A and B: X*_b iid N(0,1) drawn
+    in order b = 0..nb-1 from default_rng(seed), C_b = A X*_b B."""
+    rng = np.random.default_rng(seed)
+    p, q = inst.A.shape[1], inst.B.shape[0]
+    out = []
+    for b in range(nb):
+        X = rng.standard_normal((p, q))
+        out.append(Instance(inst.name + f" batch {b}/{nb} seed={seed}", inst.A, inst.B,
+                            _c(inst.A @ X @ inst.B), _c(X)))
+    return out
+
+
 def blur_toeplitz(size: int, sigma: float, half_width: int = 4) -> np.ndarray:
     """Banded Toeplitz Gaussian blur (2*half_width+1 taps), each row divided by its sum.
 
