@@ -16,6 +16,17 @@
  *     MEK_GRBK   greedy threshold set + residual sampling    (Alg. 3)
  *     MEK_RGRBK  the same with relaxation theta in [0, 1]    (Alg. 4)
  *     MEK_MWRBK  argmax of ||R_i||^2/||A_i||^2, lowest index (Alg. 5)
+ *   MEK_TWOSIDED extends the greedy criterion of Algs. 3/4 from rows to
+ *   entries and projects exactly onto a block of equations A_I X B_J = C_IJ
+ *   (an extension; the paper's iteration is the row form above). With
+ *   omega_ij = R_ij^2 / (||A_i||^2 ||B_j||^2) (B_j a column of B), Omega =
+ *   max omega and eps = min(Omega, theta Omega + (1 - theta) ||R||_F^2 /
+ *   (||A||_F^2 ||B||_F^2)): rows with max_j omega_ij >= eps are ranked by
+ *   that maximum (lower index first on ties); I = the first block_rows of
+ *   them less those whose Cholesky pivot in A_I A_I^T (rank order) is at
+ *   most tau times its diagonal; J likewise from the columns with B^T B, at
+ *   most block_cols; then W = (A_I A_I^T)^{-1} R_IJ (B_J^T B_J)^{-1},
+ *   X += A_I^T W B_J^T, R -= (A A^T)_{:,I} W (B^T B)_{J,:}. No step size.
  *
  * Conventions shared by every entry point:
  *   - Matrices are dense, row-major and contiguous (leading dimension equals
@@ -38,14 +49,15 @@
 extern "C" {
 #endif
 
-#define MEK_ABI_VERSION 1
+#define MEK_ABI_VERSION 2
 
-/* Selection rules (Algs. 1-5). */
+/* Selection rules (Algs. 1-5), and the two-sided block projection. */
 #define MEK_BK 0
 #define MEK_RBK 1
 #define MEK_GRBK 2
 #define MEK_RGRBK 3
 #define MEK_MWRBK 4
+#define MEK_TWOSIDED 5
 
 /* Stop rules, evaluated before every update (so 0 updates when X0 already
  * passes). REL_ERR: ||X^k - X_ref||_F <= tol ||X_ref||_F (Sec. 5's RRN is
@@ -120,6 +132,16 @@ typedef struct {
     int64_t hist_cap;
     /* MEK_MIXED only: FP32 updates per refinement pass (0: automatic). */
     int64_t inner_iters;
+    /* MEK_TWOSIDED only (FP64 plans, one instance): the block caps s and t
+     * (1 .. 32), the independence tolerance tau (<= 0: 1e-10), and optional
+     * histories (device, caller-owned): rows_hist[k * block_rows + x] = the
+     * x-th row of I at step k and cols_hist[k * block_cols + y] likewise
+     * (-1 past the block's size), for k < hist_cap. replay_idx must be NULL. */
+    int block_rows;
+    int block_cols;
+    double tau;
+    int32_t* rows_hist;
+    int32_t* cols_hist;
 } mek_solve_opts;
 
 typedef struct {

@@ -21,7 +21,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmek.so")
 
 MEK_BK, MEK_RBK, MEK_GRBK, MEK_RGRBK, MEK_MWRBK = 0, 1, 2, 3, 4
-VARIANTS = {"bk": MEK_BK, "rbk": MEK_RBK, "grbk": MEK_GRBK, "rgrbk": MEK_RGRBK, "mwrbk": MEK_MWRBK}
+MEK_TWOSIDED = 5
+VARIANTS = {"bk": MEK_BK, "rbk": MEK_RBK, "grbk": MEK_GRBK, "rgrbk": MEK_RGRBK, "mwrbk": MEK_MWRBK,
+            "twosided": MEK_TWOSIDED}
 MEK_STOP_NONE, MEK_STOP_REL_ERR, MEK_STOP_REL_RESID = 0, 1, 2
 STOPS = {"none": 0, "rel_err": 1, "rel_resid": 2}
 MEK_FP64, MEK_FP32, MEK_MIXED = 0, 1, 2
@@ -51,7 +53,10 @@ class mek_solve_opts(ctypes.Structure):
                 ("diverge", ctypes.c_double),
                 ("resid_hist", ctypes.c_void_p), ("err_hist", ctypes.c_void_p),
                 ("idx_hist", ctypes.c_void_p), ("set_hist", ctypes.c_void_p),
-                ("hist_cap", ctypes.c_int64), ("inner_iters", ctypes.c_int64)]
+                ("hist_cap", ctypes.c_int64), ("inner_iters", ctypes.c_int64),
+                ("block_rows", ctypes.c_int), ("block_cols", ctypes.c_int),
+                ("tau", ctypes.c_double), ("rows_hist", ctypes.c_void_p),
+                ("cols_hist", ctypes.c_void_p)]
 
 
 class mek_report(ctypes.Structure):
@@ -199,17 +204,29 @@ class SolveResult:
     err_hist: Optional[torch.Tensor] = None
     idx_hist: Optional[torch.Tensor] = None
     set_hist: Optional[torch.Tensor] = None
+    rows_hist: Optional[list] = None
+    cols_hist: Optional[list] = None
 
 
 def _solve_opts(nb, dev, variant, theta, alpha, stop, tol, X_ref_ptr, max_iters, seed, instance,
-                replay_idx, diverge, hist_cap, inner_iters):
+                replay_idx, diverge, hist_cap, inner_iters, block_rows=0, block_cols=0, tau=0.0):
     hists = {}
+    twosided = VARIANTS.get(variant, variant) == MEK_TWOSIDED
     if hist_cap > 0:
         hists["resid_hist"] = torch.full((nb, hist_cap), float("nan"), dtype=torch.float64, device=dev)
         hists["err_hist"] = torch.full((nb, hist_cap), float("nan"), dtype=torch.float64, device=dev)
-        hists["idx_hist"] = torch.full((nb, hist_cap), -1, dtype=torch.int32, device=dev)
-        hists["set_hist"] = torch.zeros((nb, hist_cap), dtype=torch.int32, device=dev)
+        if twosided:
+            hists["rows_hist"] = torch.full((nb, hist_cap, block_rows), -1, dtype=torch.int32,
+                                            device=dev)
+            hists["cols_hist"] = torch.full((nb, hist_cap, block_cols), -1, dtype=torch.int32,
+                                            device=dev)
+        else:
+            hists["idx_hist"] = torch.full((nb, hist_cap), -1, dtype=torch.int32, device=dev)
+            hists["set_hist"] = torch.zeros((nb, hist_cap), dtype=torch.int32, device=dev)
     o = mek_solve_opts()
+    o.block_rows = int(block_rows)
+    o.block_cols = int(block_cols)
+    o.tau = float(tau)
     o.variant = VARIANTS.get(variant, variant)
     o.theta = float(theta)
     o.alpha = float(alpha)
@@ -235,10 +252,17 @@ def _result(X, code, rep, hists, b, hist_cap):
                       int(rep.team_wgs), bool(rep.r_in_lds), int(rep.passes), rep.kernel_ms)
     if hist_cap > 0:
         k = min(int(rep.iters), hist_cap - 1)
+        kk = min(int(rep.iters), hist_cap)
         res.resid_hist = hists["resid_hist"][b, :k + 1]
         res.err_hist = hists["err_hist"][b, :k + 1]
-        res.idx_hist = hists["idx_hist"][b, :min(int(rep.iters), hist_cap)]
-        res.set_hist = hists["set_hist"][b, :min(int(rep.iters), hist_cap)]
+        if "rows_hist" in hists:
+            rows = hists["rows_hist"][b, :kk].cpu()
+            cols = hists["cols_hist"][b, :kk].cpu()
+            res.rows_hist = [r[r >= 0].tolist() for r in rows]
+            res.cols_hist = [c[c >= 0].tolist() for c in cols]
+        else:
+            res.idx_hist = hists["idx_hist"][b, :kk]
+            res.set_hist = hists["set_hist"][b, :kk]
     return res
 
 
@@ -247,13 +271,16 @@ def mek_solve(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = None, va
               X_ref: Optional[torch.Tensor] = None, max_iters: int = 100000, seed: int = 0,
               instance: int = 0, replay_idx: Optional[torch.Tensor] = None, diverge: float = 0.0,
               hist_cap: int = 0, inner_iters: int = 0, X_out: Optional[torch.Tensor] = None,
+              block_rows: int = 32, block_cols: int = 32, tau: float = 0.0,
               raise_on_error: bool = True) -> SolveResult:
+    """variant "twosided" takes block_rows / block_cols (1..32) and tau; its
+    histories are rows_hist / cols_hist (lists of I and J per step)."""
     m, p, q, n = plan.m, plan.p, plan.q, plan.n
     dev = C.device
     X = X_out if X_out is not None else torch.empty(p, q, dtype=torch.float64, device=dev)
     o, hists = _solve_opts(1, dev, variant, theta, alpha, stop, tol,
                            _dev(X_ref, shape=(p, q), name="X_ref"), max_iters, seed, instance,
-                           replay_idx, diverge, hist_cap, inner_iters)
+                           replay_idx, diverge, hist_cap, inner_iters, block_rows, block_cols, tau)
     rep = mek_report()
     code = lib().mek_solve(plan.handle, _dev(C, shape=(m, n), name="C"),
                            _dev(X0, shape=(p, q), name="X0"), ctypes.byref(o),
@@ -268,8 +295,8 @@ def mek_solve_batched(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = 
                       tol: float = 0.0, X_ref: Optional[torch.Tensor] = None,
                       max_iters: int = 100000, seed: int = 0, instance: int = 0,
                       replay_idx: Optional[torch.Tensor] = None, diverge: float = 0.0,
-                      hist_cap: int = 0, inner_iters: int = 0,
-                      raise_on_error: bool = True):
+                      hist_cap: int = 0, inner_iters: int = 0, block_rows: int = 32,
+                      block_cols: int = 32, tau: float = 0.0, raise_on_error: bool = True):
     """Uniform batch: C (nb, m, n) [, X0, X_ref (nb, p, q)] sharing the plan's A
     and B. Returns (status, [SolveResult per instance]); instance b draws
     under Philox key (seed, instance + b)."""
@@ -279,7 +306,8 @@ def mek_solve_batched(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = 
     X = torch.empty(nb, p, q, dtype=torch.float64, device=dev)
     o, hists = _solve_opts(nb, dev, variant, theta, alpha, stop, tol,
                            _dev(X_ref, shape=(nb, p, q), name="X_ref"), max_iters, seed,
-                           instance, replay_idx, diverge, hist_cap, inner_iters)
+                           instance, replay_idx, diverge, hist_cap, inner_iters, block_rows,
+                           block_cols, tau)
     reps = (mek_report * nb)()
     code = lib().mek_solve_batched(plan.handle, nb, _dev(C, shape=(nb, m, n), name="C"),
                                    _dev(X0, shape=(nb, p, q), name="X0"), ctypes.byref(o),

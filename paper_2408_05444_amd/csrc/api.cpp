@@ -61,7 +61,13 @@ struct mek_plan_s {
     int cus = 0;
     int device = 0;
     double *A = nullptr, *B = nullptr, *BT = nullptr, *GA = nullptr, *GB = nullptr, *a = nullptr;
+    double* bcol = nullptr;   // n, ||B_j||^2 (columns of B), for the two-sided variant
+    double F_B = 0.0;         // ||B||_F^2
     int* active = nullptr;
+    // Exchange buffers of the two-sided block kernel (allocated on first use).
+    void* blk = nullptr;
+    unsigned long long *hbuf = nullptr, *rbuf = nullptr, *cpart = nullptr, *gcol = nullptr,
+                       *ebuf = nullptr, *epart = nullptr;
     float *A32 = nullptr, *B32 = nullptr, *BT32 = nullptr, *GA32 = nullptr, *GB32 = nullptr;
     Workspace ws;
 };
@@ -182,8 +188,8 @@ int ensure_workspace(mek_plan_s* P, int64_t nb) {
 
 void free_plan(mek_plan_s* P) {
     if (!P) return;
-    void* ptrs[] = {P->A, P->B, P->BT, P->GA, P->GB, P->a, P->active, P->A32, P->B32, P->BT32,
-                    P->GA32, P->GB32, P->ws.base};
+    void* ptrs[] = {P->A, P->B, P->BT, P->GA, P->GB, P->a, P->bcol, P->active, P->A32, P->B32,
+                    P->BT32, P->GA32, P->GB32, P->ws.base, P->blk};
     for (void* x : ptrs)
         if (x) (void)hipFree(x);
     delete P;
@@ -260,7 +266,15 @@ int choose_layout(const mek_plan_s* P, size_t elem, int64_t nb, Layout* L) {
 
 int validate_opts(const mek_plan_s* P, const mek_solve_opts* o) {
     if (!o) return MEK_EINVAL;
-    if (o->variant < MEK_BK || o->variant > MEK_MWRBK) return MEK_EINVAL;
+    if (o->variant < MEK_BK || o->variant > MEK_TWOSIDED) return MEK_EINVAL;
+    if (o->variant == MEK_TWOSIDED) {
+        if (o->block_rows < 1 || o->block_rows > kBlkCap) return MEK_EINVAL;
+        if (o->block_cols < 1 || o->block_cols > kBlkCap) return MEK_EINVAL;
+        if (!(o->tau <= 0.0 || (o->tau < 1.0 && isfinite(o->tau)))) return MEK_EINVAL;
+        if (o->replay_len > 0) return MEK_EINVAL;
+    }
+    if (o->hist_cap > 0 && (o->rows_hist || o->cols_hist) && o->variant != MEK_TWOSIDED)
+        return MEK_EINVAL;
     if (!(o->theta >= 0.0 && o->theta <= 1.0)) return MEK_EINVAL;
     if (o->stop < MEK_STOP_NONE || o->stop > MEK_STOP_REL_RESID) return MEK_EINVAL;
     if (o->stop != MEK_STOP_NONE && !(o->tol >= 0.0)) return MEK_EINVAL;
@@ -486,8 +500,8 @@ int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n, c
     if (alloc((void**)&P->A, (size_t)(m * p) * 8) || alloc((void**)&P->B, (size_t)(q * n) * 8) ||
         alloc((void**)&P->BT, (size_t)(q * n) * 8) ||
         alloc((void**)&P->GA, (size_t)(m * m) * 8) || alloc((void**)&P->GB, (size_t)(n * n) * 8) ||
-        alloc((void**)&P->a, (size_t)m * 8) || alloc((void**)&P->active, (size_t)m * 4) ||
-        ensure_workspace(P, 1))
+        alloc((void**)&P->a, (size_t)m * 8) || alloc((void**)&P->bcol, (size_t)n * 8) ||
+        alloc((void**)&P->active, (size_t)m * 4) || ensure_workspace(P, 1))
         return fail(MEK_ENOMEM);
     Workspace& w = P->ws;
     if (copy_f64(A, m * p, P->A, s) || copy_f64(B, q * n, P->B, s) ||
@@ -504,6 +518,10 @@ int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n, c
         hipStreamSynchronize(s))
         return fail(MEK_EHIP);
     if (P->n_active == 0 || !(P->F_A > 0.0)) return fail(MEK_EINVAL);
+    // ||B_j||^2 (rows of B^T) and ||B||_F^2.
+    if (row_sq_norms(P->BT, (int)n, (int)q, P->bcol, s) || sum_reduce(P->bcol, n, w.scal + 6, w.red, s))
+        return fail(MEK_EHIP);
+    if ((st = read_scalar(w.scal + 6, &P->F_B, s))) return fail(st);
     // Gram matrices A A^T (m x m) and B^T B (n x n) on the matrix cores.
     if (gemm_f64((int)m, (int)m, (int)p, 1.0, P->A, p, 1, P->A, 1, p, 0.0, nullptr, 0, P->GA, m, s) ||
         gemm_f64((int)n, (int)n, (int)q, 1.0, P->B, 1, n, P->B, n, 1, 0.0, nullptr, 0, P->GB, n, s))
@@ -573,6 +591,146 @@ int mek_plan_query(mek_plan P, double* row_norms, double* gram_a, double* gram_b
 
 namespace {
 
+// Team layout of the two-sided block kernel: the same policy as the row
+// solver (all CUs when the residual is large, R in LDS when it fits).
+int choose_layout_block2(const mek_plan_s* P, int s_cap, int t_cap, Layout* L) {
+    const int64_t m = P->m, n = P->n, q = P->q;
+    if (m > (int64_t)kSelRows * kThreads || n > (int64_t)kSelRows * kThreads) return MEK_EUNSUPPORTED;
+    const int cus = std::max(1, P->cus);
+    const size_t budget = block2_lds_budget();
+    auto bytes = [&](int Wc, bool lds) {
+        const int rpw = ceil_div(m, Wc);
+        const int Wr = ceil_div(m, rpw);
+        return block2_lds_bytes(rpw, (int)n, Wr, s_cap, t_cap, lds);
+    };
+    int W;
+    bool lds;
+    if (P->team_wgs > 0) {
+        W = (int)std::min<int64_t>({(int64_t)P->team_wgs, (int64_t)cus, m});
+        lds = (P->r_in_lds != 0) && bytes(W, true) <= budget;
+        if (P->r_in_lds == 1 && !lds) return MEK_EUNSUPPORTED;
+    } else {
+        const int64_t work = m * n;
+        int Wt = (int)std::min<int64_t>(std::max<int64_t>(1, (work + 32767) / 32768), cus);
+        Wt = (int)std::min<int64_t>(Wt, m);
+        int Wl = -1;
+        for (int Wc = 1; Wc <= std::min<int64_t>(cus, m); ++Wc)
+            if (bytes(Wc, true) <= budget) { Wl = Wc; break; }
+        if (P->r_in_lds != 0 && Wl > 0) {
+            W = std::max(Wt, Wl);
+            if (work >= (int64_t)cus * 4096) W = std::max(W, (int)std::min<int64_t>(cus, m));
+            lds = true;
+        } else {
+            if (P->r_in_lds == 1) return MEK_EUNSUPPORTED;
+            W = Wt;
+            lds = false;
+        }
+    }
+    const int rpw = ceil_div(m, W);
+    W = ceil_div(m, rpw);
+    L->W = W;
+    L->rpw = rpw;
+    L->xpw = ceil_div(q, W);
+    L->wpw = 0;
+    L->lds = lds && bytes(W, true) <= budget;
+    L->a_lds = false;
+    L->lds_bytes = bytes(W, L->lds);
+    if (L->lds_bytes > budget || W > kMaxTeam) return MEK_EUNSUPPORTED;
+    return MEK_OK;
+}
+
+int ensure_block_ws(mek_plan_s* P) {
+    if (P->blk) return MEK_OK;
+    const size_t m = P->m, n = P->n, cus = std::max(1, P->cus);
+    const size_t words = 2 * m + cus * n + n + (size_t)kBlkCap * kBlkCap + kMaxTeam;
+    MEK_TRY(hipMalloc(&P->blk, words * 8));
+    unsigned long long* w = (unsigned long long*)P->blk;
+    P->hbuf = w;
+    P->rbuf = P->hbuf + m;
+    P->cpart = P->rbuf + m;
+    P->gcol = P->cpart + cus * n;
+    P->ebuf = P->gcol + n;
+    P->epart = P->ebuf + kBlkCap * kBlkCap;
+    return MEK_OK;
+}
+
+// One launch of the two-sided block kernel on the residual in ws.R64.
+int run_block2(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double C2, double ref2,
+               const double* Xref_t, hipStream_t s, DevReport* out, double* kernel_ms) {
+    Workspace& w = P->ws;
+    int st = ensure_block_ws(P);
+    if (st) return st;
+    Block2Params K;
+    memset(&K, 0, sizeof(K));
+    K.m = (int)P->m;
+    K.p = (int)P->p;
+    K.q = (int)P->q;
+    K.n = (int)P->n;
+    K.A = P->A;
+    K.B = P->B;
+    K.GA = P->GA;
+    K.GB = P->GB;
+    K.a = P->a;
+    K.b = P->bcol;
+    K.F_A = P->F_A;
+    K.F_B = P->F_B;
+    K.R = w.R64;
+    K.Xt = w.Xt64;
+    K.Xref_t = Xref_t;
+    K.ref2 = ref2;
+    K.C2 = C2;
+    K.hbuf = P->hbuf;
+    K.rbuf = P->rbuf;
+    K.cpart = P->cpart;
+    K.gcol = P->gcol;
+    K.ebuf = P->ebuf;
+    K.errpart = P->epart;
+    K.sync = w.sync;
+    K.report = w.report;
+    K.theta = o->theta;
+    K.tau = o->tau > 0.0 ? o->tau : 1e-10;
+    K.s_cap = o->block_rows;
+    K.t_cap = o->block_cols;
+    K.stop = o->stop;
+    K.tol = o->tol;
+    K.max_iters = o->max_iters;
+    K.diverge = o->diverge;
+    K.resid_hist = o->resid_hist;
+    K.err_hist = o->err_hist;
+    K.rows_hist = o->rows_hist;
+    K.cols_hist = o->cols_hist;
+    K.hist_cap = o->hist_cap;
+    K.W = L.W;
+    K.rpw = L.rpw;
+    K.xpw = L.xpw;
+    K.r_in_lds = L.lds ? 1 : 0;
+    static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
+    K.poll_sleep = poll_sleep;
+    // Exchange words start with tag 0, which no step waits for.
+    const size_t words = 2 * P->m + (size_t)std::max(1, P->cus) * P->n + P->n +
+                         (size_t)kBlkCap * kBlkCap + kMaxTeam;
+    MEK_TRY(fill_zero_bytes(P->blk, (long long)(words * 8), s));
+    MEK_TRY(fill_zero_bytes(w.sync, sizeof(TeamSync), s));
+    hipEvent_t ev[2];
+    MEK_TRY(hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return MEK_EHIP;
+    }
+    hipError_t e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) e = launch_block2(K, L.lds_bytes, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, w.report, sizeof(DevReport), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    st = hip_status(e);
+    float ms = 0.0f;
+    if (st == MEK_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess && kernel_ms)
+        *kernel_ms += (double)ms;
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return st;
+}
+
 // The solve of nb instances that share the plan's A and B (nb = 1: mek_solve).
 // C, X0, X, X_ref and the histories are stacked per instance.
 int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
@@ -593,10 +751,16 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
         if (o->err_hist && (st = check_dev(o->err_hist, hc * 8))) return st;
         if (o->idx_hist && (st = check_dev(o->idx_hist, hc * 4))) return st;
         if (o->set_hist && (st = check_dev(o->set_hist, hc * 4))) return st;
+        if (o->rows_hist && (st = check_dev(o->rows_hist, hc * (size_t)o->block_rows * 4))) return st;
+        if (o->cols_hist && (st = check_dev(o->cols_hist, hc * (size_t)o->block_cols * 4))) return st;
     }
     const int prec = P->precision;
+    const bool twosided = o->variant == MEK_TWOSIDED;
+    if (twosided && (prec != MEK_FP64 || nb != 1)) return MEK_EUNSUPPORTED;
     Layout L;
-    if ((st = choose_layout(P, prec == MEK_FP64 ? 8 : 4, nb, &L))) return st;
+    if (twosided) st = choose_layout_block2(P, o->block_rows, o->block_cols, &L);
+    else st = choose_layout(P, prec == MEK_FP64 ? 8 : 4, nb, &L);
+    if (st) return st;
     if ((st = ensure_workspace(P, nb))) return st;
     Workspace& w = P->ws;
     if ((st = finite_check(C, nb * m * n, w.iscal, s))) return st;
@@ -673,8 +837,11 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
                 if (X0) MEK_TRY(transpose_to<double>(X0 + b * pq, (int)p, (int)q, w.Xt64 + b * pq, s));
                 else MEK_TRY(fill_zero_bytes(w.Xt64 + b * pq, (long long)pq * 8, s));
             }
-            st = run_kernel<double>(P, o, L, alpha, slots[0], sp, (int)nb, xr, w.R64, w.Xt64, s,
-                                    rep.data(), &kms);
+            if (twosided)
+                st = run_block2(P, o, L, C2[0], ref2[0], xr, s, rep.data(), &kms);
+            else
+                st = run_kernel<double>(P, o, L, alpha, slots[0], sp, (int)nb, xr, w.R64, w.Xt64, s,
+                                        rep.data(), &kms);
             if (st) return st;
             for (int64_t b = 0; b < nb; ++b)
                 MEK_TRY(transpose_from<double>(w.Xt64 + b * pq, (int)p, (int)q, X + b * pq, s));

@@ -110,6 +110,63 @@ struct SolveParams {
     int wpw;    // entries of w per work-group
 };
 
+// Two-sided block projection (block2.hip): at most kBlkCap rows and columns
+// per step.
+constexpr int kBlkCap = 32;
+
+struct Block2Params {
+    int m, p, q, n;
+    const double* A;       // m x p
+    const double* B;       // q x n
+    const double* GA;      // m x m, A A^T
+    const double* GB;      // n x n, B^T B
+    const double* a;       // m, ||A_i||^2
+    const double* b;       // n, ||B_j||^2 (columns of B)
+    double F_A, F_B;       // ||A||_F^2, ||B||_F^2
+    double* R;             // m x n residual (initial value in, storage if not in LDS)
+    double* Xt;            // q x p, the iterate transposed
+    const double* Xref_t;  // q x p or null
+    double ref2, C2;
+    // Exchange words (64-bit, tagged).
+    unsigned long long* hbuf;     // m: max_j omega_ij of row i
+    unsigned long long* rbuf;     // m: ||R_i||^2
+    unsigned long long* cpart;    // W x n: column maxima of omega over each work-group's rows
+    unsigned long long* gcol;     // n: column maxima
+    unsigned long long* ebuf;     // kBlkCap x kBlkCap: R_IJ
+    unsigned long long* errpart;  // W: partial ||X - X_ref||^2
+    TeamSync* sync;
+    DevReport* report;
+    double theta, tau;
+    int s_cap, t_cap;
+    int stop;
+    double tol;
+    long long max_iters;
+    double diverge;
+    double* resid_hist;
+    double* err_hist;
+    int32_t* rows_hist;    // hist_cap x s_cap
+    int32_t* cols_hist;    // hist_cap x t_cap
+    long long hist_cap;
+    int W, rpw, xpw;
+    int r_in_lds;
+    int poll_sleep;
+};
+
+// Bytes of the block kernel's LDS region shared by R_IJ / W, the radix
+// histograms and the column slice of exchange B.
+__host__ __device__ inline size_t block2_ereg_bytes(int s_cap, int t_cap, int ncs) {
+    size_t e = (size_t)s_cap * (t_cap + 1) * 8;
+    e = e > 1024 * sizeof(int) ? e : 1024 * sizeof(int);
+    e = e > (size_t)ncs * 8 ? e : (size_t)ncs * 8;
+    return (e + 15) & ~(size_t)15;
+}
+hipError_t launch_block2(const Block2Params& P, size_t lds_bytes, hipStream_t s);
+size_t block2_lds_bytes(int rpw, int n, int W, int s_cap, int t_cap, bool r_in_lds);
+size_t block2_lds_budget();
+
+// Rows of a selection chunk per thread (1, 2, 4, 8 or 16) for m rows.
+int sel_rows_for(int m);
+
 // Launchers (solver.hip).
 hipError_t launch_solve(const SolveParams<double>& P, bool r_in_lds, size_t lds_bytes,
                         hipStream_t s);

@@ -24,7 +24,7 @@ def _declared_functions():
 def test_header_declares_the_boundary():
     names = _declared_functions()
     for want in ["mek_version", "mek_status_string", "mek_plan_create", "mek_plan_destroy",
-                 "mek_plan_query", "mek_solve", "mek_philox_uniform", "mek_select",
+                 "mek_plan_query", "mek_solve", "mek_solve_batched", "mek_philox_uniform", "mek_select",
                  "mek_residual", "mek_gram"]:
         assert want in names
 
@@ -69,6 +69,7 @@ def test_struct_layouts_match_c():
       F(mek_solve_opts, X_ref) F(mek_solve_opts, max_iters) F(mek_solve_opts, replay_len)
       F(mek_solve_opts, hist_cap) F(mek_solve_opts, inner_iters) F(mek_solve_opts, set_hist)
       F(mek_report, passes) F(mek_report, alpha) F(mek_plan_opts, r_in_lds)
+      F(mek_solve_opts, block_rows) F(mek_solve_opts, tau) F(mek_solve_opts, cols_hist)
       return 0;
     }
     """
