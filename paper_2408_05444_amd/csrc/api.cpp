@@ -199,15 +199,18 @@ struct Layout {
     int W, rpw, xpw, wpw;
     bool lds;
     bool a_lds;
+    bool x_lds;
     size_t lds_bytes;
 };
 
 int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+constexpr int kRowsPerWG = 8;   // target rows of R per work-group (automatic layout)
+
 // Team layout: how many work-groups share the solve and whether their rows
-// of R stay in LDS. Automatic choice: the fewest work-groups whose LDS can
-// hold all of R, but at least one per 32K residual entries (so each
-// work-group's pass stays short), capped by the number of CUs.
+// of R stay in LDS. Automatic choice: one work-group per kRowsPerWG rows of
+// R (at least as many as it takes for R to fit in LDS), capped by the CUs
+// available to the instance.
 int choose_layout(const mek_plan_s* P, size_t elem, int64_t nb, Layout* L) {
     const int64_t m = P->m, n = P->n, q = P->q;
     // The selection keeps at most kSelRows row norms per thread in registers,
@@ -223,25 +226,24 @@ int choose_layout(const mek_plan_s* P, size_t elem, int64_t nb, Layout* L) {
     auto fits = [&](int Wc) {
         const int rpw = ceil_div(m, Wc);
         const int Wr = ceil_div(m, rpw);
-        return solve_lds_bytes(rpw, (int)n, (int)q, ceil_div(q, Wr), ceil_div(n, Wr), elem, true) <=
-               budget;
+        return solve_lds_bytes(rpw, (int)n, (int)q, ceil_div(q, Wr), ceil_div(n, Wr), elem, true,
+                               Wr == 1) <= budget;
     };
     if (P->team_wgs > 0) {
         W = (int)std::min<int64_t>({(int64_t)P->team_wgs, (int64_t)cus, m});
         lds = (P->r_in_lds != 0) && fits(W);
         if (P->r_in_lds == 1 && !lds) return MEK_EUNSUPPORTED;
     } else {
-        const int64_t work = m * n;
-        int Wt = (int)std::min<int64_t>(std::max<int64_t>(1, (work + 32767) / 32768), cus);
-        Wt = (int)std::min<int64_t>(Wt, m);
+        // About kRowsPerWG rows of R per work-group: measured on MI355X, the
+        // time per update falls as rows per work-group drop to about 8 and
+        // is flat below (the exchanges cost the same for any team size).
+        int Wt = (int)std::min<int64_t>(std::max<int64_t>(1, (m + kRowsPerWG - 1) / kRowsPerWG), cus);
         int Wl = -1;
         for (int Wc = 1; Wc <= std::min<int64_t>(cus, m); ++Wc)
             if (fits(Wc)) { Wl = Wc; break; }
         if (P->r_in_lds != 0 && Wl > 0) {
-            // With R in LDS, spread the rows over as many CUs as there are
-            // (fewer rows per work-group, even load): the LDS fits any W >= Wl.
+            // With R in LDS the LDS fits any W >= Wl.
             W = std::max(Wt, Wl);
-            if (work >= (int64_t)cus * 4096) W = std::max(W, (int)std::min<int64_t>(cus, m));
             lds = true;
         } else {
             if (P->r_in_lds == 1) return MEK_EUNSUPPORTED;
@@ -256,9 +258,13 @@ int choose_layout(const mek_plan_s* P, size_t elem, int64_t nb, Layout* L) {
     L->xpw = ceil_div(q, W);
     L->wpw = ceil_div(n, W);
     L->lds = lds && fits(W);
-    L->lds_bytes = solve_lds_bytes(L->rpw, (int)n, (int)q, L->xpw, L->wpw, elem, L->lds);
+    L->lds_bytes = solve_lds_bytes(L->rpw, (int)n, (int)q, L->xpw, L->wpw, elem, L->lds, W == 1);
     if (L->lds_bytes > budget || W > kMaxTeam) return MEK_EUNSUPPORTED;
-    // ||A_i||^2 of all rows goes to LDS too when there is room.
+    // With room left: this work-group's rows of X^T (updated every step),
+    // then ||A_i||^2 of all rows.
+    const size_t xb = (size_t)L->xpw * P->p * elem;
+    L->x_lds = L->lds_bytes + xb <= budget;
+    if (L->x_lds) L->lds_bytes += xb;
     L->a_lds = L->lds_bytes + solve_lds_bytes_a((int)m) <= budget;
     if (L->a_lds) L->lds_bytes += solve_lds_bytes_a((int)m);
     return MEK_OK;
@@ -388,6 +394,7 @@ int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double a
     static const bool phases = getenv("MEK_PHASES") && getenv("MEK_PHASES")[0] == '1';
     K.phase = phases ? w.phase : nullptr;
     K.a_in_lds = L.a_lds ? 1 : 0;
+    K.x_in_lds = L.x_lds ? 1 : 0;
     // Pause between polls of exchange words (tuning knob MEK_POLL_SLEEP).
     static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
     K.poll_sleep = poll_sleep;
@@ -424,8 +431,8 @@ int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double a
             const char* names[8] = {"reduce", "select", "row", "dots", "waitw", "xupd", "update", "end"};
             const int wg[3] = {0, L.W / 2, L.W - 1};
             for (int t = 0; t < (L.W > 1 ? 3 : 1); ++t) {
-                fprintf(stderr, "[mek phases] W=%d lds=%d a_lds=%d wg=%d iters=%lld us/update:", L.W,
-                        (int)L.lds, (int)L.a_lds, wg[t], iters0);
+                fprintf(stderr, "[mek phases] W=%d lds=%d a_lds=%d x_lds=%d wg=%d iters=%lld us/update:",
+                        L.W, (int)L.lds, (int)L.a_lds, (int)L.x_lds, wg[t], iters0);
                 for (int i = 0; i < 8; ++i)
                     fprintf(stderr, " %s=%.2f", names[i],
                             (double)h[t * 8 + i] / (rate_khz * 1e-3) / iters0);
@@ -610,15 +617,12 @@ int choose_layout_block2(const mek_plan_s* P, int s_cap, int t_cap, Layout* L) {
         lds = (P->r_in_lds != 0) && bytes(W, true) <= budget;
         if (P->r_in_lds == 1 && !lds) return MEK_EUNSUPPORTED;
     } else {
-        const int64_t work = m * n;
-        int Wt = (int)std::min<int64_t>(std::max<int64_t>(1, (work + 32767) / 32768), cus);
-        Wt = (int)std::min<int64_t>(Wt, m);
+        int Wt = (int)std::min<int64_t>(std::max<int64_t>(1, (m + kRowsPerWG - 1) / kRowsPerWG), cus);
         int Wl = -1;
         for (int Wc = 1; Wc <= std::min<int64_t>(cus, m); ++Wc)
             if (bytes(Wc, true) <= budget) { Wl = Wc; break; }
         if (P->r_in_lds != 0 && Wl > 0) {
             W = std::max(Wt, Wl);
-            if (work >= (int64_t)cus * 4096) W = std::max(W, (int)std::min<int64_t>(cus, m));
             lds = true;
         } else {
             if (P->r_in_lds == 1) return MEK_EUNSUPPORTED;
@@ -634,6 +638,7 @@ int choose_layout_block2(const mek_plan_s* P, int s_cap, int t_cap, Layout* L) {
     L->wpw = 0;
     L->lds = lds && bytes(W, true) <= budget;
     L->a_lds = false;
+    L->x_lds = false;
     L->lds_bytes = bytes(W, L->lds);
     if (L->lds_bytes > budget || W > kMaxTeam) return MEK_EUNSUPPORTED;
     return MEK_OK;
@@ -706,6 +711,11 @@ int run_block2(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double C
     K.r_in_lds = L.lds ? 1 : 0;
     static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
     K.poll_sleep = poll_sleep;
+    // MEK_PHASES=1: time the phases of each step on work-group 0 and print
+    // the averages to stderr (profiling aid).
+    static const bool phases = getenv("MEK_PHASES") && getenv("MEK_PHASES")[0] == '1';
+    K.phase = phases ? w.phase : nullptr;
+    if (phases) MEK_TRY(fill_zero_bytes(w.phase, 32 * 8, s));
     // Exchange words start with tag 0, which no step waits for.
     const size_t words = 2 * P->m + (size_t)std::max(1, P->cus) * P->n + P->n +
                          (size_t)kBlkCap * kBlkCap + kMaxTeam;
@@ -726,6 +736,19 @@ int run_block2(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double C
     float ms = 0.0f;
     if (st == MEK_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess && kernel_ms)
         *kernel_ms += (double)ms;
+    if (st == MEK_OK && phases && out->iters > 0) {
+        unsigned long long h[8];
+        int rate_khz = 100000;
+        (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, P->device);
+        if (hipMemcpy(h, w.phase, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess) {
+            const char* names[8] = {"rows", "cols", "select", "factor", "E", "W", "X", "R"};
+            fprintf(stderr, "[mek block phases] W=%d lds=%d steps=%lld us/step:", L.W, (int)L.lds,
+                    (long long)out->iters);
+            for (int i = 0; i < 8; ++i)
+                fprintf(stderr, " %s=%.2f", names[i], (double)h[i] / (rate_khz * 1e-3) / out->iters);
+            fprintf(stderr, " total_kernel=%.2f\n", ms * 1e3 / out->iters);
+        }
+    }
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     return st;

@@ -40,6 +40,11 @@ namespace mek {
 namespace {
 
 constexpr int kChunk = 4;   // rows of R per pass of the fused update/score loop
+constexpr int kXRows = 8;   // rows of X^T per pass of the X update
+
+// Optional phase timing (work-group 0, thread 0): wall-clock ticks per phase
+// of a step, summed over the solve.
+enum { kB2Rows, kB2Cols, kB2Select, kB2Factor, kB2E, kB2W, kB2X, kB2R, kB2Count };
 
 // Order-preserving key of a non-negative double; 0 is reserved for "not a
 // candidate".
@@ -53,6 +58,7 @@ struct Blk2Smem {
     double err_w[kWaves];
     double diag[2][kBlkCap];             // diagonals of the candidate Gram blocks
     double dpiv[2][kBlkCap];             // pivots of the kept candidates
+    double rd[2][kBlkCap];               // 1 / diagonal of the compacted factors
     unsigned long long ukey[2][kBlkCap]; // selected candidates, index order
     int uidx[2][kBlkCap];
     unsigned long long skey[2][kBlkCap]; // the same, rank order
@@ -125,28 +131,66 @@ __device__ __forceinline__ void select_top(const unsigned long long (&kr)[SR], i
     unsigned long long thR = 0ull, thC = 0ull;
     int eqR = 0, eqC = 0;
     if (radR || radC) {
+        // Smallest and largest candidate key of each kind: the radix passes
+        // start at the highest byte where they differ (the bytes above are
+        // common to every candidate), which also keeps the first histogram
+        // from piling every key into one bin.
+        double mm[4] = {-1.0, -INFINITY, -1.0, -INFINITY};
+#pragma unroll
+        for (int j = 0; j < SR; ++j) {
+            if (j < rc && kr[j] != 0ull) {
+                const double h = __longlong_as_double((long long)(kr[j] - 1ull));
+                mm[0] = fmax(mm[0], h);
+                mm[1] = fmax(mm[1], -h);
+            }
+            if (j < cc && kc[j] != 0ull) {
+                const double h = __longlong_as_double((long long)(kc[j] - 1ull));
+                mm[2] = fmax(mm[2], h);
+                mm[3] = fmax(mm[3], -h);
+            }
+        }
+        block_sums_maxes<0, 4>(mm, sm);
+        int startR = -1, startC = -1;
+        unsigned long long preR = 0ull, preC = 0ull;
+        if (radR) {
+            const unsigned long long kmax = score_key(mm[0]), kmin = score_key(-mm[1]);
+            for (int d = 7; d >= 0 && startR < 0; --d)
+                if ((kmax >> (8 * d)) != (kmin >> (8 * d))) startR = d;
+            preR = startR >= 7 ? 0ull : (kmax >> (8 * (startR + 1))) << (8 * (startR + 1));
+            if (startR < 0) preR = kmax;   // all candidate keys equal
+        }
+        if (radC) {
+            const unsigned long long kmax = score_key(mm[2]), kmin = score_key(-mm[3]);
+            for (int d = 7; d >= 0 && startC < 0; --d)
+                if ((kmax >> (8 * d)) != (kmin >> (8 * d))) startC = d;
+            preC = startC >= 7 ? 0ull : (kmax >> (8 * (startC + 1))) << (8 * (startC + 1));
+            if (startC < 0) preC = kmax;
+        }
         for (int e = tid; e < 1024; e += kThreads) hist[e] = 0;
         if (tid == 0) {
-            sm.prefix[0] = sm.prefix[1] = 0ull;
+            sm.prefix[0] = preR;
+            sm.prefix[1] = preC;
             sm.need[0] = min(capR, totR);
             sm.need[1] = min(capC, totC);
         }
         __syncthreads();
-        for (int d = 7; d >= 0; --d) {
+        const int dstart = max(startR, startC);
+        for (int d = dstart; d >= 0; --d) {
             int* H = hist + (d & 1) * 512;
             const int sh = 8 * d;
             const unsigned long long pR = sm.prefix[0], pC = sm.prefix[1];
+            const bool inR = radR && d <= startR, inC = radC && d <= startC;
 #pragma unroll
             for (int j = 0; j < SR; ++j) {
-                if (radR && j < rc && kr[j] != 0ull &&
+                if (inR && j < rc && kr[j] != 0ull &&
                     (d == 7 || (kr[j] >> (sh + 8)) == (pR >> (sh + 8))))
                     atomicAdd(&H[(int)((kr[j] >> sh) & 255ull)], 1);
-                if (radC && j < cc && kc[j] != 0ull &&
+                if (inC && j < cc && kc[j] != 0ull &&
                     (d == 7 || (kc[j] >> (sh + 8)) == (pC >> (sh + 8))))
                     atomicAdd(&H[256 + (int)((kc[j] >> sh) & 255ull)], 1);
             }
             __syncthreads();
-            if (wv < 2 && (wv == 0 ? radR : radC)) {
+            if (wv < 2 && (wv == 0 ? inR : inC)) {
                 // Lane l holds bins 255-4l .. 252-4l (descending); find the bin
                 // where the count of keys from the top reaches `need`.
                 const int* h = H + wv * 256;
@@ -273,7 +317,8 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
     xword* const px = reinterpret_cast<xword*>(P.errpart);
 
     // LDS: [own rows of R] [E / W, also radix histograms and the column
-    // slice] [L_I] [L_J] [z: kChunk x tcap].
+    // slice] [L_I] [L_J] [z: kChunk x tcap] [(A A^T)_{i, I}: kChunk x kBlkCap]
+    // [c of the X update: kXRows x kBlkCap].
     const size_t r_bytes = P.r_in_lds ? (((size_t)P.rpw * n * 8 + 15) & ~(size_t)15) : 0;
     double* Rl = reinterpret_cast<double*>(dyn_smem);
     unsigned char* ereg = dyn_smem + r_bytes;
@@ -284,6 +329,8 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
     double* LI = reinterpret_cast<double*>(ereg + e_bytes);
     double* LJ = LI + scap * scap;
     double* z = LJ + tcap * tcap;
+    double* gaI = z + kChunk * tcap;                   // kChunk x kBlkCap
+    double* cX = gaI + kChunk * kBlkCap;               // kXRows x kBlkCap
     double* Rown = P.r_in_lds ? Rl : P.R + (size_t)row0 * n;
 
     if (P.r_in_lds) {
@@ -304,16 +351,76 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         for (int c0 = 0; c0 < nrow; c0 += kChunk) {
             const int cr = min(kChunk, nrow - c0);
             if (upd) {
-                // z_i = (A A^T)_{i, I} W for the chunk's rows.
+                // z_i = (A A^T)_{i, I} W for the chunk's rows: the entries
+                // (A A^T)_{i, I} are loaded once, all in flight together.
+                const int nI = sm.nI;
+                for (int e = tid; e < cr * nI; e += kThreads) {
+                    const int ii = e / nI, x = e - ii * nI;
+                    gaI[ii * kBlkCap + x] = P.GA[(size_t)(row0 + c0 + ii) * m + sm.I[x]];
+                }
+                __syncthreads();
                 for (int e = tid; e < cr * nJ; e += kThreads) {
                     const int ii = e / nJ, y = e - ii * nJ;
-                    const double* ga = P.GA + (size_t)(row0 + c0 + ii) * m;
-                    double acc = 0.0;
-                    for (int x = 0; x < sm.nI; ++x) acc += ga[sm.I[x]] * E[x * ldE + y];
-                    z[ii * tcap + y] = acc;
+                    double a0 = 0.0, a1 = 0.0;
+                    int x = 0;
+                    for (; x + 1 < nI; x += 2) {
+                        a0 += gaI[ii * kBlkCap + x] * E[x * ldE + y];
+                        a1 += gaI[ii * kBlkCap + x + 1] * E[(x + 1) * ldE + y];
+                    }
+                    if (x < nI) a0 += gaI[ii * kBlkCap + x] * E[x * ldE + y];
+                    z[ii * tcap + y] = a0 + a1;
                 }
                 __syncthreads();
             }
+            if (upd) {
+                // R_i -= z_i (B^T B)_{J,:}: columns in groups of 4 per thread,
+                // so each z value read from LDS serves four columns.
+#pragma unroll
+                for (int u0 = 0; u0 < SR; u0 += 4) {
+                    double acc[4][kChunk];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int ii = 0; ii < kChunk; ++ii) acc[u][ii] = 0.0;
+                    // Rows J_y of B^T B, 8 at a time with every load issued
+                    // before the multiply-adds that use them.
+                    for (int y0 = 0; y0 < nJ; y0 += 8) {
+                        double gb[8][4];
+#pragma unroll
+                        for (int yy = 0; yy < 8; ++yy) {
+                            const int y = y0 + yy;
+                            const double* gbr = P.GB + (size_t)sm.J[y < nJ ? y : 0] * n;
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int j = tid + (u0 + u) * kThreads;
+                                gb[yy][u] = (y < nJ && u0 + u < SR && j < n) ? gbr[j] : 0.0;
+                            }
+                        }
+#pragma unroll
+                        for (int yy = 0; yy < 8; ++yy) {
+                            if (y0 + yy < nJ) {
+#pragma unroll
+                                for (int ii = 0; ii < kChunk; ++ii) {
+                                    const double zv = z[ii * tcap + y0 + yy];
+#pragma unroll
+                                    for (int u = 0; u < 4; ++u) acc[u][ii] += zv * gb[yy][u];
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int j = tid + (u0 + u) * kThreads;
+                        if (u0 + u < SR && j < n) {
+#pragma unroll
+                            for (int ii = 0; ii < kChunk; ++ii)
+                                if (ii < cr) Rown[(size_t)(c0 + ii) * n + j] -= acc[u][ii];
+                        }
+                    }
+                }
+            }
+            // Norms, row maxima and column maxima of omega over the chunk's
+            // rows (the same thread's columns, so no barrier is needed).
             double aa[kChunk];
 #pragma unroll
             for (int ii = 0; ii < kChunk; ++ii) aa[ii] = (ii < cr) ? P.a[row0 + c0 + ii] : 0.0;
@@ -323,59 +430,26 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
                 v[ii] = 0.0;            // ||R_i||^2 partial
                 v[kChunk + ii] = 0.0;   // max_j omega_ij partial
             }
-            // Columns in groups of 4 per thread: each z value read from LDS
-            // serves the group's four columns.
 #pragma unroll
-            for (int u0 = 0; u0 < SR; u0 += 4) {
-                double acc[4][kChunk];
+            for (int u = 0; u < SR; ++u) {
+                const int j = tid + u * kThreads;
+                if (j < n) {
+                    const double bj = P.b[j];
+                    double cmu = cm[u];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int ii = 0; ii < kChunk; ++ii) acc[u][ii] = 0.0;
-                if (upd) {
-#pragma unroll 2
-                    for (int y = 0; y < nJ; ++y) {
-                        const double* gbr = P.GB + (size_t)sm.J[y] * n;
-                        double gb[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int j = tid + (u0 + u) * kThreads;
-                            gb[u] = (u0 + u < SR && j < n) ? gbr[j] : 0.0;
-                        }
-#pragma unroll
-                        for (int ii = 0; ii < kChunk; ++ii) {
-                            const double zv = z[ii * tcap + y];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) acc[u][ii] += zv * gb[u];
-                        }
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int j = tid + (u0 + u) * kThreads;
-                    if (u0 + u < SR && j < n) {
-                        const double bj = P.b[j];
-                        double cmu = cm[u0 + u < SR ? u0 + u : 0];
-#pragma unroll
-                        for (int ii = 0; ii < kChunk; ++ii) {
-                            if (ii < cr) {
-                                double* rp = Rown + (size_t)(c0 + ii) * n + j;
-                                double val = *rp;
-                                if (upd) {
-                                    val -= acc[u][ii];
-                                    *rp = val;
-                                }
-                                const double sq = val * val;
-                                v[ii] += sq;
-                                if (aa[ii] > 0.0 && bj > 0.0) {
-                                    const double w = sq / (aa[ii] * bj);
-                                    v[kChunk + ii] = fmax(v[kChunk + ii], w);
-                                    cmu = fmax(cmu, w);
-                                }
+                    for (int ii = 0; ii < kChunk; ++ii) {
+                        if (ii < cr) {
+                            const double val = Rown[(size_t)(c0 + ii) * n + j];
+                            const double sq = val * val;
+                            v[ii] += sq;
+                            if (aa[ii] > 0.0 && bj > 0.0) {
+                                const double w = sq / (aa[ii] * bj);
+                                v[kChunk + ii] = fmax(v[kChunk + ii], w);
+                                cmu = fmax(cmu, w);
                             }
                         }
-                        if (u0 + u < SR) cm[u0 + u] = cmu;
                     }
+                    cm[u] = cmu;
                 }
             }
             block_sums_maxes<kChunk, kChunk>(v, sm);
@@ -393,35 +467,64 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         }
     };
 
-    // X^T rows of this work-group: X^T[l, :] += sum_x c_x A_{I_x, :} with
-    // c_x = sum_y W[x][y] B[l][J_y]; returns nothing, leaves the error
-    // partial of the updated rows in sm.err_w (one per wave).
+    // X^T rows of this work-group, kXRows at a time:
+    //   c[l][x] = sum_y W[x][y] B[l][J_y] (LDS), then
+    //   X^T[l, s] += sum_x c[l][x] A[I_x][s], a thread per column s,
+    // with the entries of A loaded 8 at a time, all in flight together.
+    // Leaves the squared-error partial of the updated rows in sm.err_w.
     auto update_x = [&](int nI, int nJ) {
         double ep = 0.0;
-        for (int l = wv; l < nx; l += kWaves) {
-            const int lr = xc0 + l;
-            double cx_ = 0.0;
-            if (lane < nI) {
-                for (int y = 0; y < nJ; ++y) cx_ += E[lane * ldE + y] * P.B[(size_t)lr * n + sm.J[y]];
-            }
-            double* xr = P.Xt + (size_t)lr * p;
-            const double* xref = P.Xref_t ? P.Xref_t + (size_t)lr * p : nullptr;
-            for (int s0 = 0; s0 < p; s0 += kWave) {
-                const int s = s0 + lane;
-                double acc = 0.0;
-                for (int x = 0; x < nI; ++x) {
-                    const double c = readlane_d(cx_, x);
-                    if (s < p) acc += c * P.A[(size_t)sm.I[x] * p + s];
+        for (int l0 = 0; l0 < nx; l0 += kXRows) {
+            const int lc = min(kXRows, nx - l0);
+            for (int e = tid; e < lc * nI; e += kThreads) {
+                const int l = e / nI, x = e - l * nI;
+                const double* brow = P.B + (size_t)(xc0 + l0 + l) * n;
+                double a0 = 0.0, a1 = 0.0;
+                for (int y0 = 0; y0 < nJ; y0 += 8) {
+                    double bv[8];
+#pragma unroll
+                    for (int yy = 0; yy < 8; ++yy)
+                        bv[yy] = (y0 + yy < nJ) ? brow[sm.J[y0 + yy]] : 0.0;
+#pragma unroll
+                    for (int yy = 0; yy < 8; yy += 2) {
+                        if (y0 + yy < nJ) a0 += E[x * ldE + y0 + yy] * bv[yy];
+                        if (y0 + yy + 1 < nJ) a1 += E[x * ldE + y0 + yy + 1] * bv[yy + 1];
+                    }
                 }
-                if (s < p) {
-                    const double nv = xr[s] + acc;
-                    xr[s] = nv;
-                    if (xref) {
-                        const double d = nv - xref[s];
-                        ep += d * d;
+                cX[l * kBlkCap + x] = a0 + a1;
+            }
+            __syncthreads();
+            for (int s2 = tid; s2 < p; s2 += kThreads) {
+                double acc[kXRows];
+#pragma unroll
+                for (int l = 0; l < kXRows; ++l) acc[l] = 0.0;
+                for (int x0 = 0; x0 < nI; x0 += 8) {
+                    double av[8];
+#pragma unroll
+                    for (int xx = 0; xx < 8; ++xx)
+                        av[xx] = (x0 + xx < nI) ? P.A[(size_t)sm.I[x0 + xx] * p + s2] : 0.0;
+#pragma unroll
+                    for (int xx = 0; xx < 8; ++xx) {
+                        if (x0 + xx < nI) {
+#pragma unroll
+                            for (int l = 0; l < kXRows; ++l) acc[l] += cX[l * kBlkCap + x0 + xx] * av[xx];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int l = 0; l < kXRows; ++l) {
+                    if (l < lc) {
+                        const size_t off = (size_t)(xc0 + l0 + l) * p + s2;
+                        const double nv = P.Xt[off] + acc[l];
+                        P.Xt[off] = nv;
+                        if (P.Xref_t) {
+                            const double d = nv - P.Xref_t[off];
+                            ep += d * d;
+                        }
                     }
                 }
             }
+            __syncthreads();
         }
         ep = wave_sum(ep);
         if (lane == 0) sm.err_w[wv] = ep;
@@ -443,6 +546,17 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         if (tid == 0) xstore(&px[g], pack_word(v[0], seq_tag(0)));
     }
 
+    const bool timing = P.phase != nullptr && g == 0 && tid == 0;
+    unsigned long long ph[kB2Count] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long t_last = timing ? wall_clock64() : 0;
+#define B2_PHASE(id)                                                    \
+    do {                                                                \
+        if (timing) {                                                   \
+            const unsigned long long now_ = wall_clock64();             \
+            ph[id] += now_ - t_last;                                    \
+            t_last = now_;                                              \
+        }                                                               \
+    } while (0)
     const int cs = (max(m, n) + kThreads - 1) / kThreads;   // chunk per thread (<= SR)
     const int rb = min(m, tid * cs), rcnt = min(m, rb + cs) - rb;
     const int cb = min(n, tid * cs), ccnt = min(n, cb + cs) - cb;
@@ -515,6 +629,7 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         if (S == 0.0) { status = kExact; break; }
         if (!isfinite(S) || (P.diverge > 0.0 && S > P.diverge * S0)) { status = kEDiverged; break; }
         if (k >= P.max_iters) { status = kMaxIter; break; }
+        B2_PHASE(kB2Rows);
 
         // ---- C. Column maxima; selection of I and J.
         double gg[SR];
@@ -533,7 +648,9 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         }
         __syncthreads();   // every thread is past its use of `slice` (same LDS as hist)
         if (sm.fail) { ok = false; break; }
+        B2_PHASE(kB2Cols);
         select_top<SR>(kr, rb, rcnt, kc, cb, ccnt, scap, tcap, hist, sm);
+        B2_PHASE(kB2Select);
         const int nsR = sm.nsel[0], nsC = sm.nsel[1];
         // Gram blocks of the ranked candidates, then an in-place right-looking
         // Cholesky in rank order that skips dependent candidates.
@@ -550,6 +667,9 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
             sm.diag[1][tid - kWave] = P.GB[(size_t)sm.sidx[1][tid - kWave] * (n + 1)];
         __syncthreads();
         const int npiv = max(nsR, nsC);
+        // Thread t owns entries (t / 32 + 16 h, t % 32), h = 0, 1, of both
+        // Gram blocks (at most 32 x 32 each).
+        const int er0 = tid >> 5, ec = tid & 31;
         for (int c = 0; c < npiv; ++c) {
             // Every thread reads the pivot and takes the same decision.
             const bool doR = c < nsR, doC = c < nsC;
@@ -562,22 +682,24 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
                 if (doC) { sm.keep[1][c] = keepC; sm.dpiv[1][c] = dC; }
             }
             // Trailing update of the lower triangle below the pivot:
-            // G[c1][c2] -= G[c1][c] G[c2][c] / d for c < c2 <= c1.
-            const int lr = keepR ? nsR - c - 1 : 0, lc = keepC ? nsC - c - 1 : 0;
-            const int tr = lr * (lr + 1) / 2, tcn = lc * (lc + 1) / 2;
-            for (int e = tid; e < tr + tcn; e += kThreads) {
-                const bool isR = e < tr;
-                const int f = isR ? e : e - tr;
-                // f -> (r1, r2) with 0 <= r2 <= r1 in a lower triangle.
-                int r1 = (int)((sqrt(8.0 * f + 1.0) - 1.0) * 0.5);
-                while ((r1 + 1) * (r1 + 2) / 2 <= f) ++r1;
-                while (r1 * (r1 + 1) / 2 > f) --r1;
-                const int r2 = f - r1 * (r1 + 1) / 2;
-                const int c1 = c + 1 + r1, c2 = c + 1 + r2;
-                double* L = isR ? LI : LJ;
-                const int ld = isR ? scap : tcap;
-                const double d = isR ? dR : dC;
-                L[c1 * ld + c2] -= L[c1 * ld + c] * L[c2 * ld + c] / d;
+            // G[r][q] -= G[r][c] G[q][c] / d for c < q <= r.
+            if (keepR) {
+                const double rdR = 1.0 / dR;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = er0 + 16 * h;
+                    if (r < nsR && ec > c && ec <= r)
+                        LI[r * scap + ec] -= LI[r * scap + c] * LI[ec * scap + c] * rdR;
+                }
+            }
+            if (keepC) {
+                const double rdC = 1.0 / dC;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = er0 + 16 * h;
+                    if (r < nsC && ec > c && ec <= r)
+                        LJ[r * tcap + ec] -= LJ[r * tcap + c] * LJ[ec * tcap + c] * rdC;
+                }
             }
             __syncthreads();
         }
@@ -624,8 +746,14 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
                 LJ[x * tcap + y] = lw[u];
             }
             __syncthreads();
-            if (tid < nI) sm.I[tid] = sm.sidx[0][sm.I[tid]];
-            else if (tid >= kWave && tid < kWave + nJ) sm.J[tid - kWave] = sm.sidx[1][sm.J[tid - kWave]];
+            if (tid < nI) {
+                sm.I[tid] = sm.sidx[0][sm.I[tid]];
+                sm.rd[0][tid] = 1.0 / LI[tid * scap + tid];
+            } else if (tid >= kWave && tid < kWave + nJ) {
+                const int y = tid - kWave;
+                sm.J[y] = sm.sidx[1][sm.J[y]];
+                sm.rd[1][y] = 1.0 / LJ[y * tcap + y];
+            }
             __syncthreads();
         }
         last_nI = nI;
@@ -637,13 +765,23 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
             }
         }
         if (nI == 0 || nJ == 0) { status = kEInval; break; }
+        B2_PHASE(kB2Factor);
 
-        // ---- D. R_IJ from the owners of the rows in I.
-        for (int e = tid; e < nI * nJ; e += kThreads) {
-            const int x = e / nJ, y = e - x * nJ;
-            const int i = sm.I[x];
-            if (i >= row0 && i < row0 + nrow)
-                xstore(&ex[x * kBlkCap + y], pack_word(Rown[(size_t)(i - row0) * n + sm.J[y]], tag));
+        // ---- D. R_IJ from the owners of the rows in I. Every word of the
+        // s_cap x t_cap block is rewritten every step (zeros outside I x J;
+        // work-group 0 writes the rows past nI), so no word can keep a value
+        // from four steps back that carries the current 2-bit tag.
+        for (int e = tid; e < scap * tcap; e += kThreads) {
+            const int x = e / tcap, y = e - x * tcap;
+            if (x < nI) {
+                const int i = sm.I[x];
+                if (i >= row0 && i < row0 + nrow) {
+                    const double v = (y < nJ) ? Rown[(size_t)(i - row0) * n + sm.J[y]] : 0.0;
+                    xstore(&ex[x * kBlkCap + y], pack_word(v, tag));
+                }
+            } else if (g == 0) {
+                xstore(&ex[x * kBlkCap + y], pack_word(0.0, tag));
+            }
         }
         for (int e0 = tid; e0 < nI * nJ; e0 += kThreads * 2) {
             const xword* ptr[2];
@@ -665,38 +803,86 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         }
         __syncthreads();
         if (sm.fail) { ok = false; break; }
-        // W = (A_I A_I^T)^{-1} R_IJ (B_J^T B_J)^{-1}, in place in E: first the
-        // columns (lane y solves with L_I), then the rows (lane x with L_J).
-        if (wv == 0 && lane < nJ) {
-            const int y = lane;
-            for (int x = 0; x < nI; ++x) {
-                double v = E[x * ldE + y];
-                for (int x2 = 0; x2 < x; ++x2) v -= LI[x * scap + x2] * E[x2 * ldE + y];
-                E[x * ldE + y] = v / LI[x * scap + x];
+        B2_PHASE(kB2E);
+        // W = (A_I A_I^T)^{-1} R_IJ (B_J^T B_J)^{-1}, in place in E, by
+        // right-looking triangular solves over the whole block (one barrier
+        // per pivot): first L_I and L_I^T on the columns of E, then L_J and
+        // L_J^T on its rows. Entry (x, y) of E belongs to thread
+        // (x / 16 + ...), see below; rows are kept unscaled until the end of
+        // each sweep.
+        {
+            // Thread t handles entries (t / 32 + 16 h, t % 32) of E, h = 0, 1.
+            const int ex0 = tid >> 5, ey = tid & 31;
+            // L_I: forward (E[x'] -= L[x'][x] / L[x][x] * E[x] for x' > x).
+            for (int x = 0; x + 1 < nI; ++x) {
+                const double rx = sm.rd[0][x];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = ex0 + 16 * h;
+                    if (r > x && r < nI && ey < nJ)
+                        E[r * ldE + ey] -= LI[r * scap + x] * rx * E[x * ldE + ey];
+                }
+                __syncthreads();
             }
-            for (int x = nI - 1; x >= 0; --x) {
-                double v = E[x * ldE + y];
-                for (int x2 = x + 1; x2 < nI; ++x2) v -= LI[x2 * scap + x] * E[x2 * ldE + y];
-                E[x * ldE + y] = v / LI[x * scap + x];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = ex0 + 16 * h;
+                if (r < nI && ey < nJ) E[r * ldE + ey] *= sm.rd[0][r];
             }
+            __syncthreads();
+            // L_I^T: backward (E[x'] -= L[x][x'] / L[x][x] * E[x] for x' < x).
+            for (int x = nI - 1; x > 0; --x) {
+                const double rx = sm.rd[0][x];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = ex0 + 16 * h;
+                    if (r < x && ey < nJ) E[r * ldE + ey] -= LI[x * scap + r] * rx * E[x * ldE + ey];
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = ex0 + 16 * h;
+                if (r < nI && ey < nJ) E[r * ldE + ey] *= sm.rd[0][r];
+            }
+            __syncthreads();
+            // L_J on the rows: column y plays the role of row x above.
+            for (int y = 0; y + 1 < nJ; ++y) {
+                const double ry = sm.rd[1][y];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = ex0 + 16 * h;
+                    if (r < nI && ey > y && ey < nJ)
+                        E[r * ldE + ey] -= LJ[ey * tcap + y] * ry * E[r * ldE + y];
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = ex0 + 16 * h;
+                if (r < nI && ey < nJ) E[r * ldE + ey] *= sm.rd[1][ey];
+            }
+            __syncthreads();
+            for (int y = nJ - 1; y > 0; --y) {
+                const double ry = sm.rd[1][y];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = ex0 + 16 * h;
+                    if (r < nI && ey < y) E[r * ldE + ey] -= LJ[y * tcap + ey] * ry * E[r * ldE + y];
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = ex0 + 16 * h;
+                if (r < nI && ey < nJ) E[r * ldE + ey] *= sm.rd[1][ey];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (wv == 0 && lane < nI) {
-            const int x = lane;
-            for (int y = 0; y < nJ; ++y) {
-                double v = E[x * ldE + y];
-                for (int y2 = 0; y2 < y; ++y2) v -= LJ[y * tcap + y2] * E[x * ldE + y2];
-                E[x * ldE + y] = v / LJ[y * tcap + y];
-            }
-            for (int y = nJ - 1; y >= 0; --y) {
-                double v = E[x * ldE + y];
-                for (int y2 = y + 1; y2 < nJ; ++y2) v -= LJ[y2 * tcap + y] * E[x * ldE + y2];
-                E[x * ldE + y] = v / LJ[y * tcap + y];
-            }
-        }
-        __syncthreads();
         // ---- X and R updates; A of step k + 1.
+        B2_PHASE(kB2W);
         update_x(nI, nJ);
+        B2_PHASE(kB2X);
         const unsigned int ntag = seq_tag(k + 1);
         update_and_score(true, nJ, ntag);
         if (tid == 0) {
@@ -705,9 +891,13 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
             xstore(&px[g], pack_word(e, ntag));
         }
         __syncthreads();
+        B2_PHASE(kB2R);
         ++k;
     }
+#undef B2_PHASE
     if (sm.fail) status = kETimeout;
+    if (timing)
+        for (int i = 0; i < kB2Count; ++i) P.phase[i] += ph[i];
     if (g == 0 && tid == 0) {
         P.report->iters = k;
         P.report->status = status;
@@ -721,7 +911,8 @@ size_t block2_lds_bytes(int rpw, int n, int W, int s_cap, int t_cap, bool r_in_l
     const int ncs = (n + W - 1) / W;
     size_t b = r_in_lds ? (((size_t)rpw * n * 8 + 15) & ~(size_t)15) : 0;
     b += block2_ereg_bytes(s_cap, t_cap, ncs);
-    b += ((size_t)s_cap * s_cap + (size_t)t_cap * t_cap + (size_t)kChunk * t_cap) * 8;
+    b += ((size_t)s_cap * s_cap + (size_t)t_cap * t_cap + (size_t)kChunk * t_cap +
+          (size_t)kChunk * kBlkCap + (size_t)kXRows * kBlkCap) * 8;
     return b;
 }
 

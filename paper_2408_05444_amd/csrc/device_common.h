@@ -19,12 +19,14 @@ constexpr int kUTable = 128;      // Philox draws computed ahead, per refill
 
 // LDS doubles for dot-product partial sums: the larger of the two dot
 // batches of an update (xpw dots over n entries, wpw dots over q entries),
-// plus n more for w when the team is a single work-group.
-__host__ __device__ inline int dot_parts(int xpw, int n, int wpw, int q) {
+// plus n more for w when the team is a single work-group (`single`).
+__host__ __device__ inline int dot_parts(int xpw, int n, int wpw, int q, bool single) {
     const int seg = kDotUnroll * kWave;
     const int a = xpw * ((n + seg - 1) / seg), b = wpw * ((q + seg - 1) / seg);
-    return (a > b ? a : b) + n;
+    return (a > b ? a : b) + (single ? n : 0);
 }
+
+constexpr int kAPre = 8;          // entries of A_{i_k} per lane loaded ahead of the X update
 
 // ---------------------------------------------------------------------------
 // Wave-level reductions and scans on DPP row permutations (register-level

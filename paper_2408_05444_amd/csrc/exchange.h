@@ -24,9 +24,10 @@ __device__ __forceinline__ void xstore(U* p, U v) {
 }
 
 // ---------------------------------------------------------------------------
-// Tagged exchange words. Work-groups of a team hand each other four kinds of
-// values every update: row norms r_i, error partials, the selected row
-// R_{i_k} and the slices of w. Each value travels in one 64-bit word that
+// Tagged exchange words. Work-groups of a team hand each other a few kinds of
+// values every update (in the row solver: row norms r_i, error partials, the
+// selected row R_{i_k} and the slices of w). Each value travels in one 64-bit
+// word that
 // also carries a 2-bit sequence tag, so a reader polls the data itself
 // until the tags show the current update: the signal and the data arrive
 // together, and no team-wide barrier is needed. A double keeps the tag in its
@@ -36,11 +37,12 @@ __device__ __forceinline__ void xstore(U* p, U v) {
 // and read with agent-scope relaxed atomics (aligned 64-bit, so a reader
 // never sees half of a word).
 //
-// One buffer per kind suffices: every rewrite of a word is causally after
-// every work-group has read its previous contents (the next r needs every
-// slice of w, each slice of w needs the published row, and the next row
-// needs every r), so a reader waiting for tag t can only see tag t or the
-// tag of the update before.
+// One buffer per kind suffices when every rewrite of a word is causally after
+// every work-group has read its previous contents (row solver: the next r
+// needs every slice of w, a work-group publishes its slice of w only after
+// its own selection has read every r and it has the published row, and the
+// next row needs every r), so a reader waiting for tag t can only see tag t
+// or the tag of the update before.
 // ---------------------------------------------------------------------------
 typedef unsigned long long xword;
 

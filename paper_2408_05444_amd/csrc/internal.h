@@ -96,6 +96,7 @@ struct SolveParams {
     double S_target;             // > 0: also stop (OK) once ||R||_F^2 <= S_target
     unsigned long long* phase;   // optional: per-phase wall-clock ticks (3 timed work-groups)
     int a_in_lds;                // keep ||A_i||^2 for all rows in LDS
+    int x_in_lds;                // keep this work-group's rows of X^T in LDS
     int poll_sleep;              // s_sleep length between polls of exchange words
     // Batch: with slots set, nb teams of W work-groups, team b on instance
     // slots[b].id, whose R, X^T, X_ref^T, r, rowbuf, vbuf, wbuf, errpart,
@@ -150,6 +151,7 @@ struct Block2Params {
     int W, rpw, xpw;
     int r_in_lds;
     int poll_sleep;
+    unsigned long long* phase;   // optional: per-phase wall-clock ticks of work-group 0
 };
 
 // Bytes of the block kernel's LDS region shared by R_IJ / W, the radix
@@ -172,7 +174,8 @@ hipError_t launch_solve(const SolveParams<double>& P, bool r_in_lds, size_t lds_
                         hipStream_t s);
 hipError_t launch_solve(const SolveParams<float>& P, bool r_in_lds, size_t lds_bytes,
                         hipStream_t s);
-size_t solve_lds_bytes(int rpw, int n, int q, int xpw, int wpw, size_t elem, bool r_in_lds);
+size_t solve_lds_bytes(int rpw, int n, int q, int xpw, int wpw, size_t elem, bool r_in_lds,
+                       bool single);
 size_t solve_lds_budget();
 size_t solve_lds_bytes_a(int m);
 

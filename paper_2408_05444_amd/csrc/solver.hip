@@ -7,8 +7,8 @@
 //   - work-group g owns rows [g*rpw, (g+1)*rpw) of the residual R. When they
 //     fit, those rows live in LDS for the whole solve, so R never travels to
 //     HBM inside the loop; otherwise they stay in device memory.
-//   - it owns rows [g*xpw, ...) of X^T (columns of X) and entries
-//     [g*wpw, ...) of the vector w = (R_{i_k} B^T) B.
+//   - it owns rows [g*xpw, ...) of X^T (columns of X; in LDS when there is
+//     room) and entries [g*wpw, ...) of the vector w = (R_{i_k} B^T) B.
 // Per update k every work-group
 //   1. reads all row norms r_i = ||R_i||^2 and computes ||R||_F^2, the
 //      maximum ratio max_i r_i/||A_i||^2 and the stop test, then runs the
@@ -17,7 +17,7 @@
 //   2. takes the selected row R_{i_k} (published by its owner), computes its
 //      entries of v = R_{i_k} B^T and publishes them, updates its columns of
 //      X (Alg. 3's X^{k+1}) while the rest of v arrives, then computes and
-//      publishes its entries of w = v B;
+//      publishes its entries of w = v B (R_{i_k} B^T B in factored form);
 //   3. with all of w, updates its own rows
 //      R_i -= alpha/||A_i_k||^2 (A A^T)_{i,i_k} w (Alg. 3's R^{k+1}) and
 //      publishes their new norms, which start update k + 1.
@@ -305,17 +305,21 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     xword* const w_x = reinterpret_cast<xword*>(P.wbuf);
 
     // LDS: [own rows of R (LDS mode)] [n-vector staging] [v for own X rows]
-    // [dot-product partial sums] [row norms when the team is one work-group]
-    // [Philox draws of the next kUTable updates] [||A_i||^2, when P.a_in_lds].
+    // [dot-product partial sums (+ w when the team is one work-group)]
+    // [row norms when the team is one work-group] [Philox draws of the next
+    // kUTable updates] [||A_i||^2, when P.a_in_lds] [own rows of X^T, when
+    // P.x_in_lds].
     const size_t r_bytes = LDS ? (((size_t)P.rpw * n * sizeof(T) + 15) & ~(size_t)15) : 0;
     const size_t v_bytes = ((size_t)max(n, q) * sizeof(T) + 15) & ~(size_t)15;
     T* Rl = reinterpret_cast<T*>(dyn_smem);
     T* vec = reinterpret_cast<T*>(dyn_smem + r_bytes);
     double* vl = reinterpret_cast<double*>(dyn_smem + r_bytes + v_bytes);
     double* part = vl + P.xpw;
-    double* r_local = part + dot_parts(P.xpw, n, P.wpw, q);
+    const int wslot = dot_parts(P.xpw, n, P.wpw, q, false);
+    double* r_local = part + dot_parts(P.xpw, n, P.wpw, q, !team);
     double* u_tab = r_local + P.rpw;
     double* a_lds = u_tab + kUTable;
+    T* Xl = P.x_in_lds ? reinterpret_cast<T*>(a_lds + (P.a_in_lds ? m : 0)) : nullptr;
     T* Rown = LDS ? Rl : P.R + (size_t)row0 * n;
     if (P.a_in_lds)
         for (int i = tid; i < m; i += kThreads) a_lds[i] = P.a[i];
@@ -326,8 +330,13 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         const T* src = P.R + (size_t)row0 * n;
         const size_t tot = (size_t)nrow * n;
         for (size_t e = tid; e < tot; e += kThreads) Rl[e] = src[e];
-        __syncthreads();
     }
+    if (Xl) {
+        const T* src = P.Xt + (size_t)xc0 * p;
+        const size_t tot = (size_t)nx * p;
+        for (size_t e = tid; e < tot; e += kThreads) Xl[e] = src[e];
+    }
+    __syncthreads();
     for (int ii = wv; ii < nrow; ii += kWaves) {
         const T* rp = Rown + (size_t)ii * n;
         double acc = 0.0;
@@ -346,7 +355,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         if (P.Xref_t) {
             const size_t base = (size_t)xc0 * p, total = (size_t)nx * p;
             for (size_t e = tid; e < total; e += kThreads) {
-                const double d = (double)P.Xt[base + e] - P.Xref_t[base + e];
+                const double d = (double)(Xl ? Xl[e] : P.Xt[base + e]) - P.Xref_t[base + e];
                 ep += d * d;
             }
         }
@@ -444,6 +453,17 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             if (P.set_hist) P.set_hist[hk] = last_set;
         }
         const double c = P.alpha / asrc[ik];
+        // A_{i_k} for the X update, loaded now so that its latency hides
+        // behind the exchange of the row.
+        T apre[kAPre];
+        if (wv < nx) {
+            const T* arow = P.A + (size_t)ik * p;
+#pragma unroll
+            for (int u = 0; u < kAPre; ++u) {
+                const int s2 = lane + u * kWave;
+                apre[u] = (s2 < p) ? arow[s2] : (T)0;
+            }
+        }
         MEK_PHASE(kPhSelect);
 
         // ---- 2. The selected row: its owner publishes it, the others poll
@@ -482,17 +502,30 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
                       },
                       part);
         MEK_PHASE(kPhDots);
-        // X^T rows l: X^T[l, :] += (c A_{i_k, :}) v_l, one wave per row, with
-        // the squared error against the reference in the same pass. In a team
-        // this runs while the other slices of v are on their way.
+        // X^T rows l: X^T[l, :] += (c A_{i_k, :}) v_l, one wave per row (in
+        // LDS when there is room), with the squared error against the
+        // reference in the same pass. In a team this runs while the other
+        // slices of v are on their way.
         {
             const T* arow = P.A + (size_t)ik * p;
             double ep = 0.0;
             for (int l = wv; l < nx; l += kWaves) {
-                T* xr = P.Xt + (size_t)(xc0 + l) * p;
+                T* xr = Xl ? Xl + (size_t)l * p : P.Xt + (size_t)(xc0 + l) * p;
                 const double* rr_ = has_ref ? P.Xref_t + (size_t)(xc0 + l) * p : nullptr;
                 const T vlT = (T)vl[l];
-                for (int s2 = lane; s2 < p; s2 += kWave) {
+#pragma unroll
+                for (int u = 0; u < kAPre; ++u) {
+                    const int s2 = lane + u * kWave;
+                    if (s2 < p) {
+                        const T nv = xr[s2] + (T)(c * (double)apre[u]) * vlT;
+                        xr[s2] = nv;
+                        if (has_ref) {
+                            const double d = (double)nv - rr_[s2];
+                            ep += d * d;
+                        }
+                    }
+                }
+                for (int s2 = lane + kAPre * kWave; s2 < p; s2 += kWave) {
                     const T nv = xr[s2] + (T)(c * (double)arow[s2]) * vlT;
                     xr[s2] = nv;
                     if (has_ref) {
@@ -528,7 +561,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         block_dots<T>(vfull, q, nw, [&](int d) { return P.BT + (size_t)(wc0 + d) * q; },
                       [&](int d, double val) {
                           if (team) xstore(&w_x[wc0 + d], pack_word((T)val, tag));
-                          else part[dot_parts(P.xpw, n, P.wpw, q) - n + d] = val;
+                          else part[wslot + d] = val;
                       },
                       part);
         // w into the staging vector.
@@ -542,8 +575,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
                     if (u < cnt) vec[j0 + tid + u * kThreads] = tw[u];
             }
         } else {
-            const double* wl = part + dot_parts(P.xpw, n, P.wpw, q) - n;
-            for (int j = tid; j < n; j += kThreads) vec[j] = (T)wl[j];
+            for (int j = tid; j < n; j += kThreads) vec[j] = (T)part[wslot + j];
         }
         __syncthreads();
         if (s_fail) { ok = false; break; }
@@ -581,6 +613,11 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         ++k;
     }
     if (s_fail) status = kETimeout;
+    if (Xl) {
+        T* dst = P.Xt + (size_t)xc0 * p;
+        const size_t tot = (size_t)nx * p;
+        for (size_t e = tid; e < tot; e += kThreads) dst[e] = Xl[e];
+    }
     if (timing)
         for (int i = 0; i < kPhCount; ++i) P.phase[tslot * kPhCount + i] += ph[i];
     if (g == 0 && tid == 0) {
@@ -594,10 +631,11 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
 
 size_t solve_lds_budget() { return 160 * 1024 - 1024; }
 
-size_t solve_lds_bytes(int rpw, int n, int q, int xpw, int wpw, size_t elem, bool r_in_lds) {
+size_t solve_lds_bytes(int rpw, int n, int q, int xpw, int wpw, size_t elem, bool r_in_lds,
+                       bool single) {
     size_t b = r_in_lds ? (((size_t)rpw * n * elem + 15) & ~(size_t)15) : 0;
     b += ((size_t)(n > q ? n : q) * elem + 15) & ~(size_t)15;
-    b += (size_t)xpw * sizeof(double) + (size_t)dot_parts(xpw, n, wpw, q) * sizeof(double);
+    b += (size_t)xpw * sizeof(double) + (size_t)dot_parts(xpw, n, wpw, q, single) * sizeof(double);
     b += (size_t)rpw * sizeof(double);   // row norms of a one-work-group team
     return b + kUTable * sizeof(double); // Philox draws of the coming updates
 }

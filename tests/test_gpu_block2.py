@@ -63,6 +63,20 @@ def test_small_steps_match_oracle(s, t, theta):
     assert np.allclose(host(res.err_hist), ref.e_hist, rtol=1e-8, atol=0)
 
 
+@pytest.mark.parametrize("theta", [0.8, 0.95])
+def test_block_sizes_that_vary_between_steps(theta):
+    # With a high threshold the blocks change size from step to step, so the
+    # exchange of R_IJ reuses words left from earlier, larger blocks.
+    inst = workloads.ragged(seed=21)
+    K = 80
+    ref, res = _both(inst, 32, 32, theta, K, plan_kw=dict(team_wgs=8, r_in_lds=1),
+                     Xref=inst.X_star)
+    sizes = {(len(I), len(J)) for I, J in zip(res.rows_hist, res.cols_hist)}
+    assert len(sizes) > 3
+    _check(ref, res, K)
+    assert np.all(np.diff(host(res.err_hist)) <= 1e-12)   # projections never move away
+
+
 @pytest.mark.parametrize("team,lds", [(0, -1), (1, 0), (5, 1), (16, 1), (3, 0), (64, 0)])
 def test_ragged_team_layouts(team, lds):
     inst = workloads.ragged()

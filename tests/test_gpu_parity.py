@@ -106,7 +106,8 @@ def test_select_ties_and_flat_ratios():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("shape", [(1, 1, 1, 1), (63, 17, 9, 65), (130, 70, 52, 261),
-                                   (100, 40, 40, 100), (257, 3, 130, 66)])
+                                   (100, 40, 40, 100), (257, 3, 130, 66),
+                                   (2050, 40, 70, 2100)])   # last: the 128 x 128 tile kernel
 def test_residual_engine(shape):
     m, p, q, n = shape
     rng = np.random.default_rng(sum(shape))
@@ -116,7 +117,8 @@ def test_residual_engine(shape):
     assert np.max(np.abs(R - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
 
 
-@pytest.mark.parametrize("shape", [(1, 5), (7, 3), (70, 130), (129, 64), (300, 17)])
+@pytest.mark.parametrize("shape", [(1, 5), (7, 3), (70, 130), (129, 64), (300, 17),
+                                   (2050, 300), (300, 2050)])   # 128 x 128 tiles, both layouts
 def test_gram(shape):
     M = np.random.default_rng(shape[0]).standard_normal(shape)
     G1 = host(mek.mek_gram(cuda(M), False))
