@@ -381,6 +381,10 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     int status = kMaxIter, last_set = 0;
     bool ok = true;
     const bool has_ref = P.Xref_t != nullptr;
+    // When every wave owns at most one row of X^T and p <= kAPre * 64, the
+    // X update's operands from device memory (A_{i_k} and the wave's row of
+    // X_ref) are loaded right after the selection, into registers.
+    const bool ref_regs = has_ref && nx <= kWaves && p <= kAPre * kWave;
     while (ok) {
         const unsigned int tag = seq_tag(k);
         // Draws depend only on (seed, instance, k): every kUTable updates the
@@ -464,6 +468,14 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
                 apre[u] = (s2 < p) ? arow[s2] : (T)0;
             }
         }
+        double xref_r[kAPre];
+#pragma unroll
+        for (int u = 0; u < kAPre; ++u) {
+            const int s2 = lane + u * kWave;
+            xref_r[u] = (ref_regs && wv < nx && s2 < p) ? P.Xref_t[(size_t)(xc0 + wv) * p + s2] : 0.0;
+        }
+        // (A A^T)_{i_k, i} of the first row i each wave updates, likewise.
+        const T ga_pre = (wv < nrow) ? P.GA[(size_t)ik * m + row0 + wv] : (T)0;
         MEK_PHASE(kPhSelect);
 
         // ---- 2. The selected row: its owner publishes it, the others poll
@@ -520,7 +532,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
                         const T nv = xr[s2] + (T)(c * (double)apre[u]) * vlT;
                         xr[s2] = nv;
                         if (has_ref) {
-                            const double d = (double)nv - rr_[s2];
+                            const double d = (double)nv - (ref_regs ? xref_r[u] : rr_[s2]);
                             ep += d * d;
                         }
                     }
@@ -587,7 +599,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             const unsigned int ntag = seq_tag(k + 1);
             const T* garow = P.GA + (size_t)ik * m + row0;
             for (int ii = wv; ii < nrow; ii += kWaves) {
-                const T sc_i = (T)(c * (double)garow[ii]);
+                const T sc_i = (T)(c * (double)(ii == wv ? ga_pre : garow[ii]));
                 T* rp = Rown + (size_t)ii * n;
                 double acc = 0.0;
                 for (int j = lane; j < n; j += kWave) {
