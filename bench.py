@@ -32,21 +32,37 @@ def algorithmic_bytes_per_update(m, p, q, n, elem):
     return (2 * m * n + 2 * p * q + 2 * q * n + m + n + p) * elem
 
 
+KERNEL_SOURCES = ["paper_2408_05444_amd/csrc/solver.hip", "paper_2408_05444_amd/csrc/exchange.h",
+                  "paper_2408_05444_amd/csrc/device_common.h"]
+
+
+def kernel_source_digest():
+    """SHA-256 of the row solver's sources: its kernel file, the headers it is
+    built from, and its parameter structs (the text of internal.h from
+    `struct InstSlot` to the end of `struct SolveParams`)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    txt = open(os.path.join(ROOT, "paper_2408_05444_amd/csrc/internal.h")).read()
+    a = txt.index("struct InstSlot")
+    b = txt.index("};", txt.index("struct SolveParams")) + 2
+    h.update(txt[a:b].encode())
+    return h.hexdigest()
+
+
 def measured_traffic(team_wgs, iters):
     """HBM bytes per launch of the solve kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter record, each scaled by the same counter's
     reading on a copy kernel of known size. None when the kernel sources
     changed since the counters were taken, or the launch differs."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "solve_kernel_large_grbk_fp64_counters.json")
     try:
         rec = json.load(open(path))
-        h = hashlib.sha256()
-        for f in rec["source_files"]:
-            h.update(open(os.path.join(ROOT, f), "rb").read())
+        digest = kernel_source_digest()
     except (OSError, ValueError, KeyError):
         return None
-    if h.hexdigest() != rec["source_sha256"]:
+    if digest != rec["source_sha256"]:
         return None
     if rec["team_wgs"] != team_wgs or rec["updates_per_launch"] != iters:
         return None
@@ -56,6 +72,38 @@ def measured_traffic(team_wgs, iters):
 
 
 TS_BLOCK = 32   # block rows / columns of the two-sided form
+MFMA_F64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+
+
+def gemm_forms(mek, torch, A, B, Xs, C, reps=10):
+    """The FP64 MFMA GEMMs of the set-up and the residual engine at the
+    workload's sizes, timed with events on the stream they run on:
+    A A^T (2000 x 2000 x 500) and R = C - (A X) B (2000 x 500 x 500, then
+    2000 x 2000 x 500)."""
+    m, p = A.shape
+    q, n = B.shape
+    out = {}
+    cases = {
+        "gram_AAt": (lambda: mek.mek_gram(A, False), 2.0 * m * m * p),
+        "residual_C-AXB": (lambda: mek.mek_residual(A, Xs, B, C), 2.0 * (m * p * q + m * q * n)),
+    }
+    for name, (fn, flops) in cases.items():
+        fn()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        sec = ev0.elapsed_time(ev1) * 1e-3 / reps
+        tf = flops / sec / 1e12
+        # Each call validates its pointers and synchronises, so this time
+        # includes the call's own overhead: a lower bound on the kernels'
+        # rate (the kernel trace in profiles/ gives the kernels alone).
+        out[name] = {"ms_per_call": sec * 1e3, "tflops_incl_call": tf,
+                     "peak_tflops": MFMA_F64_PEAK_TFLOPS, "frac_incl_call": tf / MFMA_F64_PEAK_TFLOPS}
+    return out
 
 
 def blur_batch_forms(mek, workloads, torch):
@@ -128,6 +176,9 @@ def main():
     ap.add_argument("--variant", default="grbk")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--gemm-only", action="store_true",
+                    help="only time the FP64 MFMA GEMMs of the set-up and residual engine at the "
+                         "workload's sizes (for a kernel trace) and print them")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device once (a known-size kernel for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -156,6 +207,9 @@ def main():
     A, B, C, Xs = t(inst.A), t(inst.B), t(inst.C), t(inst.X_star)
     seed = 2408054440
     torch.cuda.synchronize()
+    if args.gemm_only:
+        print(json.dumps({"gemm_mfma_f64": gemm_forms(mek, torch, A, B, Xs, C)}), flush=True)
+        return
 
     def step(precision="fp64", tol=1e-6, max_iters=5_000_000):
         plan = mek.mek_plan_create(A, B, precision=precision)
@@ -238,6 +292,7 @@ def main():
                              "kernel_us_per_step": r.kernel_ms * 1e3 / max(r.iters, 1)}
         forms["blur3_batched"] = blur_batch_forms(mek, workloads, torch)
         line["forms"] = forms
+        line["gemm_mfma_f64"] = gemm_forms(mek, torch, A, B, Xs, C)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, seed)
     print(json.dumps(line), flush=True)

@@ -228,7 +228,9 @@ int mek_select(int variant, int64_t m, const double* r, const double* a, double 
 
 /* Residual engine: R = C - A X B for A (m x p), X (p x q), B (q x n),
  * C (m x n), all device double, computed as two FP64 MFMA GEMMs
- * (T = A X, then R = C - T B). R must not alias the inputs. Blocking. */
+ * (T = A X, then R = C - T B). R must not alias the inputs. Blocking. The
+ * temporary T is kept in a per-device buffer between calls (the largest
+ * m x q seen so far); calls from several threads are serialised. */
 int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, const double* X,
                  const double* B, const double* C, double* R, void* stream);
 

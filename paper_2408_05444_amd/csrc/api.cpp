@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mek.h"
@@ -451,6 +452,52 @@ int read_scalar(const double* dev, double* host, hipStream_t s) {
     return MEK_OK;
 }
 
+// Largest eigenvalue of the symmetric positive semidefinite q x q matrix G
+// (device) by repeated squaring: G_0 = G, G_{j+1} = G_j^2 / ||G_j||_F^2 on
+// the FP64 matrix cores, until G_j is numerically rank one (||G_j||_F^2
+// within 1e-13 of 1, at most 24 squarings: G^(2^24)); its column with the
+// largest diagonal entry is then the top eigenvector v, and the eigenvalue
+// is ||G v|| / ||v||. The error of that estimate is second order in the
+// part of v outside the top eigenspace. Returns the value on the host.
+int max_eig_by_squaring(const double* G, int q, double* lam, double* scal, double* red,
+                        hipStream_t s) {
+    double *buf = nullptr;
+    const size_t qq = (size_t)q * q;
+    MEK_TRY(hipMalloc((void**)&buf, (2 * qq + 2 * (size_t)q) * 8));
+    double* P0 = buf;
+    double* P1 = buf + qq;
+    double* v = buf + 2 * qq;
+    double* w = v + q;
+    int st = MEK_OK;
+    const double* cur = G;
+    for (int it = 0; it < 24 && st == MEK_OK; ++it) {
+        double f = 0.0;
+        if (sq_norm(cur, (long long)qq, scal, red, s) != hipSuccess) { st = MEK_EHIP; break; }
+        if ((st = read_scalar(scal, &f, s))) break;
+        if (!(f > 0.0) || !isfinite(f)) break;
+        if (it > 0 && fabs(f - 1.0) <= 1e-13) break;   // rank one: G_j^2 = G_j
+        double* nxt = (cur == P0) ? P1 : P0;
+        if (gemm_f64(q, q, q, 1.0 / f, cur, q, 1, cur, q, 1, 0.0, nullptr, 0, nxt, q, s) !=
+            hipSuccess) { st = MEK_EHIP; break; }
+        cur = nxt;
+    }
+    double vv = 0.0, ww = 0.0;
+    if (st == MEK_OK && diag_argmax_col(cur, q, v, s) != hipSuccess) st = MEK_EHIP;
+    if (st == MEK_OK &&
+        gemm_f64(q, 1, q, 1.0, G, q, 1, v, 1, 1, 0.0, nullptr, 0, w, 1, s) != hipSuccess)
+        st = MEK_EHIP;
+    if (st == MEK_OK && sq_norm(v, q, scal, red, s) != hipSuccess) st = MEK_EHIP;
+    if (st == MEK_OK) st = read_scalar(scal, &vv, s);
+    if (st == MEK_OK && sq_norm(w, q, scal, red, s) != hipSuccess) st = MEK_EHIP;
+    if (st == MEK_OK) st = read_scalar(scal, &ww, s);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (st) return st;
+    *lam = (vv > 0.0) ? sqrt(ww / vv) : 0.0;
+    return MEK_OK;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -538,14 +585,14 @@ int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n, c
         double* BBt = nullptr;
         if (alloc((void**)&BBt, (size_t)(q * q) * 8)) return fail(MEK_ENOMEM);
         hipError_t e = gemm_f64((int)q, (int)q, (int)n, 1.0, P->B, n, 1, P->B, 1, n, 0.0, nullptr, 0, BBt, q, s);
-        if (e == hipSuccess) e = power_iteration_max_eig(BBt, (int)q, w.scal + 1, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
+        st = (e == hipSuccess) ? max_eig_by_squaring(BBt, (int)q, &P->b2, w.scal + 1, w.red, s)
+                               : MEK_EHIP;
         (void)hipFree(BBt);
-        if (e != hipSuccess) return fail(MEK_EHIP);
+        if (st) return fail(st);
     } else {
-        if (power_iteration_max_eig(P->GB, (int)n, w.scal + 1, s)) return fail(MEK_EHIP);
+        if ((st = max_eig_by_squaring(P->GB, (int)n, &P->b2, w.scal + 1, w.red, s))) return fail(st);
     }
-    if ((st = read_scalar(w.scal + 1, &P->b2, s))) return fail(st);
     if (!(P->b2 > 0.0)) return fail(MEK_EINVAL);   // B is all zero
     P->alpha = (o.alpha > 0.0) ? o.alpha : 1.0 / P->b2;
     if (!(P->alpha < 2.0 / P->b2 * (1.0 + 1e-9))) return fail(MEK_EINVAL);
@@ -1080,13 +1127,31 @@ int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, co
         (st = check_dev(R, (size_t)(m * n) * 8)))
         return st;
     hipStream_t s = (hipStream_t)stream;
-    double* T = nullptr;
-    MEK_TRY(hipMalloc((void**)&T, (size_t)(m * q) * 8));
+    // The temporary A X (m x q) lives in a per-device buffer kept between
+    // calls (grown when a call needs more); calls are serialised on it.
+    static std::mutex mtx;
+    static double* tbuf[64] = {nullptr};
+    static size_t tbytes[64] = {0};
+    std::lock_guard<std::mutex> lock(mtx);
+    int dev = 0;
+    MEK_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return MEK_EUNSUPPORTED;
+    const size_t need = (size_t)(m * q) * 8;
+    if (tbytes[dev] < need) {
+        if (tbuf[dev]) {
+            MEK_TRY(hipDeviceSynchronize());
+            (void)hipFree(tbuf[dev]);
+            tbuf[dev] = nullptr;
+            tbytes[dev] = 0;
+        }
+        MEK_TRY(hipMalloc((void**)&tbuf[dev], need));
+        tbytes[dev] = need;
+    }
+    double* T = tbuf[dev];
     hipError_t e = gemm_f64((int)m, (int)q, (int)p, 1.0, A, p, 1, X, q, 1, 0.0, nullptr, 0, T, q, s);
     if (e == hipSuccess)
         e = gemm_f64((int)m, (int)n, (int)q, -1.0, T, q, 1, B, n, 1, 1.0, C, n, R, n, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(T);
     return hip_status(e);
 }
 

@@ -292,7 +292,7 @@ __device__ __forceinline__ void select_top(const unsigned long long (&kr)[SR], i
 
 }  // namespace
 
-template <int SR>
+template <int SR, bool LDS>
 __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     __shared__ Blk2Smem sm;
@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
     // LDS: [own rows of R] [E / W, also radix histograms and the column
     // slice] [L_I] [L_J] [z: kChunk x tcap] [(A A^T)_{i, I}: kChunk x kBlkCap]
     // [c of the X update: kXRows x kBlkCap].
-    const size_t r_bytes = P.r_in_lds ? (((size_t)P.rpw * n * 8 + 15) & ~(size_t)15) : 0;
+    const size_t r_bytes = LDS ? (((size_t)P.rpw * n * 8 + 15) & ~(size_t)15) : 0;
     double* Rl = reinterpret_cast<double*>(dyn_smem);
     unsigned char* ereg = dyn_smem + r_bytes;
     double* E = reinterpret_cast<double*>(ereg);
@@ -331,9 +331,11 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
     double* z = LJ + tcap * tcap;
     double* gaI = z + kChunk * tcap;                   // kChunk x kBlkCap
     double* cX = gaI + kChunk * kBlkCap;               // kXRows x kBlkCap
-    double* Rown = P.r_in_lds ? Rl : P.R + (size_t)row0 * n;
+    // Own rows of R: LDS or device memory, fixed at compile time so that
+    // every access is a plain LDS or global instruction.
+    double* Rown = LDS ? Rl : P.R + (size_t)row0 * n;
 
-    if (P.r_in_lds) {
+    if (LDS) {
         const double* src = P.R + (size_t)row0 * n;
         const size_t tot = (size_t)nrow * n;
         for (size_t e = tid; e < tot; e += kThreads) Rl[e] = src[e];
@@ -918,9 +920,9 @@ size_t block2_lds_bytes(int rpw, int n, int W, int s_cap, int t_cap, bool r_in_l
 
 size_t block2_lds_budget() { return 160 * 1024 - sizeof(Blk2Smem) - 256; }
 
-template <int SR>
+template <int SR, bool LDS>
 static hipError_t launch_b2(const Block2Params& P, size_t lds_bytes, hipStream_t s) {
-    auto kern = block2_kernel<SR>;
+    auto kern = block2_kernel<SR, LDS>;
     if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds_bytes) != hipSuccess)
         (void)hipGetLastError();
@@ -932,14 +934,19 @@ static hipError_t launch_b2(const Block2Params& P, size_t lds_bytes, hipStream_t
                                       (unsigned int)lds_bytes, s);
 }
 
-hipError_t launch_block2(const Block2Params& P, size_t lds_bytes, hipStream_t s) {
+template <bool LDS>
+static hipError_t launch_b2_sr(const Block2Params& P, size_t lds_bytes, hipStream_t s) {
     switch (sel_rows_for(P.m > P.n ? P.m : P.n)) {
-        case 1: return launch_b2<1>(P, lds_bytes, s);
-        case 2: return launch_b2<2>(P, lds_bytes, s);
-        case 4: return launch_b2<4>(P, lds_bytes, s);
-        case 8: return launch_b2<8>(P, lds_bytes, s);
-        default: return launch_b2<16>(P, lds_bytes, s);
+        case 1: return launch_b2<1, LDS>(P, lds_bytes, s);
+        case 2: return launch_b2<2, LDS>(P, lds_bytes, s);
+        case 4: return launch_b2<4, LDS>(P, lds_bytes, s);
+        case 8: return launch_b2<8, LDS>(P, lds_bytes, s);
+        default: return launch_b2<16, LDS>(P, lds_bytes, s);
     }
+}
+
+hipError_t launch_block2(const Block2Params& P, size_t lds_bytes, hipStream_t s) {
+    return P.r_in_lds ? launch_b2_sr<true>(P, lds_bytes, s) : launch_b2_sr<false>(P, lds_bytes, s);
 }
 
 }  // namespace mek

@@ -119,16 +119,18 @@ gemm_f64_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
 }
 
 // Large-tile variant for products that give every CU a tile: block tile
-// 128 x 128, 4 waves in a 2 x 2 grid of 64 x 64 wave tiles (4 x 4 MFMA tiles,
-// 16 accumulators per wave), K tile 16, two LDS buffers so that the next
-// K tile is stored while the current one is multiplied (one barrier per K
-// tile), and the K tile after that already in registers. LDS rows are
-// padded by 16 doubles so that the four k-rows a wave reads in one MFMA
-// step fall on disjoint halves of the 64 banks.
+// 128 x 128, 8 waves in a 2 x 4 grid of 64 x 32 wave tiles (4 x 2 MFMA tiles,
+// 8 accumulators per wave; two waves per SIMD, so one multiplies while the
+// other waits on memory), K tile 16, two LDS buffers so that the next K tile
+// is stored while the current one is multiplied (one barrier per K tile),
+// and the K tile after that already in registers. LDS rows are padded by 16
+// doubles so that the four k-rows a wave reads in one MFMA step fall on
+// disjoint halves of the 64 banks.
 constexpr int kBT = 128;
 constexpr int kBPad = 16;
+constexpr int kBThreads = 512;
 
-__global__ void __launch_bounds__(kGThreads)
+__global__ void __launch_bounds__(kBThreads)
 gemm_f64_big_kernel(int M, int N, int K, double alpha, const double* __restrict__ A, long long a_i,
                     long long a_k, const double* __restrict__ B, long long b_k, long long b_j,
                     double beta, const double* C, long long ldc, double* D, long long ldd) {
@@ -137,18 +139,18 @@ gemm_f64_big_kernel(int M, int N, int K, double alpha, const double* __restrict_
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave >> 2, wc = wave & 3;   // 64-row x 32-column wave tile
     const int tile_i = blockIdx.y * kBT, tile_j = blockIdx.x * kBT;
     const bool a_k_fast = (a_k == 1);
     const bool b_j_fast = (b_j == 1);
 
-    // 2048 elements of each operand tile, 8 per thread, with the operand's
+    // 2048 elements of each operand tile, 4 per thread, with the operand's
     // unit-stride dimension fastest across threads.
-    double ra[8], rb[8];
+    double ra[4], rb[4];
     auto load_tiles = [&](int k0) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const int e = tid + s * kGThreads;
+        for (int s = 0; s < 4; ++s) {
+            const int e = tid + s * kBThreads;
             int ii, kk;
             if (a_k_fast) { ii = e / kGK; kk = e % kGK; }
             else { kk = e / kBT; ii = e % kBT; }
@@ -163,8 +165,8 @@ gemm_f64_big_kernel(int M, int N, int K, double alpha, const double* __restrict_
     };
     auto store_tiles = [&](int buf) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const int e = tid + s * kGThreads;
+        for (int s = 0; s < 4; ++s) {
+            const int e = tid + s * kBThreads;
             int ii, kk;
             if (a_k_fast) { ii = e / kGK; kk = e % kGK; }
             else { kk = e / kBT; ii = e % kBT; }
@@ -176,11 +178,11 @@ gemm_f64_big_kernel(int M, int N, int K, double alpha, const double* __restrict_
         }
     };
 
-    double4_t acc[4][4];
+    double4_t acc[4][2];
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < 2; ++y) acc[x][y] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
     const int l16 = lane & 15, lq = lane >> 4;
     const int nk = (K + kGK - 1) / kGK;
@@ -193,15 +195,15 @@ gemm_f64_big_kernel(int M, int N, int K, double alpha, const double* __restrict_
         // Multiply the current buffer.
 #pragma unroll
         for (int ks = 0; ks < kGK; ks += 4) {
-            double af[4], bf[4];
+            double af[4], bf[2];
 #pragma unroll
             for (int x = 0; x < 4; ++x) af[x] = As[cur][ks + lq][wr * 64 + x * 16 + l16];
 #pragma unroll
-            for (int y = 0; y < 4; ++y) bf[y] = Bs[cur][ks + lq][wc * 64 + y * 16 + l16];
+            for (int y = 0; y < 2; ++y) bf[y] = Bs[cur][ks + lq][wc * 32 + y * 16 + l16];
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
-                for (int y = 0; y < 4; ++y)
+                for (int y = 0; y < 2; ++y)
                     acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
         }
         // Store the next tile into the other buffer (last read one K tile
@@ -216,11 +218,11 @@ gemm_f64_big_kernel(int M, int N, int K, double alpha, const double* __restrict_
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+        for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int gi = tile_i + wr * 64 + x * 16 + lq + 4 * j;
-                const int gj = tile_j + wc * 64 + y * 16 + l16;
+                const int gj = tile_j + wc * 32 + y * 16 + l16;
                 if (gi < M && gj < N) {
                     double v = alpha * acc[x][y][j];
                     if (beta != 0.0) v += beta * C[(long long)gi * ldc + gj];
@@ -239,7 +241,7 @@ hipError_t gemm_f64(int M, int N, int K, double alpha, const double* A, long lon
     const long long big_tiles = (long long)((M + kBT - 1) / kBT) * ((N + kBT - 1) / kBT);
     if (big_tiles >= cus) {
         dim3 grid((N + kBT - 1) / kBT, (M + kBT - 1) / kBT);
-        hipLaunchKernelGGL(gemm_f64_big_kernel, grid, dim3(kGThreads), 0, s, M, N, K, alpha, A,
+        hipLaunchKernelGGL(gemm_f64_big_kernel, grid, dim3(kBThreads), 0, s, M, N, K, alpha, A,
                            a_i, a_k, B, b_k, b_j, beta, C, ldc, D, ldd);
         return hipGetLastError();
     }

@@ -267,6 +267,44 @@ power_kernel(const double* __restrict__ G, int q, double* out, double* vbuf) {
     if (threadIdx.x == 0) *out = lam;
 }
 
+// Column of the q x q symmetric matrix G with the largest diagonal entry
+// (lowest index on ties), copied to v; one work-group.
+__global__ void __launch_bounds__(kThreads, 1)
+diag_argmax_col_kernel(const double* __restrict__ G, int q, double* v) {
+    __shared__ double bv[kWaves];
+    __shared__ int bi[kWaves];
+    __shared__ int best;
+    double mv = -1.0;
+    int mi = 0x7fffffff;
+    for (int i = threadIdx.x; i < q; i += kThreads) {
+        const double d = G[(size_t)i * q + i];
+        if (d > mv) { mv = d; mi = i; }
+    }
+    // Wave, then block: largest value, lowest index among equal values.
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(mv, off);
+        const int oi = __shfl_xor(mi, off);
+        if (ov > mv || (ov == mv && oi < mi)) { mv = ov; mi = oi; }
+    }
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    if (lane == 0) { bv[wv] = mv; bi[wv] = mi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = bv[0];
+        int ib = bi[0];
+        for (int w = 1; w < kWaves; ++w)
+            if (bv[w] > b || (bv[w] == b && bi[w] < ib)) { b = bv[w]; ib = bi[w]; }
+        best = ib < q ? ib : 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q; i += kThreads) v[i] = G[(size_t)best * q + i];
+}
+
+hipError_t diag_argmax_col(const double* G, int q, double* v, hipStream_t s) {
+    hipLaunchKernelGGL(diag_argmax_col_kernel, dim3(1), dim3(kThreads), 0, s, G, q, v);
+    return hipGetLastError();
+}
+
 hipError_t power_iteration_max_eig(const double* G, int q, double* out, hipStream_t s) {
     double* vbuf = nullptr;
     hipError_t e = hipMallocAsync((void**)&vbuf, sizeof(double) * 2 * (size_t)q, s);

@@ -152,6 +152,26 @@ def _both(inst, variant, theta, K, seed, plan_kw=None, X0=None, **kw):
     return ref, res
 
 
+@pytest.mark.parametrize("case", ["wide_B", "tall_B", "blur"])
+def test_plan_alpha_is_inverse_spectral_norm(case):
+    # alpha = 1/||B||_2^2 (Sec. 5) from the plan, against the SVD. The blur
+    # matrix has a cluster of singular values at the top (slow for power
+    # iteration); the estimate lies inside that cluster.
+    rng = np.random.default_rng(77)
+    if case == "wide_B":
+        B = rng.standard_normal((60, 300))
+    elif case == "tall_B":
+        B = rng.standard_normal((300, 60))
+    else:
+        B = workloads.blur_toeplitz(64, 1.0).T.copy()
+    A = rng.standard_normal((50, B.shape[0]))
+    plan = mek.mek_plan_create(cuda(A), cuda(B))
+    _, _, _, alpha = mek.mek_plan_query(plan)
+    ref = oracle.spectral_alpha(B)
+    assert alpha == pytest.approx(ref, rel=1e-12 if case != "blur" else 1e-5)
+    assert alpha >= ref * (1 - 1e-12)       # never beyond 1/sigma_max^2 by more than rounding
+
+
 @pytest.mark.parametrize("variant,theta", VARIANTS)
 def test_small_trajectory_matches_oracle(variant, theta):
     inst = workloads.small()
