@@ -41,7 +41,7 @@ struct Workspace {
     DevReport* report = nullptr;
     InstSlot* slots = nullptr;
     // Shared scratch.
-    double* T64 = nullptr;     // m x q, GEMM temporary A X
+    double* T64 = nullptr;     // per instance m x q, GEMM temporary A X
     double* scal = nullptr;    // 8 scalars
     double* red = nullptr;     // 256 partial sums of the reductions
     int* iscal = nullptr;      // 8 ints
@@ -152,7 +152,7 @@ int ensure_workspace(mek_plan_s* P, int64_t nb) {
     add(B * sizeof(TeamSync));
     add(B * sizeof(DevReport));
     add(B * sizeof(InstSlot));
-    add(m * q * 8);
+    add(B * m * q * 8);
     add(8 * 8);
     add(256 * 8);
     add(8 * 4);
@@ -179,7 +179,7 @@ int ensure_workspace(mek_plan_s* P, int64_t nb) {
     w.sync = carve<TeamSync>(cur, B);
     w.report = carve<DevReport>(cur, B);
     w.slots = carve<InstSlot>(cur, B);
-    w.T64 = carve<double>(cur, m * q);
+    w.T64 = carve<double>(cur, B * m * q);
     w.scal = carve<double>(cur, 8);
     w.red = carve<double>(cur, 256);
     w.iscal = carve<int>(cur, 8);
@@ -877,6 +877,17 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
         }
         return MEK_OK;
     };
+    // All instances at once (uniform batches share A and B): one launch per
+    // product for the whole batch.
+    auto residual_all_into_R64 = [&](const double* Xall) -> int {
+        if (nb == 1) return residual_into_R64(0, Xall);
+        if (!Xall) return copy_f64(C, nb * mn, w.R64, s) == hipSuccess ? MEK_OK : MEK_EHIP;
+        MEK_TRY(gemm_f64_batched((int)nb, (int)m, (int)q, (int)p, 1.0, P->A, p, 1, 0, Xall, q, 1,
+                                 pq, 0.0, nullptr, 0, 0, w.T64, q, m * q, s));
+        MEK_TRY(gemm_f64_batched((int)nb, (int)m, (int)n, (int)q, -1.0, w.T64, q, 1, m * q, P->B,
+                                 n, 1, 0, 1.0, C, n, mn, w.R64, n, mn, s));
+        return MEK_OK;
+    };
     auto slot_for = [&](int64_t b) {
         InstSlot sl;
         memset(&sl, 0, sizeof(sl));
@@ -894,8 +905,8 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
     double kms = 0.0;
     if (prec == MEK_FP64 || prec == MEK_FP32) {
         std::vector<InstSlot> slots(nb);
+        if ((st = residual_all_into_R64(X0))) return st;
         for (int64_t b = 0; b < nb; ++b) {
-            if ((st = residual_into_R64(b, X0 ? X0 + b * pq : nullptr))) return st;
             if (o->X_ref)
                 MEK_TRY(transpose_to<double>(o->X_ref + b * pq, (int)p, (int)q, w.Xref_t + b * pq, s));
             slots[b] = slot_for(b);
@@ -954,10 +965,13 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
         std::vector<DevReport> ir(nb);
         for (;;) {
             std::vector<InstSlot> slots;
+            const bool all_running = nb > 1 && std::all_of(running.begin(), running.end(),
+                                                           [](char c) { return c != 0; });
+            if (all_running && (st = residual_all_into_R64(w.Xacc))) return st;
             for (int64_t b = 0; b < nb; ++b) {
                 if (!running[b]) continue;
                 double* Xacc = w.Xacc + b * pq;
-                if ((st = residual_into_R64(b, Xacc))) return st;
+                if (!all_running && (st = residual_into_R64(b, Xacc))) return st;
                 double S = 0.0, err2 = NAN, err = NAN;
                 MEK_TRY(sq_norm(w.R64 + b * mn, m * n, w.scal + 4, w.red, s));
                 if ((st = read_scalar(w.scal + 4, &S, s))) return st;

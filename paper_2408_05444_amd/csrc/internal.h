@@ -192,6 +192,13 @@ hipError_t launch_philox(uint64_t seed, uint64_t inst, long long k0, long long c
 hipError_t gemm_f64(int M, int N, int K, double alpha, const double* A, long long a_i,
                     long long a_k, const double* B, long long b_k, long long b_j, double beta,
                     const double* C, long long ldc, double* D, long long ldd, hipStream_t s);
+// The same for nb instances in one launch: instance b reads A + b sA, B + b sB,
+// C + b sC and writes D + b sD (a stride of 0 shares the operand).
+hipError_t gemm_f64_batched(int nb, int M, int N, int K, double alpha, const double* A,
+                            long long a_i, long long a_k, long long sA, const double* B,
+                            long long b_k, long long b_j, long long sB, double beta,
+                            const double* C, long long ldc, long long sC, double* D,
+                            long long ldd, long long sD, hipStream_t s);
 
 // Utility kernels (util.hip).
 hipError_t row_sq_norms(const double* A, int m, int p, double* out, hipStream_t s);
