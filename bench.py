@@ -75,11 +75,12 @@ TS_BLOCK = 32   # block rows / columns of the two-sided form
 MFMA_F64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 
 
-def gemm_forms(mek, torch, A, B, Xs, C, reps=10):
+def gemm_forms(mek, torch, A, B, Xs, C, blur=None, reps=10):
     """The FP64 MFMA GEMMs of the set-up and the residual engine at the
     workload's sizes, timed with events on the stream they run on:
     A A^T (2000 x 2000 x 500) and R = C - (A X) B (2000 x 500 x 500, then
-    2000 x 2000 x 500)."""
+    2000 x 2000 x 500); with blur = (A, B, C, X) of the 3-channel image form,
+    also its residual as one batched launch per product (3 x 512^3 twice)."""
     m, p = A.shape
     q, n = B.shape
     out = {}
@@ -87,6 +88,12 @@ def gemm_forms(mek, torch, A, B, Xs, C, reps=10):
         "gram_AAt": (lambda: mek.mek_gram(A, False), 2.0 * m * m * p),
         "residual_C-AXB": (lambda: mek.mek_residual(A, Xs, B, C), 2.0 * (m * p * q + m * q * n)),
     }
+    if blur is not None:
+        A3, B3, C3, X3 = blur
+        nb, p3, q3 = X3.shape
+        m3, n3 = A3.shape[0], B3.shape[1]
+        cases["residual_blur3_batched"] = (lambda: mek.mek_residual_batched(A3, X3, B3, C3),
+                                           2.0 * nb * (m3 * p3 * q3 + m3 * q3 * n3))
     for name, (fn, flops) in cases.items():
         fn()
         torch.cuda.synchronize()
@@ -106,18 +113,22 @@ def gemm_forms(mek, torch, A, B, Xs, C, reps=10):
     return out
 
 
+def blur_tensors(workloads, torch):
+    """A, B (512 x 512 blur, shared), C and X* (3 x 512 x 512) on the GPU."""
+    chans = workloads.blurred_image(512, 3, 2.0, seed=4, noise_std=1e-3)
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    return (t(chans[0].A), t(chans[0].B), t(np.stack([c.C for c in chans])),
+            t(np.stack([c.X_star for c in chans])))
+
+
 def blur_batch_forms(mek, workloads, torch):
     """The image-restoration form: 3 channels of a 512 x 512 image, banded
     Gaussian blur (sigma 2, 9 taps, rows summing to 1) on both sides, noise
     std 1e-3, a fixed budget of 100 m updates per channel (rel. error 1e-6
     is out of reach at this conditioning). One batched launch per form; the
     mixed form is compared with the FP64 iterate under the same indices."""
-    chans = workloads.blurred_image(512, 3, 2.0, seed=4, noise_std=1e-3)
-    dev = torch.device("cuda:0")
-    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
-    A, B = t(chans[0].A), t(chans[0].B)
-    C = t(np.stack([c.C for c in chans]))
-    Xs = t(np.stack([c.X_star for c in chans]))
+    A, B, C, Xs = blur_tensors(workloads, torch)
     K = 100 * 512
     out = {"budget_per_channel": K, "channels": 3}
     ref = None
@@ -208,7 +219,9 @@ def main():
     seed = 2408054440
     torch.cuda.synchronize()
     if args.gemm_only:
-        print(json.dumps({"gemm_mfma_f64": gemm_forms(mek, torch, A, B, Xs, C)}), flush=True)
+        print(json.dumps({"gemm_mfma_f64": gemm_forms(mek, torch, A, B, Xs, C,
+                                                      blur=blur_tensors(workloads, torch))}),
+              flush=True)
         return
 
     def step(precision="fp64", tol=1e-6, max_iters=5_000_000):
@@ -292,7 +305,8 @@ def main():
                              "kernel_us_per_step": r.kernel_ms * 1e3 / max(r.iters, 1)}
         forms["blur3_batched"] = blur_batch_forms(mek, workloads, torch)
         line["forms"] = forms
-        line["gemm_mfma_f64"] = gemm_forms(mek, torch, A, B, Xs, C)
+        line["gemm_mfma_f64"] = gemm_forms(mek, torch, A, B, Xs, C,
+                                           blur=blur_tensors(workloads, torch))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, seed)
     print(json.dumps(line), flush=True)

@@ -226,13 +226,26 @@ int mek_select(int variant, int64_t m, const double* r, const double* a, double 
                double theta, uint64_t seed, uint64_t instance, int64_t k0, int64_t count,
                int32_t* idx, uint8_t* in_set, int32_t* set_list, double* stats, void* stream);
 
-/* Residual engine: R = C - A X B for A (m x p), X (p x q), B (q x n),
- * C (m x n), all device double, computed as two FP64 MFMA GEMMs
+/* Residual engine (the residual R^0 = C - A X^0 B with which Alg. 3 starts,
+ * also used by the refinement passes): R = C - A X B for A (m x p),
+ * X (p x q), B (q x n), C (m x n), all device double, computed as two FP64 MFMA GEMMs
  * (T = A X, then R = C - T B). R must not alias the inputs. Blocking. The
  * temporary T is kept in a per-device buffer between calls (the largest
  * m x q seen so far); calls from several threads are serialised. */
 int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, const double* X,
                  const double* B, const double* C, double* R, void* stream);
+
+/* The residual engine of Alg. 3's start for a uniform batch that shares A
+ * and B: for b < nb,
+ * R_b = C_b - (A X_b) B with X_b = X + b p q, C_b = C + b m n and
+ * R_b = R + b m n (all device double, row-major, instances contiguous).
+ * Two strided-batched launches, one per product. R must not overlap any
+ * input. Blocking; the temporaries share the per-device buffer of
+ * mek_residual (nb x m x q doubles). Errors: MEK_EINVAL for sizes <= 0, null
+ * or overlapping pointers; MEK_EHIP for host or unregistered pointers. */
+int mek_residual_batched(int64_t nb, int64_t m, int64_t p, int64_t q, int64_t n, const double* A,
+                         const double* X, const double* B, const double* C, double* R,
+                         void* stream);
 
 /* Gram products by the FP64 MFMA GEMM: G = M M^T (transpose_first = 0,
  * G rows x rows) or G = M^T M (transpose_first = 1, G cols x cols) for M

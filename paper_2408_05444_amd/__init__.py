@@ -101,6 +101,8 @@ def lib() -> ctypes.CDLL:
         L.mek_select.restype = ci
         L.mek_residual.argtypes = [i64, i64, i64, i64, vp, vp, vp, vp, vp, vp]
         L.mek_residual.restype = ci
+        L.mek_residual_batched.argtypes = [i64, i64, i64, i64, i64, vp, vp, vp, vp, vp, vp]
+        L.mek_residual_batched.restype = ci
         L.mek_gram.argtypes = [i64, i64, vp, ci, vp, vp]
         L.mek_gram.restype = ci
         _lib_handle = L
@@ -353,6 +355,19 @@ def mek_residual(A, X, B, C) -> torch.Tensor:
     _check(lib().mek_residual(m, p, q, n, _dev(A, name="A"), _dev(X, shape=(p, q), name="X"),
                               _dev(B, name="B"), _dev(C, shape=(m, n), name="C"), _dev(R),
                               _stream()), "mek_residual")
+    return R
+
+
+def mek_residual_batched(A, X, B, C) -> torch.Tensor:
+    """R_b = C_b - A X_b B for X (nb, p, q) and C (nb, m, n) sharing A, B."""
+    m, p = A.shape
+    q, n = B.shape
+    nb = X.shape[0]
+    R = torch.empty(nb, m, n, dtype=torch.float64, device=A.device)
+    _check(lib().mek_residual_batched(nb, m, p, q, n, _dev(A, name="A"),
+                                      _dev(X, shape=(nb, p, q), name="X"), _dev(B, name="B"),
+                                      _dev(C, shape=(nb, m, n), name="C"), _dev(R), _stream()),
+           "mek_residual_batched")
     return R
 
 

@@ -1128,21 +1128,30 @@ int mek_select(int variant, int64_t m, const double* r, const double* a, double 
     return hip_status(e);
 }
 
-int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, const double* X,
-                 const double* B, const double* C, double* R, void* stream) {
-    if (m <= 0 || p <= 0 || q <= 0 || n <= 0) return MEK_EINVAL;
-    if (m > INT32_MAX / 2 || p > INT32_MAX / 2 || q > INT32_MAX / 2 || n > INT32_MAX / 2) return MEK_EINVAL;
+int mek_residual_batched(int64_t nb, int64_t m, int64_t p, int64_t q, int64_t n, const double* A,
+                         const double* X, const double* B, const double* C, double* R,
+                         void* stream) {
+    if (nb <= 0 || m <= 0 || p <= 0 || q <= 0 || n <= 0) return MEK_EINVAL;
+    if (m > INT32_MAX / 2 || p > INT32_MAX / 2 || q > INT32_MAX / 2 || n > INT32_MAX / 2 ||
+        nb > INT32_MAX / 2)
+        return MEK_EINVAL;
     if (!A || !X || !B || !C || !R) return MEK_EINVAL;
-    if ((const double*)R == A || (const double*)R == X || (const double*)R == B || (const double*)R == C)
+    const size_t rb = (size_t)(nb * m * n) * 8;
+    auto overlaps = [&](const double* x, size_t bytes) {
+        const char *r0 = (const char*)R, *x0 = (const char*)x;
+        return r0 < x0 + bytes && x0 < r0 + rb;
+    };
+    if (overlaps(A, (size_t)(m * p) * 8) || overlaps(X, (size_t)(nb * p * q) * 8) ||
+        overlaps(B, (size_t)(q * n) * 8) || overlaps(C, rb))
         return MEK_EINVAL;
     int st;
-    if ((st = check_dev(A, (size_t)(m * p) * 8)) || (st = check_dev(X, (size_t)(p * q) * 8)) ||
-        (st = check_dev(B, (size_t)(q * n) * 8)) || (st = check_dev(C, (size_t)(m * n) * 8)) ||
-        (st = check_dev(R, (size_t)(m * n) * 8)))
+    if ((st = check_dev(A, (size_t)(m * p) * 8)) || (st = check_dev(X, (size_t)(nb * p * q) * 8)) ||
+        (st = check_dev(B, (size_t)(q * n) * 8)) || (st = check_dev(C, rb)) ||
+        (st = check_dev(R, rb)))
         return st;
     hipStream_t s = (hipStream_t)stream;
-    // The temporary A X (m x q) lives in a per-device buffer kept between
-    // calls (grown when a call needs more); calls are serialised on it.
+    // The temporaries A X_b (nb x m x q) live in a per-device buffer kept
+    // between calls (grown when a call needs more); calls are serialised on it.
     static std::mutex mtx;
     static double* tbuf[64] = {nullptr};
     static size_t tbytes[64] = {0};
@@ -1150,7 +1159,7 @@ int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, co
     int dev = 0;
     MEK_TRY(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return MEK_EUNSUPPORTED;
-    const size_t need = (size_t)(m * q) * 8;
+    const size_t need = (size_t)(nb * m * q) * 8;
     if (tbytes[dev] < need) {
         if (tbuf[dev]) {
             MEK_TRY(hipDeviceSynchronize());
@@ -1162,11 +1171,19 @@ int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, co
         tbytes[dev] = need;
     }
     double* T = tbuf[dev];
-    hipError_t e = gemm_f64((int)m, (int)q, (int)p, 1.0, A, p, 1, X, q, 1, 0.0, nullptr, 0, T, q, s);
+    const int b = (int)nb;
+    hipError_t e = gemm_f64_batched(b, (int)m, (int)q, (int)p, 1.0, A, p, 1, 0, X, q, 1, p * q,
+                                    0.0, nullptr, 0, 0, T, q, m * q, s);
     if (e == hipSuccess)
-        e = gemm_f64((int)m, (int)n, (int)q, -1.0, T, q, 1, B, n, 1, 1.0, C, n, R, n, s);
+        e = gemm_f64_batched(b, (int)m, (int)n, (int)q, -1.0, T, q, 1, m * q, B, n, 1, 0, 1.0, C, n,
+                             m * n, R, n, m * n, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return hip_status(e);
+}
+
+int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, const double* X,
+                 const double* B, const double* C, double* R, void* stream) {
+    return mek_residual_batched(1, m, p, q, n, A, X, B, C, R, stream);
 }
 
 int mek_gram(int64_t rows, int64_t cols, const double* M, int transpose_first, double* G,

@@ -26,14 +26,16 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 //
 // LDS layout: element (k, i) of a K tile sits at k * BM + (i ^ swz(k)). The
 // XOR keeps i inside its aligned 32-column group, moves it to the other
-// 16-column half when k is odd and permutes within the half by k / 2. With
-// 8-byte words in 32 slots per half-wave access this makes three access
-// sets conflict free: the MFMA read (4 consecutive k x 16 consecutive i),
-// the store of a unit-stride-in-i operand (64 consecutive i, one k) and the
-// store of a unit-stride-in-k operand (32 consecutive k x 2 i).
+// 16-column half when k is odd and permutes its low 4 bits by a value that
+// differs for any 16 consecutive k (and, with the half bit, for any 32).
+// With 8-byte words this makes three access sets conflict free whether LDS
+// serves 16 lanes over 16 word slots or 32 lanes over 32 slots per cycle:
+// the MFMA read (4 consecutive k x 16 consecutive i), the store of a
+// unit-stride-in-i operand (64 consecutive i, one k) and the store of a
+// unit-stride-in-k operand (32 consecutive k x 2 i).
 constexpr int kTK = 32;
 
-__device__ __forceinline__ int swz(int k) { return ((k & 1) << 4) | ((k >> 1) & 15); }
+__device__ __forceinline__ int swz(int k) { return ((k & 1) << 4) | ((k & 15) ^ ((k >> 4) & 1)); }
 
 // Blocks are dealt to the 8 XCDs round-robin by linear id. Give each XCD a
 // contiguous range of a grouped tile order (G tile rows, column by column)

@@ -219,7 +219,6 @@ hipError_t fill_zero_bytes(void* x, long long bytes, hipStream_t s);
 // out = a x + b y elementwise (out may alias x or y).
 hipError_t lincomb_f64(double a, const double* x, double b, const double* y, long long len,
                        double* out, hipStream_t s);
-hipError_t power_iteration_max_eig(const double* G, int q, double* out, hipStream_t s);
 hipError_t diag_argmax_col(const double* G, int q, double* v, hipStream_t s);
 
 }  // namespace mek

@@ -1,5 +1,5 @@
 // Small dense kernels around the solver: norms, transposes, conversions,
-// the active-row list and the power iteration for ||B||_2^2.
+// the active-row list and the column pick of the repeated squaring for ||B||_2^2.
 #include "internal.h"
 
 #include <math.h>
@@ -220,53 +220,6 @@ hipError_t lincomb_f64(double a, const double* x, double b, const double* y, lon
     return hipGetLastError();
 }
 
-// Largest eigenvalue of the symmetric positive semidefinite q x q matrix G by
-// power iteration with the Rayleigh quotient, one work-group. Thread i forms
-// (G v)_i from column i of G (equal to row i by symmetry), so the loads of a
-// wave are contiguous. Stops when the quotient changes by less than 1e-14
-// relative for 4 steps in a row, or after 20000 steps.
-__global__ void __launch_bounds__(kThreads, 1)
-power_kernel(const double* __restrict__ G, int q, double* out, double* vbuf) {
-    __shared__ BlockScratch sc;
-    // vbuf: 2 * q doubles of scratch (device memory).
-    double* v = vbuf;
-    double* w = vbuf + q;
-    for (int i = threadIdx.x; i < q; i += kThreads) v[i] = 1.0 + 0.125 * (double)(i % 7);
-    __syncthreads();
-    double nv[1] = {0.0};
-    for (int i = threadIdx.x; i < q; i += kThreads) nv[0] += v[i] * v[i];
-    block_sum<1>(nv, sc);
-    double inv = 1.0 / sqrt(nv[0]);
-    for (int i = threadIdx.x; i < q; i += kThreads) v[i] *= inv;
-    __syncthreads();
-    double lam = 0.0;
-    int stable = 0;
-    for (int it = 0; it < 20000 && stable < 4; ++it) {
-        double acc[2] = {0.0, 0.0};   // v.w and w.w
-        for (int i = threadIdx.x; i < q; i += kThreads) {
-            double s0 = 0.0, s1 = 0.0;
-            int j = 0;
-            for (; j + 1 < q; j += 2) {
-                s0 += G[(size_t)j * q + i] * v[j];
-                s1 += G[(size_t)(j + 1) * q + i] * v[j + 1];
-            }
-            if (j < q) s0 += G[(size_t)j * q + i] * v[j];
-            const double sum = s0 + s1;
-            w[i] = sum;
-            acc[0] += v[i] * sum;
-            acc[1] += sum * sum;
-        }
-        block_sum<2>(acc, sc);
-        const double nl = acc[0];
-        stable = (fabs(nl - lam) <= 1e-14 * fabs(nl)) ? stable + 1 : 0;
-        lam = nl;
-        const double invw = acc[1] > 0.0 ? 1.0 / sqrt(acc[1]) : 0.0;
-        for (int i = threadIdx.x; i < q; i += kThreads) v[i] = w[i] * invw;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = lam;
-}
-
 // Column of the q x q symmetric matrix G with the largest diagonal entry
 // (lowest index on ties), copied to v; one work-group.
 __global__ void __launch_bounds__(kThreads, 1)
@@ -303,16 +256,6 @@ diag_argmax_col_kernel(const double* __restrict__ G, int q, double* v) {
 hipError_t diag_argmax_col(const double* G, int q, double* v, hipStream_t s) {
     hipLaunchKernelGGL(diag_argmax_col_kernel, dim3(1), dim3(kThreads), 0, s, G, q, v);
     return hipGetLastError();
-}
-
-hipError_t power_iteration_max_eig(const double* G, int q, double* out, hipStream_t s) {
-    double* vbuf = nullptr;
-    hipError_t e = hipMallocAsync((void**)&vbuf, sizeof(double) * 2 * (size_t)q, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(power_kernel, dim3(1), dim3(kThreads), 0, s, G, q, out, vbuf);
-    e = hipGetLastError();
-    hipError_t f = hipFreeAsync(vbuf, s);
-    return e != hipSuccess ? e : f;
 }
 
 }  // namespace mek

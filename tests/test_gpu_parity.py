@@ -117,6 +117,25 @@ def test_residual_engine(shape):
     assert np.max(np.abs(R - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("nb,shape", [(3, (512, 512, 512, 512)), (2, (300, 70, 45, 650)),
+                                      (5, (17, 3, 40, 129)), (2, (2050, 40, 70, 2100)),
+                                      (2, (1500, 60, 50, 1500))])   # batch: 128-tiles, one: 64
+def test_residual_engine_batched(nb, shape):
+    # One launch per product for the whole batch: each instance equals the
+    # oracle residual, and is bit-identical to the single-instance call
+    # (the per-element accumulation order does not depend on the tile shape).
+    m, p, q, n = shape
+    rng = np.random.default_rng(nb + sum(shape))
+    A, B = rng.standard_normal((m, p)), rng.standard_normal((q, n))
+    X, C = rng.standard_normal((nb, p, q)), rng.standard_normal((nb, m, n))
+    R = host(mek.mek_residual_batched(cuda(A), cuda(X), cuda(B), cuda(C)))
+    for b in range(nb):
+        ref = oracle.residual(A, X[b], B, C[b])
+        assert np.max(np.abs(R[b] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+        one = host(mek.mek_residual(cuda(A), cuda(X[b]), cuda(B), cuda(C[b])))
+        assert np.array_equal(one, R[b])
+
+
 @pytest.mark.parametrize("shape", [(1, 5), (7, 3), (70, 130), (129, 64), (300, 17),
                                    (2050, 300), (300, 2050)])   # 128 x 128 tiles, both layouts
 def test_gram(shape):
