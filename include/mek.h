@@ -207,6 +207,28 @@ int mek_solve(mek_plan plan, const double* C, const double* X0, const mek_solve_
 int mek_solve_batched(mek_plan plan, int64_t batch, const double* C, const double* X0,
                       const mek_solve_opts* opts, double* X, mek_report* reports, void* stream);
 
+/* Ragged batch: solve A_b X_b B_b = C_b for b < batch, each instance with
+ * its own plan plans[b] (own sizes m_b, p_b, q_b, n_b; every plan distinct,
+ * all of one precision, FP64 or FP32, on one device), in one persistent
+ * launch. Each instance runs the iteration of Algs. 3-5 exactly as mek_solve
+ * would (same selection, sampling, update and stop rule); instance b draws
+ * under Philox key (seed, instance + b). The work-groups of the launch are
+ * shared out in proportion to each instance's per-update work (m_b n_b +
+ * p_b q_b), at most one per compute unit in all; residuals stay in device
+ * memory. plans, C, X0, X_ref and X are host arrays of batch entries;
+ * C[b] (m_b x n_b), X0[b] (p_b x q_b; X0 or an entry NULL means zero),
+ * X_ref[b] (p_b x q_b; needed by MEK_STOP_REL_ERR) and X[b] (p_b x q_b,
+ * output) are device pointers. opts is shared; opts->X_ref must be NULL
+ * (references come through X_ref); each history holds batch x hist_cap
+ * entries, instance b from b * hist_cap. Returns as mek_solve_batched.
+ * Errors: MEK_EINVAL for bad arguments, a repeated plan or mixed
+ * precisions; MEK_EUNSUPPORTED for MEK_MIXED plans, replay_idx, the
+ * two-sided variant or batch above the compute units. */
+int mek_solve_multi(int64_t batch, const mek_plan* plans, const double* const* C,
+                    const double* const* X0, const double* const* X_ref,
+                    const mek_solve_opts* opts, double* const* X, mek_report* reports,
+                    void* stream);
+
 /* ---- Unit entry points: the hot path's stages run on their own. ---- */
 
 /* out[j] = u_{k0+j} for j < count: the uniform draw of update k0+j,

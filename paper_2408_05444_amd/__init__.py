@@ -95,6 +95,9 @@ def lib() -> ctypes.CDLL:
         L.mek_solve_batched.argtypes = [vp, i64, vp, vp, ctypes.POINTER(mek_solve_opts), vp,
                                         ctypes.POINTER(mek_report), vp]
         L.mek_solve_batched.restype = ci
+        L.mek_solve_multi.argtypes = [i64, vp, vp, vp, vp, ctypes.POINTER(mek_solve_opts), vp,
+                                      vp, vp]
+        L.mek_solve_multi.restype = ci
         L.mek_philox_uniform.argtypes = [u64, u64, i64, i64, vp, vp]
         L.mek_philox_uniform.restype = ci
         L.mek_select.argtypes = [ci, i64, vp, vp, d, d, u64, u64, i64, i64, vp, vp, vp, vp, vp]
@@ -316,6 +319,43 @@ def mek_solve_batched(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = 
                                    _dev(X, shape=(nb, p, q), name="X"), reps, _stream())
     if raise_on_error and code < 0:
         raise MekError(code, "mek_solve_batched")
+    return int(code), [_result(X[b], reps[b].status, reps[b], hists, b, hist_cap)
+                       for b in range(nb)]
+
+
+def _ptr_array(tensors, shapes, name):
+    """Host array of device pointers (NULL for None entries)."""
+    arr = (ctypes.c_void_p * len(tensors))()
+    for b, (t, shp) in enumerate(zip(tensors, shapes)):
+        arr[b] = _dev(t, shape=shp, name=f"{name}[{b}]") if t is not None else None
+    return arr
+
+
+def mek_solve_multi(plans, C, X0=None, X_ref=None, variant="grbk", theta: float = 0.5,
+                    alpha: float = 0.0, stop="none", tol: float = 0.0, max_iters: int = 100000,
+                    seed: int = 0, instance: int = 0, diverge: float = 0.0, hist_cap: int = 0,
+                    raise_on_error: bool = True):
+    """Ragged batch: plans[b] with its own A_b, B_b; C, X0, X_ref are lists of
+    per-instance tensors (X0 / X_ref entries may be None). One persistent
+    launch; instance b draws under Philox key (seed, instance + b). Returns
+    (status, [SolveResult per instance])."""
+    nb = len(plans)
+    if len(C) != nb:
+        raise ValueError("one C per plan")
+    dev = C[0].device
+    pq = [(P.p, P.q) for P in plans]
+    X = [torch.empty(p, q, dtype=torch.float64, device=dev) for p, q in pq]
+    handles = (ctypes.c_void_p * nb)(*[P.handle for P in plans])
+    Cp = _ptr_array(C, [(P.m, P.n) for P in plans], "C")
+    X0p = _ptr_array(X0, pq, "X0") if X0 is not None else None
+    Xrp = _ptr_array(X_ref, pq, "X_ref") if X_ref is not None else None
+    Xp = _ptr_array(X, pq, "X")
+    o, hists = _solve_opts(nb, dev, variant, theta, alpha, stop, tol, None, max_iters, seed,
+                           instance, None, diverge, hist_cap, 0)
+    reps = (mek_report * nb)()
+    code = lib().mek_solve_multi(nb, handles, Cp, X0p, Xrp, ctypes.byref(o), Xp, reps, _stream())
+    if raise_on_error and code < 0:
+        raise MekError(code, "mek_solve_multi")
     return int(code), [_result(X[b], reps[b].status, reps[b], hists, b, hist_cap)
                        for b in range(nb)]
 

@@ -212,15 +212,16 @@ constexpr int kRowsPerWG = 8;   // target rows of R per work-group (automatic la
 // of R stay in LDS. Automatic choice: one work-group per kRowsPerWG rows of
 // R (at least as many as it takes for R to fit in LDS), capped by the CUs
 // available to the instance.
-int choose_layout(const mek_plan_s* P, size_t elem, int64_t nb, Layout* L) {
+// Team layout of one instance with at most cap work-groups; R may live in
+// LDS only when allow_lds (and the plan's r_in_lds option permits it).
+int choose_layout_cap(const mek_plan_s* P, size_t elem, int cap, bool allow_lds, Layout* L) {
     const int64_t m = P->m, n = P->n, q = P->q;
     // The selection keeps at most kSelRows row norms per thread in registers,
     // and the n-vector staging buffer must fit in LDS.
     if (m > (int64_t)kSelRows * kThreads) return MEK_EUNSUPPORTED;
     if ((size_t)std::max(n, q) * elem + 4096 > solve_lds_budget()) return MEK_EUNSUPPORTED;
-    // A batch splits the CUs evenly between its instances' teams.
-    if (nb > std::max(1, P->cus)) return MEK_EUNSUPPORTED;
-    const int cus = std::max(1, P->cus / (int)nb);
+    if (!allow_lds && P->r_in_lds == 1) return MEK_EUNSUPPORTED;
+    const int cus = std::max(1, cap);
     const size_t budget = solve_lds_budget();
     int W;
     bool lds;
@@ -232,7 +233,7 @@ int choose_layout(const mek_plan_s* P, size_t elem, int64_t nb, Layout* L) {
     };
     if (P->team_wgs > 0) {
         W = (int)std::min<int64_t>({(int64_t)P->team_wgs, (int64_t)cus, m});
-        lds = (P->r_in_lds != 0) && fits(W);
+        lds = allow_lds && (P->r_in_lds != 0) && fits(W);
         if (P->r_in_lds == 1 && !lds) return MEK_EUNSUPPORTED;
     } else {
         // About kRowsPerWG rows of R per work-group: measured on MI355X, the
@@ -242,7 +243,7 @@ int choose_layout(const mek_plan_s* P, size_t elem, int64_t nb, Layout* L) {
         int Wl = -1;
         for (int Wc = 1; Wc <= std::min<int64_t>(cus, m); ++Wc)
             if (fits(Wc)) { Wl = Wc; break; }
-        if (P->r_in_lds != 0 && Wl > 0) {
+        if (allow_lds && P->r_in_lds != 0 && Wl > 0) {
             // With R in LDS the LDS fits any W >= Wl.
             W = std::max(Wt, Wl);
             lds = true;
@@ -269,6 +270,12 @@ int choose_layout(const mek_plan_s* P, size_t elem, int64_t nb, Layout* L) {
     L->a_lds = L->lds_bytes + solve_lds_bytes_a((int)m) <= budget;
     if (L->a_lds) L->lds_bytes += solve_lds_bytes_a((int)m);
     return MEK_OK;
+}
+
+// A uniform batch splits the CUs evenly between its instances' teams.
+int choose_layout(const mek_plan_s* P, size_t elem, int64_t nb, Layout* L) {
+    if (nb > std::max(1, P->cus)) return MEK_EUNSUPPORTED;
+    return choose_layout_cap(P, elem, std::max(1, P->cus / (int)nb), true, L);
 }
 
 int validate_opts(const mek_plan_s* P, const mek_solve_opts* o) {
@@ -334,6 +341,10 @@ void fill_common(SolveParams<T>& K, const mek_plan_s* P, const mek_solve_opts* o
     K.hist_offset = 0;
     K.nb = 1;
     K.slots = nullptr;
+    K.multi = nullptr;
+    K.multi_start = nullptr;
+    K.multi_n = 0;
+    K.multi_wgs = 0;
     K.W = L.W;
     K.rpw = L.rpw;
     K.xpw = L.xpw;
@@ -1067,9 +1078,248 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
     return ret;
 }
 
+// Ragged batch: instance b of plan plans[b] (sizes of its own), one
+// persistent launch of the MULTI kernel form. Teams get work-groups in
+// proportion to their per-update work (R and X touched), within one
+// work-group per CU for the whole grid; R stays in device memory.
+template <typename T>
+int run_multi(int64_t nb, mek_plan_s* const* plans, const std::vector<Layout>& Ls,
+              const mek_solve_opts* o, const std::vector<double>& C2,
+              const std::vector<double>& ref2, const double* const* Xref, hipStream_t s,
+              std::vector<DevReport>& rep, double* kernel_ms) {
+    std::vector<SolveParams<T>> K(nb);
+    std::vector<int> start(nb + 1, 0);
+    size_t lds = 0;
+    int max_m = 1;
+    static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
+    for (int64_t b = 0; b < nb; ++b) {
+        mek_plan_s* P = plans[b];
+        const Layout& L = Ls[b];
+        Workspace& w = P->ws;
+        SolveParams<T>& k = K[b];
+        fill_common(k, P, o, L, o->alpha > 0.0 ? o->alpha : P->alpha);
+        if (sizeof(T) == 8) {
+            k.A = (const T*)P->A;
+            k.B = (const T*)P->B;
+            k.BT = (const T*)P->BT;
+            k.GA = (const T*)P->GA;
+            k.GB = (const T*)P->GB;
+            k.R = (T*)w.R64;
+            k.Xt = (T*)w.Xt64;
+        } else {
+            k.A = (const T*)P->A32;
+            k.B = (const T*)P->B32;
+            k.BT = (const T*)P->BT32;
+            k.GA = (const T*)P->GA32;
+            k.GB = (const T*)P->GB32;
+            k.R = (T*)w.R32;
+            k.Xt = (T*)w.Xt32;
+        }
+        k.Xref_t = (Xref && Xref[b]) ? w.Xref_t : nullptr;
+        k.C2 = C2[b];
+        k.ref2 = ref2[b];
+        k.S_target = 0.0;
+        k.inst = o->instance + (uint64_t)b;
+        const size_t hc = (size_t)b * (size_t)std::max<int64_t>(o->hist_cap, 0);
+        k.resid_hist = o->resid_hist ? o->resid_hist + hc : nullptr;
+        k.err_hist = o->err_hist ? o->err_hist + hc : nullptr;
+        k.idx_hist = o->idx_hist ? o->idx_hist + hc : nullptr;
+        k.set_hist = o->set_hist ? o->set_hist + hc : nullptr;
+        k.phase = nullptr;
+        k.a_in_lds = L.a_lds ? 1 : 0;
+        k.x_in_lds = L.x_lds ? 1 : 0;
+        k.poll_sleep = poll_sleep;
+        start[b + 1] = start[b] + L.W;
+        lds = std::max(lds, L.lds_bytes);
+        max_m = std::max(max_m, (int)P->m);
+        MEK_TRY(fill_zero_bytes(w.sync, (long long)sizeof(TeamSync), s));
+        MEK_TRY(fill_zero_bytes(w.errpart, kErrStride * 8, s));
+        MEK_TRY(fill_zero_bytes(w.r, P->m * 8, s));
+        MEK_TRY(fill_zero_bytes((char*)w.rowbuf, P->n * 8, s));
+        MEK_TRY(fill_zero_bytes((char*)w.wbuf, P->n * 8, s));
+        MEK_TRY(fill_zero_bytes((char*)w.vbuf, P->q * 8, s));
+    }
+    const size_t pbytes = sizeof(SolveParams<T>) * (size_t)nb;
+    char* dbuf = nullptr;
+    MEK_TRY(hipMalloc((void**)&dbuf, pbytes + sizeof(int) * (size_t)(nb + 1)));
+    int st = MEK_OK;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipMemcpyAsync(dbuf, K.data(), pbytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dbuf + pbytes, start.data(), sizeof(int) * (size_t)(nb + 1),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    SolveParams<T> head = K[0];
+    head.multi = reinterpret_cast<const SolveParams<T>*>(dbuf);
+    head.multi_start = reinterpret_cast<const int*>(dbuf + pbytes);
+    head.multi_n = (int)nb;
+    head.multi_wgs = start[nb];
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) e = launch_solve_multi(head, max_m, lds, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    for (int64_t b = 0; b < nb && e == hipSuccess; ++b)
+        e = hipMemcpyAsync(&rep[b], plans[b]->ws.report, sizeof(DevReport), hipMemcpyDeviceToHost,
+                           s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    st = hip_status(e);
+    float ms = 0.0f;
+    if (st == MEK_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess && kernel_ms)
+        *kernel_ms += (double)ms;
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFree(dbuf);
+    return st;
+}
+
+int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
+                     const double* const* X0, const double* const* Xref,
+                     const mek_solve_opts* o, double* const* X, mek_report* reports,
+                     hipStream_t s) {
+    if (nb < 1 || !plans || !C || !X || !o) return MEK_EINVAL;
+    // References come per instance through Xref; forced indices and the
+    // two-sided projection are single-instance features.
+    if (o->X_ref) return MEK_EINVAL;
+    if (o->replay_len > 0 || o->variant == MEK_TWOSIDED) return MEK_EUNSUPPORTED;
+    std::vector<mek_plan_s*> Ps(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+        Ps[b] = plans[b];
+        if (!Ps[b] || !C[b] || !X[b]) return MEK_EINVAL;
+        for (int64_t c = 0; c < b; ++c)
+            if (Ps[c] == Ps[b]) return MEK_EINVAL;   // each instance needs its own workspace
+        if (Ps[b]->precision != Ps[0]->precision || Ps[b]->device != Ps[0]->device)
+            return MEK_EINVAL;
+        mek_solve_opts ob = *o;
+        ob.X_ref = Xref ? Xref[b] : nullptr;
+        int st = validate_opts(Ps[b], &ob);
+        if (st) return st;
+    }
+    const int prec = Ps[0]->precision;
+    if (prec == MEK_MIXED) return MEK_EUNSUPPORTED;
+    const int cus = std::max(1, Ps[0]->cus);
+    if (nb > cus) return MEK_EUNSUPPORTED;
+    int st;
+    for (int64_t b = 0; b < nb; ++b) {
+        const mek_plan_s* P = Ps[b];
+        const size_t mn = (size_t)(P->m * P->n), pq = (size_t)(P->p * P->q);
+        if ((st = check_dev(C[b], mn * 8)) || (st = check_dev(X[b], pq * 8))) return st;
+        if (X0 && X0[b] && (st = check_dev(X0[b], pq * 8))) return st;
+        if (Xref && Xref[b] && (st = check_dev(Xref[b], pq * 8))) return st;
+    }
+    if (o->hist_cap > 0) {
+        const size_t hc = (size_t)(nb * o->hist_cap);
+        if (o->resid_hist && (st = check_dev(o->resid_hist, hc * 8))) return st;
+        if (o->err_hist && (st = check_dev(o->err_hist, hc * 8))) return st;
+        if (o->idx_hist && (st = check_dev(o->idx_hist, hc * 4))) return st;
+        if (o->set_hist && (st = check_dev(o->set_hist, hc * 4))) return st;
+    }
+    // Work-group caps in proportion to the bytes one update touches.
+    std::vector<double> cost(nb);
+    double tot = 0.0;
+    for (int64_t b = 0; b < nb; ++b) {
+        cost[b] = (double)Ps[b]->m * Ps[b]->n + (double)Ps[b]->p * Ps[b]->q;
+        tot += cost[b];
+    }
+    std::vector<int> cap(nb);
+    int sum = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        cap[b] = std::max(1, (int)floor(cus * cost[b] / tot));
+        sum += cap[b];
+    }
+    while (sum > cus) {
+        int64_t big = 0;
+        for (int64_t b = 1; b < nb; ++b)
+            if (cap[b] > cap[big]) big = b;
+        --cap[big];
+        --sum;
+    }
+    const size_t elem = prec == MEK_FP64 ? 8 : 4;
+    std::vector<Layout> Ls(nb);
+    for (int64_t b = 0; b < nb; ++b)
+        if ((st = choose_layout_cap(Ps[b], elem, cap[b], false, &Ls[b]))) return st;
+    // Per instance: workspace, the finite checks, ||C||^2, ||X_ref||^2, the
+    // starting residual, X^0 and X_ref transposed.
+    std::vector<double> C2(nb, 0.0), ref2(nb, 1.0);
+    for (int64_t b = 0; b < nb; ++b) {
+        mek_plan_s* P = Ps[b];
+        const int64_t m = P->m, p = P->p, q = P->q, n = P->n;
+        const double* x0 = X0 ? X0[b] : nullptr;
+        const double* xr = Xref ? Xref[b] : nullptr;
+        if ((st = ensure_workspace(P, 1))) return st;
+        Workspace& w = P->ws;
+        if ((st = finite_check(C[b], m * n, w.iscal, s))) return st;
+        if (x0 && (st = finite_check(x0, p * q, w.iscal, s))) return st;
+        if (xr && (st = finite_check(xr, p * q, w.iscal, s))) return st;
+        MEK_TRY(sq_norm(C[b], m * n, w.scal + 2, w.red, s));
+        if ((st = read_scalar(w.scal + 2, &C2[b], s))) return st;
+        if (xr) {
+            MEK_TRY(sq_norm(xr, p * q, w.scal + 3, w.red, s));
+            if ((st = read_scalar(w.scal + 3, &ref2[b], s))) return st;
+            if (!(ref2[b] > 0.0)) ref2[b] = 1.0;
+            MEK_TRY(transpose_to<double>(xr, (int)p, (int)q, w.Xref_t, s));
+        }
+        if (x0) {
+            MEK_TRY(gemm_f64((int)m, (int)q, (int)p, 1.0, P->A, p, 1, x0, q, 1, 0.0, nullptr, 0,
+                             w.T64, q, s));
+            MEK_TRY(gemm_f64((int)m, (int)n, (int)q, -1.0, w.T64, q, 1, P->B, n, 1, 1.0, C[b], n,
+                             w.R64, n, s));
+        } else {
+            MEK_TRY(copy_f64(C[b], m * n, w.R64, s));
+        }
+        if (prec == MEK_FP64) {
+            if (x0) MEK_TRY(transpose_to<double>(x0, (int)p, (int)q, w.Xt64, s));
+            else MEK_TRY(fill_zero_bytes(w.Xt64, (long long)(p * q) * 8, s));
+        } else {
+            MEK_TRY(convert_f64_f32(w.R64, m * n, w.R32, s));
+            if (x0) MEK_TRY(transpose_to<float>(x0, (int)p, (int)q, w.Xt32, s));
+            else MEK_TRY(fill_zero_bytes(w.Xt32, (long long)(p * q) * 4, s));
+        }
+    }
+    std::vector<DevReport> rep(nb);
+    memset(rep.data(), 0, sizeof(DevReport) * nb);
+    double kms = 0.0;
+    st = prec == MEK_FP64 ? run_multi<double>(nb, Ps.data(), Ls, o, C2, ref2, Xref, s, rep, &kms)
+                          : run_multi<float>(nb, Ps.data(), Ls, o, C2, ref2, Xref, s, rep, &kms);
+    if (st) return st;
+    for (int64_t b = 0; b < nb; ++b) {
+        mek_plan_s* P = Ps[b];
+        if (prec == MEK_FP64)
+            MEK_TRY(transpose_from<double>(P->ws.Xt64, (int)P->p, (int)P->q, X[b], s));
+        else
+            MEK_TRY(transpose_from<float>(P->ws.Xt32, (int)P->p, (int)P->q, X[b], s));
+    }
+    MEK_TRY(hipStreamSynchronize(s));
+    int ret = MEK_OK;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (reports) {
+            mek_report& r = reports[b];
+            r.iters = rep[b].iters;
+            r.status = rep[b].status;
+            r.resid2 = rep[b].S;
+            r.rel_err = (Xref && Xref[b]) ? rep[b].err : NAN;
+            r.alpha = o->alpha > 0.0 ? o->alpha : Ps[b]->alpha;
+            r.team_wgs = Ls[b].W;
+            r.r_in_lds = 0;
+            r.passes = 1;
+            r.kernel_ms = kms;
+        }
+        const int sb = rep[b].status;
+        if (ret == MEK_OK && sb != MEK_OK) ret = sb;
+        else if (ret >= 0 && sb < 0) ret = sb;
+    }
+    return ret;
+}
+
 }  // namespace
 
 extern "C" {
+
+int mek_solve_multi(int64_t nb, const mek_plan* plans, const double* const* C,
+                    const double* const* X0, const double* const* X_ref,
+                    const mek_solve_opts* opts, double* const* X, mek_report* reports,
+                    void* stream) {
+    return solve_multi_impl(nb, plans, C, X0, X_ref, opts, X, reports, (hipStream_t)stream);
+}
 
 int mek_solve(mek_plan P, const double* C, const double* X0, const mek_solve_opts* o, double* X,
               mek_report* report, void* stream) {

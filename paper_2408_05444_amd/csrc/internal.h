@@ -104,6 +104,14 @@ struct SolveParams {
     // pointers above; its scalars come from the slot.
     int nb;
     const InstSlot* slots;
+    // Ragged batch (the kernel's MULTI form): multi_n instances, each with
+    // its own complete parameter block multi[b] (multi unset there), owning
+    // work-groups [multi_start[b], multi_start[b + 1]) of a grid of
+    // multi_wgs.
+    const SolveParams* multi;
+    const int* multi_start;
+    int multi_n;
+    int multi_wgs;
     // Team layout.
     int W;      // work-groups in the team
     int rpw;    // rows of R per work-group
@@ -170,6 +178,13 @@ size_t block2_lds_budget();
 int sel_rows_for(int m);
 
 // Launchers (solver.hip).
+// Ragged batch: P carries multi, multi_start, multi_n and multi_wgs; R stays
+// in device memory; max_m sizes the selection chunk; lds_bytes is the
+// largest of the instances' LDS needs.
+hipError_t launch_solve_multi(const SolveParams<double>& P, int max_m, size_t lds_bytes,
+                              hipStream_t s);
+hipError_t launch_solve_multi(const SolveParams<float>& P, int max_m, size_t lds_bytes,
+                              hipStream_t s);
 hipError_t launch_solve(const SolveParams<double>& P, bool r_in_lds, size_t lds_bytes,
                         hipStream_t s);
 hipError_t launch_solve(const SolveParams<float>& P, bool r_in_lds, size_t lds_bytes,

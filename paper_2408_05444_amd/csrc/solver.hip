@@ -275,7 +275,7 @@ __device__ __forceinline__ void bind_instance(SolveParams<T>& P, int b) {
     P.inst = sl.inst;
 }
 
-template <typename T, bool LDS, int SR>
+template <typename T, bool LDS, int SR, bool MULTI = false>
 __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     __shared__ BlockScratch sc;
@@ -283,14 +283,26 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     __shared__ double s_err[kWaves];
     if (threadIdx.x == 0) s_fail = 0;
 
-    const int W = P.W;
-    const bool team = W > 1;
     int g = blockIdx.x;
-    if (P.slots) {
-        const int b = g / W;
-        g -= b * W;
+    if (MULTI) {
+        // Ragged batch: instance b owns work-groups [multi_start[b],
+        // multi_start[b + 1]) and brings its own sizes, operands, state and
+        // team layout.
+        int lo = 0, hi = P.multi_n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (P.multi_start[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        g -= P.multi_start[lo];
+        P = P.multi[lo];
+    } else if (P.slots) {
+        const int b = g / P.W;
+        g -= b * P.W;
         bind_instance(P, b);
     }
+    const int W = P.W;
+    const bool team = W > 1;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int m = P.m, n = P.n, p = P.p, q = P.q;
     const int row0 = g * P.rpw;
@@ -654,9 +666,9 @@ size_t solve_lds_bytes(int rpw, int n, int q, int xpw, int wpw, size_t elem, boo
 
 size_t solve_lds_bytes_a(int m) { return (size_t)m * sizeof(double); }
 
-template <typename T, bool LDS, int SR>
+template <typename T, bool LDS, int SR, bool MULTI = false>
 static hipError_t launch_one(const SolveParams<T>& P, size_t lds_bytes, hipStream_t s) {
-    auto kern = solve_kernel<T, LDS, SR>;
+    auto kern = solve_kernel<T, LDS, SR, MULTI>;
     // Raise the dynamic LDS cap for this kernel; if the runtime refuses, the
     // launch below reports the error.
     if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -664,7 +676,7 @@ static hipError_t launch_one(const SolveParams<T>& P, size_t lds_bytes, hipStrea
         (void)hipGetLastError();
     SolveParams<T> copy = P;
     void* args[] = {&copy};
-    const int blocks = P.W * (P.slots ? P.nb : 1);
+    const int blocks = MULTI ? P.multi_wgs : P.W * (P.slots ? P.nb : 1);
     if (blocks == 1)
         return hipLaunchKernel((const void*)kern, dim3(1), dim3(kThreads), args, lds_bytes, s);
     // Teams wait on each other's words, so every work-group of the grid must
@@ -688,6 +700,27 @@ static hipError_t launch_sr(const SolveParams<T>& P, size_t lds_bytes, hipStream
         case 8: return launch_one<T, LDS, 8>(P, lds_bytes, s);
         default: return launch_one<T, LDS, 16>(P, lds_bytes, s);
     }
+}
+
+template <typename T>
+static hipError_t launch_multi_sr(const SolveParams<T>& P, int max_m, size_t lds_bytes,
+                                  hipStream_t s) {
+    switch (sel_rows_for(max_m)) {
+        case 1: return launch_one<T, false, 1, true>(P, lds_bytes, s);
+        case 2: return launch_one<T, false, 2, true>(P, lds_bytes, s);
+        case 4: return launch_one<T, false, 4, true>(P, lds_bytes, s);
+        case 8: return launch_one<T, false, 8, true>(P, lds_bytes, s);
+        default: return launch_one<T, false, 16, true>(P, lds_bytes, s);
+    }
+}
+
+hipError_t launch_solve_multi(const SolveParams<double>& P, int max_m, size_t lds_bytes,
+                              hipStream_t s) {
+    return launch_multi_sr(P, max_m, lds_bytes, s);
+}
+hipError_t launch_solve_multi(const SolveParams<float>& P, int max_m, size_t lds_bytes,
+                              hipStream_t s) {
+    return launch_multi_sr(P, max_m, lds_bytes, s);
 }
 
 hipError_t launch_solve(const SolveParams<double>& P, bool r_in_lds, size_t lds_bytes,

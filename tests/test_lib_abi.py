@@ -25,7 +25,7 @@ def test_header_declares_the_boundary():
     names = _declared_functions()
     for want in ["mek_version", "mek_status_string", "mek_plan_create", "mek_plan_destroy",
                  "mek_plan_query", "mek_solve", "mek_solve_batched", "mek_philox_uniform", "mek_select",
-                 "mek_residual", "mek_residual_batched", "mek_gram"]:
+                 "mek_residual", "mek_residual_batched", "mek_gram", "mek_solve_multi"]:
         assert want in names
 
 
@@ -113,6 +113,8 @@ def test_host_validation_rejects_before_any_gpu_work():
     assert L.mek_residual(0, 1, 1, 1, vp(1), vp(1), vp(1), vp(1), vp(2), None) == EINVAL
     assert L.mek_residual(1, 1, 1, 1, vp(1), vp(1), vp(1), vp(1), vp(1), None) == EINVAL  # R aliases
     assert L.mek_residual_batched(0, 1, 1, 1, 1, vp(8), vp(8), vp(8), vp(8), vp(64), None) == EINVAL
+    assert L.mek_solve_multi(0, None, None, None, None, None, None, None, None) == EINVAL
+    assert L.mek_solve_multi(1, None, None, None, None, None, None, None, None) == EINVAL
     # R_1 (bytes 24..32) overlaps C_0..C_1 (bytes 16..32)
     assert L.mek_residual_batched(2, 1, 1, 1, 1, vp(1024), vp(2048), vp(4096), vp(16), vp(24),
                                   None) == EINVAL

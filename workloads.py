@@ -141,6 +141,30 @@ def shared_ab_batch(inst: Instance, nb: int, seed: int):
     return out
 
 
+def ragged_batch(nb: int, seed: int, mn_range=(128, 1024), pq_range=(64, 512)):
+    """Independent consistent instances of uneven size: first all sizes, m and
+    n uniform on the integers of mn_range, p and q on pq_range (inclusive),
+    in the order (m, p, q, n) per instance; then A (m x p), B (q x n),
+    X* (p x q) iid N(0,1) per instance in order, all from default_rng(seed);
+    C_b = A_b X*_b B_b."""
+    rng = np.random.default_rng(seed)
+    sizes = []
+    for _ in range(nb):
+        m = int(rng.integers(mn_range[0], mn_range[1] + 1))
+        p = int(rng.integers(pq_range[0], pq_range[1] + 1))
+        q = int(rng.integers(pq_range[0], pq_range[1] + 1))
+        n = int(rng.integers(mn_range[0], mn_range[1] + 1))
+        sizes.append((m, p, q, n))
+    out = []
+    for b, (m, p, q, n) in enumerate(sizes):
+        A = rng.standard_normal((m, p))
+        B = rng.standard_normal((q, n))
+        X = rng.standard_normal((p, q))
+        out.append(Instance(f"ragged batch seed={seed} #{b} m={m} p={p} q={q} n={n}",
+                            _c(A), _c(B), _c(A @ X @ B), _c(X)))
+    return out
+
+
 def blur_toeplitz(size: int, sigma: float, half_width: int = 4) -> np.ndarray:
     """Banded Toeplitz Gaussian blur (2*half_width+1 taps), each row divided by its sum.
 
