@@ -165,6 +165,43 @@ def blur_batch_forms(mek, workloads, torch):
     return out
 
 
+def ragged_batch_forms(mek, workloads, torch, nb=64, budget=10_000):
+    """The uneven-instance form: 64 independent consistent systems, m and n
+    uniform in 128..1024, p and q in 64..512 (data seed 5), FP32 iterations
+    (FP64 row norms, step size and stop test), a fixed budget of updates per
+    instance. One ragged launch (mek_solve_multi) against the same instances
+    solved one after another (mek_solve)."""
+    insts = workloads.ragged_batch(nb, seed=5)
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    plans = [mek.mek_plan_create(t(i.A), t(i.B), precision="fp32") for i in insts]
+    Cs = [t(i.C) for i in insts]
+    kw = dict(variant="grbk", max_iters=budget, seed=2408054440)
+    out = {"instances": nb, "budget_per_instance": budget, "precision": "fp32",
+           "elements_of_R": int(sum(i.shape[0] * i.shape[3] for i in insts))}
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    code, res = mek.mek_solve_multi(plans, Cs, **kw)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - ts
+    its = sum(r.iters for r in res)
+    out["one_launch"] = {"time_s": te, "iters_per_s": its / te,
+                         "kernel_ms": res[0].kernel_ms, "work_groups": sum(r.team_wgs for r in res),
+                         "all_ran_budget": all(r.iters == budget for r in res)}
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    its1 = 0
+    for b, (P, C) in enumerate(zip(plans, Cs)):
+        its1 += mek.mek_solve(P, C, instance=b, **kw).iters
+    torch.cuda.synchronize()
+    te1 = time.perf_counter() - ts
+    out["one_after_another"] = {"time_s": te1, "iters_per_s": its1 / te1}
+    out["speedup"] = te1 / te
+    for P in plans:
+        mek.mek_plan_destroy(P)
+    return out
+
+
 def cpu_baseline(inst, seed, updates=600):
     import oracle
     alpha = oracle.spectral_alpha(inst.B)
@@ -190,6 +227,8 @@ def main():
     ap.add_argument("--gemm-only", action="store_true",
                     help="only time the FP64 MFMA GEMMs of the set-up and residual engine at the "
                          "workload's sizes (for a kernel trace) and print them")
+    ap.add_argument("--ragged-only", action="store_true",
+                    help="only run the uneven-instance batch form and print it")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device once (a known-size kernel for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -218,6 +257,9 @@ def main():
     A, B, C, Xs = t(inst.A), t(inst.B), t(inst.C), t(inst.X_star)
     seed = 2408054440
     torch.cuda.synchronize()
+    if args.ragged_only:
+        print(json.dumps({"ragged64_fp32": ragged_batch_forms(mek, workloads, torch)}), flush=True)
+        return
     if args.gemm_only:
         print(json.dumps({"gemm_mfma_f64": gemm_forms(mek, torch, A, B, Xs, C,
                                                       blur=blur_tensors(workloads, torch))}),
@@ -304,6 +346,7 @@ def main():
                              "status": r.status,
                              "kernel_us_per_step": r.kernel_ms * 1e3 / max(r.iters, 1)}
         forms["blur3_batched"] = blur_batch_forms(mek, workloads, torch)
+        forms["ragged64_fp32"] = ragged_batch_forms(mek, workloads, torch)
         line["forms"] = forms
         line["gemm_mfma_f64"] = gemm_forms(mek, torch, A, B, Xs, C,
                                            blur=blur_tensors(workloads, torch))

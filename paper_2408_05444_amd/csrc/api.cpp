@@ -1213,25 +1213,24 @@ int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
         if (o->idx_hist && (st = check_dev(o->idx_hist, hc * 4))) return st;
         if (o->set_hist && (st = check_dev(o->set_hist, hc * 4))) return st;
     }
-    // Work-group caps in proportion to the bytes one update touches.
+    // Work-group caps: starting from one each, every further work-group goes
+    // to the instance with the most elements per work-group that one update
+    // touches (R, B twice for v and w, X), so the slowest team is as fast as
+    // the budget allows; no team beyond about kRowsPerWG rows per work-group.
     std::vector<double> cost(nb);
-    double tot = 0.0;
+    std::vector<int> cap(nb, 1), wmax(nb);
     for (int64_t b = 0; b < nb; ++b) {
-        cost[b] = (double)Ps[b]->m * Ps[b]->n + (double)Ps[b]->p * Ps[b]->q;
-        tot += cost[b];
+        const mek_plan_s* P = Ps[b];
+        cost[b] = (double)P->m * P->n + 2.0 * P->q * P->n + 2.0 * P->p * P->q;
+        wmax[b] = (int)std::max<int64_t>(1, (P->m + kRowsPerWG - 1) / kRowsPerWG);
     }
-    std::vector<int> cap(nb);
-    int sum = 0;
-    for (int64_t b = 0; b < nb; ++b) {
-        cap[b] = std::max(1, (int)floor(cus * cost[b] / tot));
-        sum += cap[b];
-    }
-    while (sum > cus) {
-        int64_t big = 0;
-        for (int64_t b = 1; b < nb; ++b)
-            if (cap[b] > cap[big]) big = b;
-        --cap[big];
-        --sum;
+    for (int spare = cus - (int)nb; spare > 0; --spare) {
+        int64_t best = -1;
+        for (int64_t b = 0; b < nb; ++b)
+            if (cap[b] < wmax[b] && (best < 0 || cost[b] / cap[b] > cost[best] / cap[best]))
+                best = b;
+        if (best < 0) break;
+        ++cap[best];
     }
     const size_t elem = prec == MEK_FP64 ? 8 : 4;
     std::vector<Layout> Ls(nb);

@@ -27,6 +27,7 @@ __host__ __device__ inline int dot_parts(int xpw, int n, int wpw, int q, bool si
 }
 
 constexpr int kAPre = 8;          // entries of A_{i_k} per lane loaded ahead of the X update
+constexpr int kRowBatch = 8;      // loads in flight per lane when rows of R sit in device memory
 
 // ---------------------------------------------------------------------------
 // Wave-level reductions and scans on DPP row permutations (register-level

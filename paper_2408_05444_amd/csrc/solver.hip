@@ -610,19 +610,63 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         {
             const unsigned int ntag = seq_tag(k + 1);
             const T* garow = P.GA + (size_t)ik * m + row0;
-            for (int ii = wv; ii < nrow; ii += kWaves) {
-                const T sc_i = (T)(c * (double)(ii == wv ? ga_pre : garow[ii]));
-                T* rp = Rown + (size_t)ii * n;
-                double acc = 0.0;
-                for (int j = lane; j < n; j += kWave) {
-                    const T v = rp[j] - sc_i * vec[j];
-                    rp[j] = v;
-                    acc += (double)v * (double)v;
-                }
+            auto publish = [&](int ii, double acc) {
                 acc = wave_sum(acc);
                 if (lane == 0) {
                     if (team) xstore(&r_x[row0 + ii], pack_word(acc, ntag));
                     else r_local[ii] = acc;
+                }
+            };
+            if (LDS) {
+                for (int ii = wv; ii < nrow; ii += kWaves) {
+                    const T sc_i = (T)(c * (double)(ii == wv ? ga_pre : garow[ii]));
+                    T* rp = Rown + (size_t)ii * n;
+                    double acc = 0.0;
+                    for (int j = lane; j < n; j += kWave) {
+                        const T v = rp[j] - sc_i * vec[j];
+                        rp[j] = v;
+                        acc += (double)v * (double)v;
+                    }
+                    publish(ii, acc);
+                }
+            } else {
+                // R in device memory: two rows per wave at a time and
+                // kRowBatch loads in flight per lane and row (each row's
+                // elements in the same order as above, so the same sums).
+                for (int ii = wv; ii < nrow; ii += 2 * kWaves) {
+                    const int i2 = ii + kWaves;
+                    const bool two = i2 < nrow;
+                    const T sa = (T)(c * (double)(ii == wv ? ga_pre : garow[ii]));
+                    const T sb = two ? (T)(c * (double)garow[i2]) : T(0);
+                    T* ra = Rown + (size_t)ii * n;
+                    T* rb = Rown + (size_t)(two ? i2 : ii) * n;
+                    double acc_a = 0.0, acc_b = 0.0;
+                    for (int j0 = 0; j0 < n; j0 += kRowBatch * kWave) {
+                        T xa[kRowBatch], xb[kRowBatch];
+#pragma unroll
+                        for (int u = 0; u < kRowBatch; ++u) {
+                            const int j = j0 + u * kWave + lane;
+                            xa[u] = j < n ? ra[j] : T(0);
+                            xb[u] = (two && j < n) ? rb[j] : T(0);
+                        }
+#pragma unroll
+                        for (int u = 0; u < kRowBatch; ++u) {
+                            const int j = j0 + u * kWave + lane;
+                            if (j < n) {
+                                const T wj = vec[j];
+                                const T va = xa[u] - sa * wj;
+                                ra[j] = va;
+                                acc_a += (double)va * (double)va;
+                                if (two) {
+                                    const T vb = xb[u] - sb * wj;
+                                    rb[j] = vb;
+                                    acc_b += (double)vb * (double)vb;
+                                }
+                            }
+                        }
+                    }
+                    publish(ii, acc_a);
+                    if (two) publish(i2, acc_b);
                 }
             }
             if (tid == 0) {
