@@ -1,0 +1,135 @@
+"""Pins of the warm-start network's FP64 oracle (oracle/conv.py) against
+things other than itself: scipy's correlate2d, closed forms of identity and
+shift kernels, the adjoint identity, brute-force sums and central finite
+differences through the whole network on 8 x 8 images."""
+import numpy as np
+import pytest
+from scipy.signal import correlate2d
+
+from oracle import conv
+
+
+def _rand(rng, *shape):
+    return rng.standard_normal(shape)
+
+
+def test_forward_matches_scipy_correlate2d():
+    rng = np.random.default_rng(0)
+    x, W, b = _rand(rng, 2, 3, 9, 7), _rand(rng, 4, 3, 3, 3), _rand(rng, 4)
+    y = conv.conv3x3(x, W, b)
+    for n in range(2):
+        for o in range(4):
+            ref = b[o] + sum(correlate2d(x[n, c], W[o, c], mode="same", boundary="fill")
+                             for c in range(3))
+            assert np.allclose(y[n, o], ref, rtol=1e-13, atol=1e-13)
+
+
+def test_identity_and_shift_kernels():
+    rng = np.random.default_rng(1)
+    x = _rand(rng, 1, 2, 6, 5)
+    W = np.zeros((2, 2, 3, 3))
+    W[0, 0, 1, 1] = W[1, 1, 1, 1] = 1.0
+    assert np.array_equal(conv.conv3x3(x, W), x)
+    # A single tap at (i, j) reads x[h + i - 1, w + j - 1], zero outside.
+    for i in range(3):
+        for j in range(3):
+            W = np.zeros((1, 2, 3, 3))
+            W[0, 1, i, j] = 1.0
+            y = conv.conv3x3(x, W)[0, 0]
+            ref = np.zeros((6, 5))
+            for h in range(6):
+                for w in range(5):
+                    hh, ww = h + i - 1, w + j - 1
+                    if 0 <= hh < 6 and 0 <= ww < 5:
+                        ref[h, w] = x[0, 1, hh, ww]
+            assert np.array_equal(y, ref)
+
+
+def test_grad_input_is_the_adjoint():
+    rng = np.random.default_rng(2)
+    x, W, g = _rand(rng, 3, 4, 8, 6), _rand(rng, 5, 4, 3, 3), _rand(rng, 3, 5, 8, 6)
+    lhs = np.sum(conv.conv3x3(x, W) * g)
+    rhs = np.sum(x * conv.conv3x3_grad_input(g, W))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_grad_weight_brute_force():
+    rng = np.random.default_rng(3)
+    x, g = _rand(rng, 2, 3, 5, 4), _rand(rng, 2, 2, 5, 4)
+    dW, db = conv.conv3x3_grad_weight(g, x)
+    ref = np.zeros((2, 3, 3, 3))
+    for o in range(2):
+        for c in range(3):
+            for i in range(3):
+                for j in range(3):
+                    s = 0.0
+                    for n in range(2):
+                        for h in range(5):
+                            for w in range(4):
+                                hh, ww = h + i - 1, w + j - 1
+                                if 0 <= hh < 5 and 0 <= ww < 4:
+                                    s += g[n, o, h, w] * x[n, c, hh, ww]
+                    ref[o, c, i, j] = s
+    assert np.allclose(dW, ref, rtol=1e-13, atol=1e-13)
+    assert np.allclose(db, [g[:, o].sum() for o in range(2)], rtol=1e-13)
+
+
+def _net(rng, chans=conv.CHANNELS, scale=0.3):
+    return [(scale * _rand(rng, co, ci, 3, 3), 0.1 * _rand(rng, co))
+            for ci, co in zip(chans[:-1], chans[1:])]
+
+
+def test_network_gradients_by_central_differences():
+    # 8 x 8 images, the full 3-32-32-32-3 network; central differences with
+    # step 1e-6 on sampled weights, every bias of the first and last layer
+    # and sampled input pixels (ReLU kinks have measure zero).
+    rng = np.random.default_rng(4)
+    params = _net(rng)
+    x, label = rng.uniform(0, 1, (2, 3, 8, 8)), rng.uniform(0, 1, (2, 3, 8, 8))
+    acts = conv.forward(params, x)
+    loss, grads, dx = conv.backward(params, acts, label)
+    assert loss == pytest.approx(conv.mse(acts[-1], label))
+
+    def loss_at(p, xx):
+        return conv.mse(conv.forward(p, xx)[-1], label)
+
+    eps = 1e-6
+    for li in range(4):
+        W, b = params[li]
+        for _ in range(6):
+            idx = tuple(rng.integers(0, s) for s in W.shape)
+            Wp, Wm = W.copy(), W.copy()
+            Wp[idx] += eps
+            Wm[idx] -= eps
+            pp = [(Wp, b) if k == li else params[k] for k in range(4)]
+            pm = [(Wm, b) if k == li else params[k] for k in range(4)]
+            fd = (loss_at(pp, x) - loss_at(pm, x)) / (2 * eps)
+            assert grads[li][0][idx] == pytest.approx(fd, rel=1e-5, abs=1e-10)
+        for o in (range(b.size) if li in (0, 3) else rng.integers(0, b.size, 3)):
+            bp, bm = b.copy(), b.copy()
+            bp[o] += eps
+            bm[o] -= eps
+            pp = [(W, bp) if k == li else params[k] for k in range(4)]
+            pm = [(W, bm) if k == li else params[k] for k in range(4)]
+            fd = (loss_at(pp, x) - loss_at(pm, x)) / (2 * eps)
+            assert grads[li][1][o] == pytest.approx(fd, rel=1e-5, abs=1e-10)
+    for _ in range(6):
+        idx = tuple(rng.integers(0, s) for s in x.shape)
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += eps
+        xm[idx] -= eps
+        fd = (loss_at(params, xp) - loss_at(params, xm)) / (2 * eps)
+        assert dx[idx] == pytest.approx(fd, rel=1e-5, abs=1e-10)
+
+
+def test_relu_mask_uses_the_layer_output():
+    # A layer whose pre-activations are all negative passes no gradient.
+    rng = np.random.default_rng(5)
+    params = _net(rng)
+    W0, b0 = params[0]
+    params[0] = (np.zeros_like(W0), -np.ones_like(b0))
+    x, label = rng.uniform(0, 1, (1, 3, 8, 8)), rng.uniform(0, 1, (1, 3, 8, 8))
+    acts = conv.forward(params, x)
+    _, grads, dx = conv.backward(params, acts, label)
+    assert np.all(grads[0][0] == 0.0) and np.all(grads[0][1] == 0.0)
+    assert np.all(dx == 0.0)
