@@ -275,6 +275,54 @@ int mek_residual_batched(int64_t nb, int64_t m, int64_t p, int64_t q, int64_t n,
 int mek_gram(int64_t rows, int64_t cols, const double* M, int transpose_first, double* G,
              void* stream);
 
+/* ---- Learned warm start X0 = C + f(C) (not in the paper: an extension of
+ * its initial guess X^0). f is a network of 3 x 3 convolutions; these calls
+ * are its layers, gradients and optimiser step. Tensors are device arrays in
+ * NCHW order; BF16 tensors are uint16_t (the upper half of an IEEE single,
+ * rounded to nearest even); weights are float arrays (O, C, 3, 3) holding
+ * BF16-rounded values; sums are FP32 (the loss FP64). Channel counts must be
+ * 3 or 32, N <= 65535, H, W <= 32768. All calls synchronise `stream`.
+ * Errors: MEK_EINVAL for bad sizes or pointers, MEK_EHIP for host or
+ * short buffers and launch failures. */
+
+/* y[n,o,h,w] = b[o] + sum_{c,i,j} w[o,c,i,j] x[n,c,h+i-1,w+j-1] (zero
+ * padding 1), then max(., 0) when relu; written to exactly one of y_bf16
+ * (BF16) or y_f64; an FP64 output adds add_f64 (same shape) when that is not
+ * NULL (the warm start's X0 = C + f(C)). b may be NULL. */
+int mek_cnn_conv3x3(int64_t N, int64_t Cin, int64_t H, int64_t W, int64_t Cout, const uint16_t* x,
+                    const float* w, const float* b, int relu, uint16_t* y_bf16, double* y_f64,
+                    const double* add_f64, void* stream);
+
+/* Input gradient of that convolution for the upstream gradient g (N, Cout,
+ * H, W; BF16): gx[n,c,h,w] = sum_{o,i,j} w[o,c,i,j] g'[n,o,h-i+1,w-j+1], with
+ * g' = g where g_gate > 0 and 0 elsewhere (g_gate: the layer's ReLU output,
+ * or NULL for no gate). gx (N, Cin, H, W) BF16. */
+int mek_cnn_conv3x3_grad_input(int64_t N, int64_t Cout, int64_t H, int64_t W, int64_t Cin,
+                               const uint16_t* g, const uint16_t* g_gate, const float* w,
+                               uint16_t* gx, void* stream);
+
+/* Weight and bias gradients: dw[o,c,i,j] = sum_{n,h,w} g'[n,o,h,w]
+ * x[n,c,h+i-1,w+j-1], db[o] = sum g' (g' gated as above), FP32, summed over
+ * 16 x 16 pixel tiles and then over the tiles in a fixed order. Uses a
+ * per-device scratch buffer kept between calls. */
+int mek_cnn_conv3x3_grad_weight(int64_t N, int64_t Cin, int64_t H, int64_t W, int64_t Cout,
+                                const uint16_t* x, const uint16_t* g, const uint16_t* g_gate,
+                                float* dw, float* db, void* stream);
+
+/* *loss (host) = mean((y - label)^2) over len entries (device double), and,
+ * when g is not NULL, g = BF16(2 (y - label) / len). */
+int mek_cnn_mse_grad(int64_t len, const double* y, const double* label, uint16_t* g, double* loss,
+                     void* stream);
+
+/* One Adam step (t >= 1) on n FP32 master weights w with gradient g and
+ * moments m, v; wq receives the BF16-rounded weights the layers use. */
+int mek_cnn_adam(int64_t n, float* w, float* wq, const float* g, float* m, float* v, double lr,
+                 double beta1, double beta2, double eps, int64_t t, void* stream);
+
+/* y = BF16(scale x) for n doubles; y = BF16-rounded x for n floats. */
+int mek_cnn_to_bf16(int64_t n, const double* x, double scale, uint16_t* y, void* stream);
+int mek_cnn_round_bf16(int64_t n, const float* x, float* y, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

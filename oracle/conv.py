@@ -76,13 +76,32 @@ def relu(z):
     return np.maximum(z, 0.0)
 
 
-def forward(params, x):
+def bf16(x):
+    """Round to the nearest BF16 value (8-bit significand), ties to even,
+    from the FP32 value of x: the storage precision of the GPU network's
+    activations and gradients (finite inputs)."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    u = (u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(params, x, store=None, add=None):
     """params: list of (W, b) for the four layers. Returns the list of layer
-    outputs (after ReLU for the first three) with x prepended."""
+    outputs (after ReLU for the first three) with x prepended. store, if
+    given, rounds each hidden layer's output (the storage precision); add
+    is added to the last layer's output."""
     acts = [np.asarray(x, np.float64)]
     for li, (W, b) in enumerate(params):
         z = conv3x3(acts[-1], W, b)
-        acts.append(relu(z) if li < len(params) - 1 else z)
+        if li < len(params) - 1:
+            z = relu(z)
+            if store is not None:
+                z = store(z)
+        elif add is not None:
+            z = z + np.asarray(add, np.float64)
+        acts.append(z)
     return acts
 
 
@@ -91,12 +110,15 @@ def mse(y, label):
     return float(np.mean(d * d))
 
 
-def backward(params, acts, label):
+def backward(params, acts, label, store=None):
     """Gradients of the mean squared error of forward(params, x) against
-    label. Returns (loss, [(dW, db)] per layer, dx of the input)."""
+    label. Returns (loss, [(dW, db)] per layer, dx of the input). store, if
+    given, rounds the loss gradient and each propagated input gradient."""
     y = acts[-1]
     loss = mse(y, label)
     g = 2.0 * (y - np.asarray(label, np.float64)) / y.size
+    if store is not None:
+        g = store(g)
     grads = [None] * len(params)
     for li in range(len(params) - 1, -1, -1):
         W, _ = params[li]
@@ -104,4 +126,6 @@ def backward(params, acts, label):
             g = g * (acts[li + 1] > 0.0)
         grads[li] = conv3x3_grad_weight(g, acts[li])
         g = conv3x3_grad_input(g, W)
+        if store is not None and li > 0:
+            g = store(g)
     return loss, grads, g

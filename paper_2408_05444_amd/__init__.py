@@ -98,6 +98,20 @@ def lib() -> ctypes.CDLL:
         L.mek_solve_multi.argtypes = [i64, vp, vp, vp, vp, ctypes.POINTER(mek_solve_opts), vp,
                                       vp, vp]
         L.mek_solve_multi.restype = ci
+        L.mek_cnn_conv3x3.argtypes = [i64, i64, i64, i64, i64, vp, vp, vp, ci, vp, vp, vp, vp]
+        L.mek_cnn_conv3x3.restype = ci
+        L.mek_cnn_conv3x3_grad_input.argtypes = [i64, i64, i64, i64, i64, vp, vp, vp, vp, vp]
+        L.mek_cnn_conv3x3_grad_input.restype = ci
+        L.mek_cnn_conv3x3_grad_weight.argtypes = [i64, i64, i64, i64, i64, vp, vp, vp, vp, vp, vp]
+        L.mek_cnn_conv3x3_grad_weight.restype = ci
+        L.mek_cnn_mse_grad.argtypes = [i64, vp, vp, vp, ctypes.POINTER(d), vp]
+        L.mek_cnn_mse_grad.restype = ci
+        L.mek_cnn_adam.argtypes = [i64, vp, vp, vp, vp, vp, d, d, d, d, i64, vp]
+        L.mek_cnn_adam.restype = ci
+        L.mek_cnn_to_bf16.argtypes = [i64, vp, d, vp, vp]
+        L.mek_cnn_to_bf16.restype = ci
+        L.mek_cnn_round_bf16.argtypes = [i64, vp, vp, vp]
+        L.mek_cnn_round_bf16.restype = ci
         L.mek_philox_uniform.argtypes = [u64, u64, i64, i64, vp, vp]
         L.mek_philox_uniform.restype = ci
         L.mek_select.argtypes = [ci, i64, vp, vp, d, d, u64, u64, i64, i64, vp, vp, vp, vp, vp]

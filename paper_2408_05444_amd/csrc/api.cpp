@@ -1435,6 +1435,161 @@ int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, co
     return mek_residual_batched(1, m, p, q, n, A, X, B, C, R, stream);
 }
 
+}  // extern "C"
+
+// ---- Warm-start network (cnn.hip). Scratch for the weight-gradient
+// partials and the loss partials: a per-device buffer kept between calls
+// (grown when needed); calls are serialised on it.
+namespace {
+std::mutex g_cnn_mtx;
+void* g_cnn_buf[64] = {nullptr};
+size_t g_cnn_bytes[64] = {0};
+
+int cnn_scratch(size_t need, void** out) {
+    int dev = 0;
+    MEK_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return MEK_EUNSUPPORTED;
+    if (g_cnn_bytes[dev] < need) {
+        if (g_cnn_buf[dev]) {
+            MEK_TRY(hipDeviceSynchronize());
+            (void)hipFree(g_cnn_buf[dev]);
+            g_cnn_buf[dev] = nullptr;
+            g_cnn_bytes[dev] = 0;
+        }
+        MEK_TRY(hipMalloc(&g_cnn_buf[dev], need));
+        g_cnn_bytes[dev] = need;
+    }
+    *out = g_cnn_buf[dev];
+    return MEK_OK;
+}
+
+bool cnn_dims_ok(int64_t N, int64_t H, int64_t W) {
+    return N > 0 && H > 0 && W > 0 && N <= 65535 && H <= (1 << 15) && W <= (1 << 15);
+}
+}  // namespace
+
+extern "C" {
+
+int mek_cnn_conv3x3(int64_t N, int64_t Cin, int64_t H, int64_t W, int64_t Cout, const uint16_t* x,
+                    const float* w, const float* b, int relu, uint16_t* y_bf16, double* y_f64,
+                    const double* add_f64, void* stream) {
+    if (!cnn_dims_ok(N, H, W) || !cnn_channels_ok(Cin) || !cnn_channels_ok(Cout)) return MEK_EINVAL;
+    if (!x || !w || (!y_bf16) == (!y_f64) || (add_f64 && !y_f64)) return MEK_EINVAL;
+    const size_t in = (size_t)(N * Cin * H * W), outn = (size_t)(N * Cout * H * W);
+    int st;
+    if ((st = check_dev(x, in * 2)) || (st = check_dev(w, (size_t)(Cout * Cin * 9) * 4)) ||
+        (b && (st = check_dev(b, (size_t)Cout * 4))) ||
+        (y_bf16 && (st = check_dev(y_bf16, outn * 2))) || (y_f64 && (st = check_dev(y_f64, outn * 8))) ||
+        (add_f64 && (st = check_dev(add_f64, outn * 8))))
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = cnn_conv3x3((int)N, (int)Cin, (int)H, (int)W, (int)Cout, x, nullptr, w, b,
+                               relu ? 1 : 0, y_bf16, y_f64, add_f64, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e);
+}
+
+int mek_cnn_conv3x3_grad_input(int64_t N, int64_t Cout, int64_t H, int64_t W, int64_t Cin,
+                               const uint16_t* g, const uint16_t* g_gate, const float* w,
+                               uint16_t* gx, void* stream) {
+    if (!cnn_dims_ok(N, H, W) || !cnn_channels_ok(Cin) || !cnn_channels_ok(Cout)) return MEK_EINVAL;
+    if (!g || !w || !gx) return MEK_EINVAL;
+    const size_t gn = (size_t)(N * Cout * H * W), xn = (size_t)(N * Cin * H * W);
+    int st;
+    if ((st = check_dev(g, gn * 2)) || (g_gate && (st = check_dev(g_gate, gn * 2))) ||
+        (st = check_dev(w, (size_t)(Cout * Cin * 9) * 4)) || (st = check_dev(gx, xn * 2)))
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = cnn_conv3x3_grad_input((int)N, (int)Cout, (int)H, (int)W, (int)Cin, g, g_gate, w,
+                                          gx, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e);
+}
+
+int mek_cnn_conv3x3_grad_weight(int64_t N, int64_t Cin, int64_t H, int64_t W, int64_t Cout,
+                                const uint16_t* x, const uint16_t* g, const uint16_t* g_gate,
+                                float* dw, float* db, void* stream) {
+    if (!cnn_dims_ok(N, H, W) || !cnn_channels_ok(Cin) || !cnn_channels_ok(Cout)) return MEK_EINVAL;
+    if (!x || !g || !dw || !db) return MEK_EINVAL;
+    const size_t gn = (size_t)(N * Cout * H * W), xn = (size_t)(N * Cin * H * W);
+    int st;
+    if ((st = check_dev(x, xn * 2)) || (st = check_dev(g, gn * 2)) ||
+        (g_gate && (st = check_dev(g_gate, gn * 2))) ||
+        (st = check_dev(dw, (size_t)(Cout * Cin * 9) * 4)) || (st = check_dev(db, (size_t)Cout * 4)))
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(g_cnn_mtx);
+    void* part = nullptr;
+    if ((st = cnn_scratch(cnn_wgrad_partial_floats((int)N, (int)Cin, (int)H, (int)W, (int)Cout) * 4,
+                          &part)))
+        return st;
+    hipError_t e = cnn_conv3x3_grad_weight((int)N, (int)Cin, (int)H, (int)W, (int)Cout, x, g,
+                                           g_gate, (float*)part, dw, db, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e);
+}
+
+int mek_cnn_mse_grad(int64_t len, const double* y, const double* label, uint16_t* g, double* loss,
+                     void* stream) {
+    if (len <= 0 || !y || !label || !loss) return MEK_EINVAL;
+    int st;
+    if ((st = check_dev(y, (size_t)len * 8)) || (st = check_dev(label, (size_t)len * 8)) ||
+        (g && (st = check_dev(g, (size_t)len * 2))))
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(g_cnn_mtx);
+    constexpr int kBlocks = 256;
+    void* buf = nullptr;
+    if ((st = cnn_scratch((kBlocks + 256 + 8) * 8, &buf))) return st;
+    double* part = (double*)buf;
+    double* scratch = part + kBlocks;
+    double* out = scratch + 256;
+    hipError_t e = cnn_mse_grad(len, y, label, 2.0 / (double)len, g, part, kBlocks, s);
+    if (e == hipSuccess) e = sum_reduce(part, kBlocks, out, scratch, s);
+    double h = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, out, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) *loss = h / (double)len;
+    return hip_status(e);
+}
+
+int mek_cnn_adam(int64_t n, float* w, float* wq, const float* g, float* m, float* v, double lr,
+                 double beta1, double beta2, double eps, int64_t t, void* stream) {
+    if (n <= 0 || !w || !wq || !g || !m || !v || t < 1) return MEK_EINVAL;
+    if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+        return MEK_EINVAL;
+    int st;
+    const size_t b = (size_t)n * 4;
+    if ((st = check_dev(w, b)) || (st = check_dev(wq, b)) || (st = check_dev(g, b)) ||
+        (st = check_dev(m, b)) || (st = check_dev(v, b)))
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = cnn_adam(n, w, wq, g, m, v, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                            (int)std::min<int64_t>(t, INT32_MAX), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e);
+}
+
+int mek_cnn_to_bf16(int64_t n, const double* x, double scale, uint16_t* y, void* stream) {
+    if (n <= 0 || !x || !y) return MEK_EINVAL;
+    int st;
+    if ((st = check_dev(x, (size_t)n * 8)) || (st = check_dev(y, (size_t)n * 2))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = cnn_to_bf16(n, x, scale, y, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e);
+}
+
+int mek_cnn_round_bf16(int64_t n, const float* x, float* y, void* stream) {
+    if (n <= 0 || !x || !y) return MEK_EINVAL;
+    int st;
+    if ((st = check_dev(x, (size_t)n * 4)) || (st = check_dev(y, (size_t)n * 4))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = cnn_round_bf16(n, x, y, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e);
+}
+
 int mek_gram(int64_t rows, int64_t cols, const double* M, int transpose_first, double* G,
              void* stream) {
     if (rows <= 0 || cols <= 0 || rows > INT32_MAX / 2 || cols > INT32_MAX / 2) return MEK_EINVAL;

@@ -215,6 +215,26 @@ hipError_t gemm_f64_batched(int nb, int M, int N, int K, double alpha, const dou
                             const double* C, long long ldc, long long sC, double* D,
                             long long ldd, long long sD, hipStream_t s);
 
+// Warm-start network kernels (cnn.hip): BF16 tensors as uint16_t, NCHW;
+// channel counts 3 or 32.
+bool cnn_channels_ok(int64_t c);
+size_t cnn_wgrad_partial_floats(int N, int Cin, int H, int W, int Cout);
+hipError_t cnn_conv3x3(int N, int Cin, int H, int W, int Cout, const uint16_t* x,
+                       const uint16_t* mask, const float* w, const float* b, int relu,
+                       uint16_t* yb, double* yd, const double* add, hipStream_t s);
+hipError_t cnn_conv3x3_grad_input(int N, int Cout, int H, int W, int Cin, const uint16_t* g,
+                                  const uint16_t* gmask, const float* w, uint16_t* gx,
+                                  hipStream_t s);
+hipError_t cnn_conv3x3_grad_weight(int N, int Cin, int H, int W, int Cout, const uint16_t* x,
+                                   const uint16_t* g, const uint16_t* gmask, float* partial,
+                                   float* dw, float* db, hipStream_t s);
+hipError_t cnn_mse_grad(long long len, const double* y, const double* label, double scale,
+                        uint16_t* g, double* part, int nblocks, hipStream_t s);
+hipError_t cnn_adam(long long n, float* w, float* wq, const float* g, float* m, float* v, float lr,
+                    float b1, float b2, float eps, int t, hipStream_t s);
+hipError_t cnn_to_bf16(long long n, const double* x, double scale, uint16_t* y, hipStream_t s);
+hipError_t cnn_round_bf16(long long n, const float* x, float* y, hipStream_t s);
+
 // Utility kernels (util.hip).
 hipError_t row_sq_norms(const double* A, int m, int p, double* out, hipStream_t s);
 // Fixed-order reductions; scratch holds 256 doubles of partial sums.

@@ -1,0 +1,147 @@
+"""Learned warm start X0 = C + f(C) for the image form of A X B = C (an
+extension of the paper's initial guess X^0, not in the paper).
+
+f is four 3 x 3 convolutions 3 -> 32 -> 32 -> 32 -> 3 with ReLU after the
+first three, applied to the three channels of C at once; activations and
+their gradients are BF16, sums FP32, the output and the loss FP64. Every
+step (layers, gradients, loss, Adam) runs in the library's kernels through
+the C ABI; this module only sequences the calls and owns the buffers.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import _check, _stream, lib
+
+CHANNELS = (3, 32, 32, 32, 3)
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class WarmStartNet:
+    """The network, its FP32 master weights, BF16-rounded working weights and
+    Adam moments, all on the GPU."""
+
+    def __init__(self, seed: int = 0, device: str = "cuda"):
+        self.device = torch.device(device)
+        rng = np.random.default_rng(seed)
+        self.w: List[torch.Tensor] = []
+        self.b: List[torch.Tensor] = []
+        nl = len(CHANNELS) - 1
+        for li, (ci, co) in enumerate(zip(CHANNELS[:-1], CHANNELS[1:])):
+            # He initialisation; the last layer starts small so that the
+            # untrained network gives X0 close to C.
+            std = np.sqrt(2.0 / (ci * 9)) * (0.1 if li == nl - 1 else 1.0)
+            self.w.append(self._t(rng.standard_normal((co, ci, 3, 3)) * std))
+            self.b.append(self._t(np.zeros(co)))
+        self.params = self.w + self.b
+        self.q = [torch.empty_like(t) for t in self.params]      # BF16-rounded copies
+        self.m = [torch.zeros_like(t) for t in self.params]
+        self.v = [torch.zeros_like(t) for t in self.params]
+        self.g = [torch.zeros_like(t) for t in self.params]
+        self.t = 0
+        for src, dst in zip(self.params, self.q):
+            _check(lib().mek_cnn_round_bf16(src.numel(), _p(src), _p(dst), _stream()),
+                   "mek_cnn_round_bf16")
+
+    def _t(self, a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(self.device)
+
+    @property
+    def wq(self):
+        return self.q[:len(self.w)]
+
+    @property
+    def bq(self):
+        return self.q[len(self.w):]
+
+    def num_params(self) -> int:
+        return sum(t.numel() for t in self.params)
+
+    def to_input(self, C: torch.Tensor) -> torch.Tensor:
+        """C (N, 3, H, W) float64 -> BF16 input."""
+        x = torch.empty(C.shape, dtype=torch.int16, device=self.device)
+        _check(lib().mek_cnn_to_bf16(C.numel(), _p(C), 1.0, _p(x), _stream()), "mek_cnn_to_bf16")
+        return x
+
+    def forward(self, C: torch.Tensor):
+        """Returns (activations [x, y1, y2, y3] in BF16, X0 = C + f(C) FP64)."""
+        N, _, H, W = C.shape
+        acts = [self.to_input(C)]
+        nl = len(CHANNELS) - 1
+        for li in range(nl):
+            ci, co = CHANNELS[li], CHANNELS[li + 1]
+            if li < nl - 1:
+                y = torch.empty((N, co, H, W), dtype=torch.int16, device=self.device)
+                _check(lib().mek_cnn_conv3x3(N, ci, H, W, co, _p(acts[-1]), _p(self.wq[li]),
+                                             _p(self.bq[li]), 1, _p(y), None, None, _stream()),
+                       "mek_cnn_conv3x3")
+                acts.append(y)
+            else:
+                out = torch.empty((N, co, H, W), dtype=torch.float64, device=self.device)
+                _check(lib().mek_cnn_conv3x3(N, ci, H, W, co, _p(acts[-1]), _p(self.wq[li]),
+                                             _p(self.bq[li]), 0, None, _p(out), _p(C),
+                                             _stream()), "mek_cnn_conv3x3")
+        return acts, out
+
+    def predict(self, C: torch.Tensor) -> torch.Tensor:
+        return self.forward(C)[1]
+
+    def loss_and_grads(self, C: torch.Tensor, label: torch.Tensor) -> float:
+        """Mean squared error of X0 against label; fills self.g (weights
+        then biases) with its gradients."""
+        N, _, H, W = C.shape
+        acts, out = self.forward(C)
+        g = torch.empty(out.shape, dtype=torch.int16, device=self.device)
+        loss = ctypes.c_double()
+        _check(lib().mek_cnn_mse_grad(out.numel(), _p(out), _p(label), _p(g), ctypes.byref(loss),
+                                      _stream()), "mek_cnn_mse_grad")
+        nl = len(CHANNELS) - 1
+        for li in range(nl - 1, -1, -1):
+            ci, co = CHANNELS[li], CHANNELS[li + 1]
+            gate = acts[li + 1] if li < nl - 1 else None   # the layer's ReLU output
+            _check(lib().mek_cnn_conv3x3_grad_weight(N, ci, H, W, co, _p(acts[li]), _p(g), _p(gate),
+                                                     _p(self.g[li]), _p(self.g[nl + li]),
+                                                     _stream()), "mek_cnn_conv3x3_grad_weight")
+            if li > 0:
+                gx = torch.empty((N, ci, H, W), dtype=torch.int16, device=self.device)
+                _check(lib().mek_cnn_conv3x3_grad_input(N, co, H, W, ci, _p(g), _p(gate),
+                                                        _p(self.wq[li]), _p(gx), _stream()),
+                       "mek_cnn_conv3x3_grad_input")
+                g = gx
+        return loss.value
+
+    def adam_step(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8):
+        self.t += 1
+        for k in range(len(self.params)):
+            _check(lib().mek_cnn_adam(self.params[k].numel(), _p(self.params[k]), _p(self.q[k]),
+                                      _p(self.g[k]), _p(self.m[k]), _p(self.v[k]), lr, beta1,
+                                      beta2, eps, self.t, _stream()), "mek_cnn_adam")
+
+    def train(self, C: torch.Tensor, labels: torch.Tensor, epochs: int, batch: int = 4,
+              lr: float = 1e-3, seed: int = 0) -> List[float]:
+        """Adam on (C, label) pairs (N, 3, H, W) float64; returns the mean
+        loss of each epoch. The order of the pairs is shuffled per epoch
+        from default_rng(seed)."""
+        rng = np.random.default_rng(seed)
+        n = C.shape[0]
+        hist = []
+        for ep in range(epochs):
+            order = rng.permutation(n)
+            tot = 0.0
+            for s in range(0, n - batch + 1, batch):
+                idx = torch.as_tensor(order[s:s + batch], device=self.device)
+                cb = C.index_select(0, idx).contiguous()
+                lb = labels.index_select(0, idx).contiguous()
+                # Step size halves over the last third of the epochs.
+                tot += self.loss_and_grads(cb, lb) * batch
+                self.adam_step(lr * (0.5 if ep >= (2 * epochs) // 3 else 1.0))
+            hist.append(tot / (n - n % batch))
+        return hist

@@ -25,7 +25,9 @@ def test_header_declares_the_boundary():
     names = _declared_functions()
     for want in ["mek_version", "mek_status_string", "mek_plan_create", "mek_plan_destroy",
                  "mek_plan_query", "mek_solve", "mek_solve_batched", "mek_philox_uniform", "mek_select",
-                 "mek_residual", "mek_residual_batched", "mek_gram", "mek_solve_multi"]:
+                 "mek_residual", "mek_residual_batched", "mek_gram", "mek_solve_multi",
+                 "mek_cnn_conv3x3", "mek_cnn_conv3x3_grad_input", "mek_cnn_conv3x3_grad_weight",
+                 "mek_cnn_mse_grad", "mek_cnn_adam", "mek_cnn_to_bf16", "mek_cnn_round_bf16"]:
         assert want in names
 
 
@@ -114,6 +116,14 @@ def test_host_validation_rejects_before_any_gpu_work():
     assert L.mek_residual(1, 1, 1, 1, vp(1), vp(1), vp(1), vp(1), vp(1), None) == EINVAL  # R aliases
     assert L.mek_residual_batched(0, 1, 1, 1, 1, vp(8), vp(8), vp(8), vp(8), vp(64), None) == EINVAL
     assert L.mek_solve_multi(0, None, None, None, None, None, None, None, None) == EINVAL
+    assert L.mek_cnn_conv3x3(1, 4, 8, 8, 32, vp(2), vp(4), None, 1, vp(8), None, None, None) == EINVAL
+    assert L.mek_cnn_conv3x3(1, 3, 8, 8, 32, vp(2), vp(4), None, 1, vp(8), vp(16), None, None) == EINVAL
+    assert L.mek_cnn_conv3x3(1, 3, 8, 8, 32, vp(2), vp(4), None, 1, vp(8), None, vp(8), None) == EINVAL
+    assert L.mek_cnn_conv3x3_grad_input(0, 32, 8, 8, 3, vp(2), None, vp(4), vp(8), None) == EINVAL
+    assert L.mek_cnn_conv3x3_grad_weight(1, 3, 8, 8, 7, vp(2), vp(2), None, vp(4), vp(4), None) == EINVAL
+    assert L.mek_cnn_mse_grad(0, vp(8), vp(8), None, ctypes.byref(ctypes.c_double()), None) == EINVAL
+    assert L.mek_cnn_adam(4, vp(4), vp(4), vp(4), vp(4), vp(4), 1e-3, 0.9, 0.999, 1e-8, 0, None) == EINVAL
+    assert L.mek_cnn_adam(4, vp(4), vp(4), vp(4), vp(4), vp(4), 1e-3, 1.0, 0.999, 1e-8, 1, None) == EINVAL
     assert L.mek_solve_multi(1, None, None, None, None, None, None, None, None) == EINVAL
     # R_1 (bytes 24..32) overlaps C_0..C_1 (bytes 16..32)
     assert L.mek_residual_batched(2, 1, 1, 1, 1, vp(1024), vp(2048), vp(4096), vp(16), vp(24),

@@ -133,3 +133,31 @@ def test_relu_mask_uses_the_layer_output():
     _, grads, dx = conv.backward(params, acts, label)
     assert np.all(grads[0][0] == 0.0) and np.all(grads[0][1] == 0.0)
     assert np.all(dx == 0.0)
+
+
+def test_bf16_rounding_closed_forms():
+    # 8-bit significand: spacing 2^-7 on [1, 2); halfway cases go to even.
+    cases = {1.0: 1.0, 1.0 + 2.0 ** -8: 1.0, 1.0 + 3 * 2.0 ** -8: 1.0 + 2.0 ** -6,
+             1.0 + 2.0 ** -7: 1.0 + 2.0 ** -7, 1.0 + 1.1 * 2.0 ** -8: 1.0 + 2.0 ** -7,
+             -3.0 - 2.0 ** -7: -3.0, 0.0: 0.0, 2.0 ** -130: 2.0 ** -130}
+    for x, r in cases.items():
+        assert conv.bf16(np.array([x]))[0] == r, x
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(1000)
+    y = conv.bf16(x)
+    # every result has at most 8 significant bits, and is within half a spacing
+    m, e = np.frexp(y)
+    assert np.all(m * 256 == np.round(m * 256))
+    assert np.all(np.abs(y - x) <= 2.0 ** -8 * np.abs(x) * (1 + 1e-6) + 1e-300)
+
+
+def test_forward_store_and_add():
+    rng = np.random.default_rng(7)
+    params = _net(rng)
+    x = rng.uniform(0, 1, (1, 3, 6, 6))
+    add = rng.standard_normal((1, 3, 6, 6))
+    a = conv.forward(params, x)
+    b = conv.forward(params, x, store=conv.bf16, add=add)
+    assert np.allclose(b[-1] - add, a[-1], rtol=0.05, atol=0.05)
+    for li in (1, 2, 3):
+        assert np.array_equal(conv.bf16(b[li]), b[li])

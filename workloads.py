@@ -239,6 +239,38 @@ def blurred_image(size: int, channels: int, sigma: float, seed: int,
 #            over work-groups (data seed 11).
 # --------------------------------------------------------------------------
 
+def warmstart_image(seed: int, size: int = 256, channels: int = 3, sigma_range=(1.0, 3.0),
+                    half_width: int = 4):
+    """One image of the learned-warm-start workload: sigma uniform on
+    sigma_range from default_rng(seed), then the synthetic image of
+    synthetic_image(seed + 1); A = blur_toeplitz(size, sigma), B = A^T,
+    C_c = A X*_c B without noise. Returns (A, B, C (channels, size, size),
+    X* (channels, size, size), sigma)."""
+    sigma = float(np.random.default_rng(seed).uniform(*sigma_range))
+    A = blur_toeplitz(size, sigma, half_width)
+    B = _c(A.T)
+    X = synthetic_image(size, size, channels, seed + 1)
+    C = np.stack([A @ X[c] @ B for c in range(channels)])
+    return A, B, _c(C), _c(X), sigma
+
+
+def bf16_bits(x) -> np.ndarray:
+    """BF16 bit patterns (uint16) of x rounded to nearest even (via FP32)."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+def bf16_values(bits) -> np.ndarray:
+    """The float64 values of BF16 bit patterns."""
+    return (np.asarray(bits, np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def bf16_random(rng, shape, scale=1.0) -> np.ndarray:
+    """N(0, scale^2) draws rounded to BF16 (float64 holding BF16 values)."""
+    return bf16_values(bf16_bits(scale * rng.standard_normal(shape)))
+
+
 def small(seed: int = 1) -> Instance:
     return gaussian_consistent(100, 40, 40, 100, seed, name="small 100x40 / 40x100")
 
