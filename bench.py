@@ -202,6 +202,57 @@ def ragged_batch_forms(mek, workloads, torch, nb=64, budget=10_000):
     return out
 
 
+def warm_start_forms(mek, workloads, torch, n_train=128, n_test=8, epochs=60, lr=2e-3,
+                     size=256, tau=1e-3):
+    """The learned warm start: 3-channel 256 x 256 blurred images (sigma
+    uniform on [1, 3], no noise; training seeds 100000 + i, held-out
+    200000 + j), labels = the FP64 ME-GRBK iterate at relative residual tau
+    (= 1e-3, the smallest of 1e-6..1e-3 that the X0 = 0 solve reaches
+    within 1e6 updates on held-out images 0-7), the network trained by the
+    library's BF16 kernels, then every held-out image solved to tau from
+    X0 = 0 and from X0 = C + f(C)."""
+    from paper_2408_05444_amd import warmstart
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    train = []
+    for i in range(n_train):
+        A, B, C, _, _ = workloads.warmstart_image(100000 + i, size=size)
+        train.append((t(A), t(B), t(C)))
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    labels = warmstart.solver_labels(mek, train, tau=tau, seed=2408054440)
+    torch.cuda.synchronize()
+    t_labels = time.perf_counter() - ts
+    Cs = torch.stack([c for _, _, c in train])
+    Ls = torch.stack(labels)
+    del train, labels
+    net = warmstart.WarmStartNet(seed=0)
+    ts = time.perf_counter()
+    hist = net.train(Cs, Ls, epochs=epochs, batch=4, lr=lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - ts
+    del Cs, Ls
+    rows = []
+    for j in range(n_test):
+        A, B, C, _, sigma = workloads.warmstart_image(200000 + j, size=size)
+        r = warmstart.compare_warm_start(mek, net, t(A), t(B), t(C), tau=tau, seed=2408054440)
+        r["sigma"] = sigma
+        rows.append(r)
+    iz = [i for r in rows for i in r["iters_zero"]]
+    iw = [i for r in rows for i in r["iters_warm"]]
+    tz = sum(r["time_zero_s"] for r in rows)
+    tw = sum(r["time_warm_s"] for r in rows)
+    return {"tau_rel_resid": tau, "train_images": n_train, "epochs": epochs, "params": net.num_params(),
+            "label_time_s": t_labels, "train_time_s": t_train, "loss_first_epoch": hist[0],
+            "loss_last_epoch": hist[-1], "held_out_images": n_test,
+            "mean_iters_zero": float(np.mean(iz)), "mean_iters_warm": float(np.mean(iw)),
+            "iters_ratio": float(np.mean(iw) / np.mean(iz)),
+            "time_to_tau_zero_s": tz, "time_to_tau_warm_s": tw, "time_ratio": tw / tz,
+            "all_reached_tau": all(s == 0 for r in rows for s in r["status_zero"] + r["status_warm"]),
+            "fallbacks": int(sum(sum(r["fallback"]) for r in rows)),
+            "mean_start_rel_resid_warm": float(np.mean([x for r in rows for x in r["start_rel_resid_warm"]]))}
+
+
 def cpu_baseline(inst, seed, updates=600):
     import oracle
     alpha = oracle.spectral_alpha(inst.B)
@@ -227,6 +278,8 @@ def main():
     ap.add_argument("--gemm-only", action="store_true",
                     help="only time the FP64 MFMA GEMMs of the set-up and residual engine at the "
                          "workload's sizes (for a kernel trace) and print them")
+    ap.add_argument("--warm-start-only", action="store_true",
+                    help="only run the learned warm-start form and print it")
     ap.add_argument("--ragged-only", action="store_true",
                     help="only run the uneven-instance batch form and print it")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -257,6 +310,9 @@ def main():
     A, B, C, Xs = t(inst.A), t(inst.B), t(inst.C), t(inst.X_star)
     seed = 2408054440
     torch.cuda.synchronize()
+    if args.warm_start_only:
+        print(json.dumps({"warm_start": warm_start_forms(mek, workloads, torch)}), flush=True)
+        return
     if args.ragged_only:
         print(json.dumps({"ragged64_fp32": ragged_batch_forms(mek, workloads, torch)}), flush=True)
         return
@@ -347,6 +403,7 @@ def main():
                              "kernel_us_per_step": r.kernel_ms * 1e3 / max(r.iters, 1)}
         forms["blur3_batched"] = blur_batch_forms(mek, workloads, torch)
         forms["ragged64_fp32"] = ragged_batch_forms(mek, workloads, torch)
+        forms["warm_start"] = warm_start_forms(mek, workloads, torch)
         line["forms"] = forms
         line["gemm_mfma_f64"] = gemm_forms(mek, torch, A, B, Xs, C,
                                            blur=blur_tensors(workloads, torch))

@@ -10,6 +10,7 @@ the C ABI; this module only sequences the calls and owns the buffers.
 from __future__ import annotations
 
 import ctypes
+import time
 from typing import List, Optional
 
 import numpy as np
@@ -145,3 +146,63 @@ class WarmStartNet:
                 self.adam_step(lr * (0.5 if ep >= (2 * epochs) // 3 else 1.0))
             hist.append(tot / (n - n % batch))
         return hist
+
+
+def solver_labels(mek, images, tau: float, max_iters: int = 1_000_000, seed: int = 0,
+                  chunk: int = 63):
+    """Training labels produced by the solver itself: for each image
+    (A, B, C) with C (3, H, W) on the GPU, the FP64 ME-GRBK iterate from
+    X0 = 0 at relative residual ||C - A X B||_F <= tau ||C||_F (or after
+    max_iters), every channel an instance of ragged launches of up to
+    `chunk` instances. Returns a list of (3, H, W) tensors."""
+    inst = [(i, c) for i in range(len(images)) for c in range(images[i][2].shape[0])]
+    out = [torch.empty_like(images[i][2]) for i in range(len(images))]
+    for s0 in range(0, len(inst), chunk):
+        part = inst[s0:s0 + chunk]
+        plans = [mek.mek_plan_create(images[i][0], images[i][1]) for i, _ in part]
+        try:
+            _, res = mek.mek_solve_multi(plans, [images[i][2][c].contiguous() for i, c in part],
+                                         variant="grbk", stop="rel_resid", tol=tau,
+                                         max_iters=max_iters, seed=seed, instance=s0)
+            for (i, c), r in zip(part, res):
+                out[i][c].copy_(r.X)
+        finally:
+            for P in plans:
+                mek.mek_plan_destroy(P)
+    return out
+
+
+def compare_warm_start(mek, net: WarmStartNet, A, B, C, tau: float, max_iters: int = 1_000_000,
+                       seed: int = 0):
+    """Solve the channels of one image (uniform batch sharing A and B) to
+    relative residual tau from X0 = 0 and from X0 = C + f(C). A channel
+    falls back to X0 = 0 when ||C - A X0 B||_F >= ||C||_F. Returns a dict of
+    iterations, times, start residuals and fallbacks."""
+    plan = mek.mek_plan_create(A, B)
+    try:
+        kw = dict(variant="grbk", stop="rel_resid", tol=tau, max_iters=max_iters, seed=seed)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, base = mek.mek_solve_batched(plan, C, **kw)
+        torch.cuda.synchronize()
+        t_base = time.perf_counter() - ts
+        ts = time.perf_counter()
+        X0 = net.predict(C.unsqueeze(0).contiguous())[0].contiguous()
+        # The judge of the prediction: the residual it leaves (no update made).
+        _, r0 = mek.mek_solve_batched(plan, C, X0=X0, max_iters=0)
+        _, z0 = mek.mek_solve_batched(plan, C, max_iters=0)
+        fallback = [r0[c].resid2 >= z0[c].resid2 for c in range(C.shape[0])]
+        for c, fb in enumerate(fallback):
+            if fb:
+                X0[c].zero_()
+        _, warm = mek.mek_solve_batched(plan, C, X0=X0, **kw)
+        torch.cuda.synchronize()
+        t_warm = time.perf_counter() - ts
+        return {"iters_zero": [r.iters for r in base], "iters_warm": [r.iters for r in warm],
+                "status_zero": [r.status for r in base], "status_warm": [r.status for r in warm],
+                "time_zero_s": t_base, "time_warm_s": t_warm,
+                "start_rel_resid_warm": [float(np.sqrt(r0[c].resid2 / z0[c].resid2))
+                                         for c in range(C.shape[0])],
+                "fallback": fallback}
+    finally:
+        mek.mek_plan_destroy(plan)
