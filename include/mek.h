@@ -207,6 +207,30 @@ int mek_solve(mek_plan plan, const double* C, const double* X0, const mek_solve_
 int mek_solve_batched(mek_plan plan, int64_t batch, const double* C, const double* X0,
                       const mek_solve_opts* opts, double* X, mek_report* reports, void* stream);
 
+/* The report of a stream-ordered solve, in device memory. */
+typedef struct mek_device_report {
+    int64_t iters;    /* updates made */
+    int32_t status;   /* MEK_OK, MEK_MAXITER, MEK_EXACT, MEK_EDIVERGED, ... */
+    int32_t last_set; /* size of the last index set (GRBK/RGRBK) */
+    double resid2;    /* ||R||_F^2 at exit */
+    double rel_err;   /* ||X - X_ref||_F / ||X_ref||_F at exit, NaN without X_ref */
+} mek_device_report;
+
+/* Stream-ordered solve of Alg. 3 (and the other variants) for one instance:
+ * the same iteration and result as mek_solve, but every step (residual,
+ * norms, transposes, the persistent launch, X) is enqueued on `stream` and
+ * the call returns without waiting; the report is written to dev_report
+ * (device memory) when the stream reaches it. Nothing in the call reads
+ * device data on the host, so once the plan's workspace exists (after one
+ * call of any solve on the plan) it can be captured into a graph. FP64 and
+ * FP32 plans; MIXED, the two-sided variant and replay_idx return
+ * MEK_EUNSUPPORTED. No finite check of the inputs is made (non-finite data
+ * ends in MEK_EDIVERGED or a non-finite report). X, the histories and the
+ * plan's workspace must not be touched until the stream has passed the
+ * call; calls on one plan must be ordered on one stream. */
+int mek_solve_async(mek_plan plan, const double* C, const double* X0, const mek_solve_opts* opts,
+                    double* X, mek_device_report* dev_report, void* stream);
+
 /* Ragged batch: solve A_b X_b B_b = C_b for b < batch, each instance with
  * its own plan plans[b] (own sizes m_b, p_b, q_b, n_b; every plan distinct,
  * all of one precision, FP64 or FP32, on one device), in one persistent

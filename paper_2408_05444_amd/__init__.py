@@ -98,6 +98,8 @@ def lib() -> ctypes.CDLL:
         L.mek_solve_multi.argtypes = [i64, vp, vp, vp, vp, ctypes.POINTER(mek_solve_opts), vp,
                                       vp, vp]
         L.mek_solve_multi.restype = ci
+        L.mek_solve_async.argtypes = [vp, vp, vp, ctypes.POINTER(mek_solve_opts), vp, vp, vp]
+        L.mek_solve_async.restype = ci
         L.mek_cnn_conv3x3.argtypes = [i64, i64, i64, i64, i64, vp, vp, vp, ci, vp, vp, vp, vp]
         L.mek_cnn_conv3x3.restype = ci
         L.mek_cnn_conv3x3_grad_input.argtypes = [i64, i64, i64, i64, i64, vp, vp, vp, vp, vp]
@@ -335,6 +337,56 @@ def mek_solve_batched(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = 
         raise MekError(code, "mek_solve_batched")
     return int(code), [_result(X[b], reps[b].status, reps[b], hists, b, hist_cap)
                        for b in range(nb)]
+
+
+DEVICE_REPORT_BYTES = 32   # mek_device_report: int64 iters, int32 status, int32 last_set,
+                           # double resid2, double rel_err
+
+
+def mek_solve_async(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = None,
+                    variant="grbk", theta: float = 0.5, alpha: float = 0.0, stop="none",
+                    tol: float = 0.0, X_ref: Optional[torch.Tensor] = None,
+                    max_iters: int = 100000, seed: int = 0, instance: int = 0,
+                    diverge: float = 0.0, X_out: Optional[torch.Tensor] = None,
+                    report: Optional[torch.Tensor] = None, hist: Optional[dict] = None):
+    """Stream-ordered solve on the current stream; returns (X, report) where
+    report is a 32-byte device tensor holding mek_device_report (decode it
+    with read_device_report once the stream has passed the call). With
+    `hist` (a dict from make_histories) the histories are recorded there."""
+    m, p, q, n = plan.m, plan.p, plan.q, plan.n
+    dev = C.device
+    X = X_out if X_out is not None else torch.empty(p, q, dtype=torch.float64, device=dev)
+    rep = report if report is not None else torch.zeros(DEVICE_REPORT_BYTES, dtype=torch.uint8,
+                                                        device=dev)
+    o, _ = _solve_opts(1, dev, variant, theta, alpha, stop, tol,
+                       _dev(X_ref, shape=(p, q), name="X_ref"), max_iters, seed, instance, None,
+                       diverge, 0, 0)
+    if hist is not None:
+        o.hist_cap = hist["cap"]
+        o.resid_hist = _dev(hist["resid_hist"])
+        o.err_hist = _dev(hist["err_hist"])
+        o.idx_hist = _dev(hist["idx_hist"], dtype=torch.int32)
+        o.set_hist = _dev(hist["set_hist"], dtype=torch.int32)
+    _check(lib().mek_solve_async(plan.handle, _dev(C, shape=(m, n), name="C"),
+                                 _dev(X0, shape=(p, q), name="X0"), ctypes.byref(o),
+                                 _dev(X, shape=(p, q), name="X"), _dev(rep, dtype=torch.uint8),
+                                 _stream()), "mek_solve_async")
+    return X, rep
+
+
+def make_histories(cap: int, device="cuda") -> dict:
+    """Device history buffers for mek_solve_async (cap entries each)."""
+    return {"cap": cap,
+            "resid_hist": torch.full((cap,), float("nan"), dtype=torch.float64, device=device),
+            "err_hist": torch.full((cap,), float("nan"), dtype=torch.float64, device=device),
+            "idx_hist": torch.full((cap,), -1, dtype=torch.int32, device=device),
+            "set_hist": torch.zeros(cap, dtype=torch.int32, device=device)}
+
+
+def read_device_report(rep: torch.Tensor) -> dict:
+    import struct
+    it, st, ls, r2, err = struct.unpack("<qiidd", bytes(rep.cpu().tolist()))
+    return {"iters": it, "status": st, "last_set": ls, "resid2": r2, "rel_err": err}
 
 
 def _ptr_array(tensors, shapes, name):

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <mutex>
 #include <vector>
 
@@ -72,6 +73,13 @@ struct mek_plan_s {
     float *A32 = nullptr, *B32 = nullptr, *BT32 = nullptr, *GA32 = nullptr, *GB32 = nullptr;
     Workspace ws;
 };
+
+static_assert(sizeof(mek_device_report) == sizeof(DevReport), "device report layout");
+static_assert(offsetof(mek_device_report, iters) == offsetof(DevReport, iters) &&
+                  offsetof(mek_device_report, status) == offsetof(DevReport, status) &&
+                  offsetof(mek_device_report, resid2) == offsetof(DevReport, S) &&
+                  offsetof(mek_device_report, rel_err) == offsetof(DevReport, err),
+              "device report layout");
 
 namespace {
 
@@ -341,6 +349,7 @@ void fill_common(SolveParams<T>& K, const mek_plan_s* P, const mek_solve_opts* o
     K.hist_offset = 0;
     K.nb = 1;
     K.slots = nullptr;
+    K.norms = nullptr;
     K.multi = nullptr;
     K.multi_start = nullptr;
     K.multi_n = 0;
@@ -1309,9 +1318,116 @@ int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
     return ret;
 }
 
+// Stream-ordered solve (FP64 / FP32, one instance): every step is a kernel
+// or a device copy on the stream, nothing waits on the host, and the kernel
+// writes its report to the caller's device struct, so the call can be
+// captured into a graph once the plan's workspace exists.
+template <typename T>
+int enqueue_solve(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, const double* C,
+                  const double* X0, double* X, DevReport* dev_report, hipStream_t s) {
+    Workspace& w = P->ws;
+    const int64_t m = P->m, p = P->p, q = P->q, n = P->n;
+    // ||C||^2 and ||X_ref||^2 (0 without a reference) into the scalar slots
+    // the kernel reads at its start.
+    MEK_TRY(sq_norm(C, m * n, w.scal + 2, w.red, s));
+    if (o->X_ref) {
+        MEK_TRY(sq_norm(o->X_ref, p * q, w.scal + 3, w.red, s));
+        MEK_TRY(transpose_to<double>(o->X_ref, (int)p, (int)q, w.Xref_t, s));
+    } else {
+        MEK_TRY(fill_zero_bytes(w.scal + 3, 8, s));
+    }
+    if (X0) {
+        MEK_TRY(gemm_f64((int)m, (int)q, (int)p, 1.0, P->A, p, 1, X0, q, 1, 0.0, nullptr, 0, w.T64,
+                         q, s));
+        MEK_TRY(gemm_f64((int)m, (int)n, (int)q, -1.0, w.T64, q, 1, P->B, n, 1, 1.0, C, n, w.R64, n,
+                         s));
+    } else {
+        MEK_TRY(copy_f64(C, m * n, w.R64, s));
+    }
+    T* R = (T*)w.R64;
+    T* Xt = (T*)w.Xt64;
+    if (sizeof(T) == 4) {
+        MEK_TRY(convert_f64_f32(w.R64, m * n, w.R32, s));
+        R = (T*)w.R32;
+        Xt = (T*)w.Xt32;
+    }
+    if (X0) MEK_TRY(transpose_to<T>(X0, (int)p, (int)q, Xt, s));
+    else MEK_TRY(fill_zero_bytes(Xt, (long long)(p * q) * (long long)sizeof(T), s));
+    SolveParams<T> K;
+    fill_common(K, P, o, L, o->alpha > 0.0 ? o->alpha : P->alpha);
+    if (sizeof(T) == 8) {
+        K.A = (const T*)P->A;
+        K.B = (const T*)P->B;
+        K.BT = (const T*)P->BT;
+        K.GA = (const T*)P->GA;
+        K.GB = (const T*)P->GB;
+    } else {
+        K.A = (const T*)P->A32;
+        K.B = (const T*)P->B32;
+        K.BT = (const T*)P->BT32;
+        K.GA = (const T*)P->GA32;
+        K.GB = (const T*)P->GB32;
+    }
+    K.R = R;
+    K.Xt = Xt;
+    K.Xref_t = o->X_ref ? w.Xref_t : nullptr;
+    K.norms = w.scal + 2;
+    K.C2 = 1.0;
+    K.ref2 = 1.0;
+    K.S_target = 0.0;
+    K.report = dev_report;
+    K.phase = nullptr;
+    K.a_in_lds = L.a_lds ? 1 : 0;
+    K.x_in_lds = L.x_lds ? 1 : 0;
+    static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
+    K.poll_sleep = poll_sleep;
+    MEK_TRY(fill_zero_bytes(w.sync, (long long)sizeof(TeamSync), s));
+    MEK_TRY(fill_zero_bytes(w.errpart, kErrStride * 8, s));
+    MEK_TRY(fill_zero_bytes(w.r, m * 8, s));
+    MEK_TRY(fill_zero_bytes((char*)w.rowbuf, n * 8, s));
+    MEK_TRY(fill_zero_bytes((char*)w.wbuf, n * 8, s));
+    MEK_TRY(fill_zero_bytes((char*)w.vbuf, q * 8, s));
+    MEK_TRY(launch_solve(K, L.lds, L.lds_bytes, s));
+    MEK_TRY(transpose_from<T>(Xt, (int)p, (int)q, X, s));
+    return MEK_OK;
+}
+
+int solve_async_impl(mek_plan P, const double* C, const double* X0, const mek_solve_opts* o,
+                     double* X, void* dev_report, hipStream_t s) {
+    if (!P || !C || !X || !dev_report || !o) return MEK_EINVAL;
+    if (P->precision == MEK_MIXED || o->variant == MEK_TWOSIDED || o->replay_len > 0)
+        return MEK_EUNSUPPORTED;
+    int st = validate_opts(P, o);
+    if (st) return st;
+    const int64_t m = P->m, p = P->p, q = P->q, n = P->n;
+    const size_t mn = (size_t)(m * n), pq = (size_t)(p * q);
+    if ((st = check_dev(C, mn * 8)) || (X0 && (st = check_dev(X0, pq * 8))) ||
+        (st = check_dev(X, pq * 8)) || (o->X_ref && (st = check_dev(o->X_ref, pq * 8))) ||
+        (st = check_dev(dev_report, sizeof(DevReport))))
+        return st;
+    if (o->hist_cap > 0) {
+        const size_t hc = (size_t)o->hist_cap;
+        if (o->resid_hist && (st = check_dev(o->resid_hist, hc * 8))) return st;
+        if (o->err_hist && (st = check_dev(o->err_hist, hc * 8))) return st;
+        if (o->idx_hist && (st = check_dev(o->idx_hist, hc * 4))) return st;
+        if (o->set_hist && (st = check_dev(o->set_hist, hc * 4))) return st;
+    }
+    Layout L;
+    const bool f64 = P->precision == MEK_FP64;
+    if ((st = choose_layout(P, f64 ? 8 : 4, 1, &L))) return st;
+    if ((st = ensure_workspace(P, 1))) return st;
+    return f64 ? enqueue_solve<double>(P, o, L, C, X0, X, (DevReport*)dev_report, s)
+               : enqueue_solve<float>(P, o, L, C, X0, X, (DevReport*)dev_report, s);
+}
+
 }  // namespace
 
 extern "C" {
+
+int mek_solve_async(mek_plan P, const double* C, const double* X0, const mek_solve_opts* o,
+                    double* X, mek_device_report* dev_report, void* stream) {
+    return solve_async_impl(P, C, X0, o, X, dev_report, (hipStream_t)stream);
+}
 
 int mek_solve_multi(int64_t nb, const mek_plan* plans, const double* const* C,
                     const double* const* X0, const double* const* X_ref,

@@ -68,6 +68,8 @@ struct SolveParams {
     const double* Xref_t;  // q x p or null
     double ref2;       // ||X_ref||_F^2
     double C2;         // ||C||_F^2 (REL_RESID denominator, squared)
+    const double* norms;   // optional: {||C||_F^2, ||X_ref||_F^2} read from device memory at
+                           // the start instead of C2 and ref2 (0 for ref2 means no reference)
     double* r;         // m row norms of R
     T* rowbuf;         // n, the published row R_{i_k}
     T* vbuf;           // q, v = R_{i_k} B^T

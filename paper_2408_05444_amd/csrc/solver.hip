@@ -301,6 +301,10 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         g -= b * P.W;
         bind_instance(P, b);
     }
+    if (P.norms) {   // stream-ordered solves: the norms were computed on the device
+        P.C2 = P.norms[0];
+        P.ref2 = P.norms[1] > 0.0 ? P.norms[1] : 1.0;
+    }
     const int W = P.W;
     const bool team = W > 1;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;

@@ -25,7 +25,7 @@ def test_header_declares_the_boundary():
     names = _declared_functions()
     for want in ["mek_version", "mek_status_string", "mek_plan_create", "mek_plan_destroy",
                  "mek_plan_query", "mek_solve", "mek_solve_batched", "mek_philox_uniform", "mek_select",
-                 "mek_residual", "mek_residual_batched", "mek_gram", "mek_solve_multi",
+                 "mek_residual", "mek_residual_batched", "mek_gram", "mek_solve_multi", "mek_solve_async",
                  "mek_cnn_conv3x3", "mek_cnn_conv3x3_grad_input", "mek_cnn_conv3x3_grad_weight",
                  "mek_cnn_mse_grad", "mek_cnn_adam", "mek_cnn_to_bf16", "mek_cnn_round_bf16"]:
         assert want in names
@@ -116,6 +116,7 @@ def test_host_validation_rejects_before_any_gpu_work():
     assert L.mek_residual(1, 1, 1, 1, vp(1), vp(1), vp(1), vp(1), vp(1), None) == EINVAL  # R aliases
     assert L.mek_residual_batched(0, 1, 1, 1, 1, vp(8), vp(8), vp(8), vp(8), vp(64), None) == EINVAL
     assert L.mek_solve_multi(0, None, None, None, None, None, None, None, None) == EINVAL
+    assert L.mek_solve_async(None, vp(8), None, None, vp(8), vp(8), None) == EINVAL
     assert L.mek_cnn_conv3x3(1, 4, 8, 8, 32, vp(2), vp(4), None, 1, vp(8), None, None, None) == EINVAL
     assert L.mek_cnn_conv3x3(1, 3, 8, 8, 32, vp(2), vp(4), None, 1, vp(8), vp(16), None, None) == EINVAL
     assert L.mek_cnn_conv3x3(1, 3, 8, 8, 32, vp(2), vp(4), None, 1, vp(8), None, vp(8), None) == EINVAL
