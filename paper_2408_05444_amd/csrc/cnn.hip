@@ -189,13 +189,26 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
     }
 }
 
-// out[e] = sum over the T tile partials of entry e, in tile order.
+// Two-level fixed-order sum of the T tile partials of each entry e: block
+// (x, k) sums tiles [k T / S, (k + 1) T / S) in tile order into mid[k][e],
+// then mid is summed over k in order.
 __global__ void sum_partials_kernel(const float* __restrict__ partial, long long T, long long E,
-                                    float* __restrict__ dw, float* __restrict__ db, long long nw) {
+                                    int S, float* __restrict__ mid) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const long long k = blockIdx.y;
+    const long long t0 = k * T / S, t1 = (k + 1) * T / S;
+    float s = 0.0f;
+    for (long long t = t0; t < t1; ++t) s += partial[t * E + e];
+    mid[k * E + e] = s;
+}
+
+__global__ void sum_mid_kernel(const float* __restrict__ mid, int S, long long E,
+                               float* __restrict__ dw, float* __restrict__ db, long long nw) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
     float s = 0.0f;
-    for (long long t = 0; t < T; ++t) s += partial[t * E + e];
+    for (int k = 0; k < S; ++k) s += mid[(long long)k * E + e];
     if (e < nw) dw[e] = s;
     else db[e - nw] = s;
 }
@@ -273,9 +286,11 @@ hipError_t conv_dispatch(int N, int Cin, int H, int W, int Cout, const uint16_t*
 
 bool cnn_channels_ok(int64_t c) { return c == 3 || c == 32; }
 
+constexpr int kSumSplits = 64;   // chunks of the first summation level
+
 size_t cnn_wgrad_partial_floats(int N, int Cin, int H, int W, int Cout) {
     const size_t tiles = (size_t)((H + kCT - 1) / kCT) * ((W + kCT - 1) / kCT);
-    return tiles * N * ((size_t)Cout * Cin * 9 + Cout);
+    return (tiles * N + kSumSplits) * ((size_t)Cout * Cin * 9 + Cout);
 }
 
 hipError_t cnn_conv3x3(int N, int Cin, int H, int W, int Cout, const uint16_t* x,
@@ -311,8 +326,15 @@ hipError_t cnn_conv3x3_grad_weight(int N, int Cin, int H, int W, int Cout, const
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long nw = (long long)Cout * Cin * 9, E = nw + Cout;
-    hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s,
-                       partial, (long long)tiles * N, E, dw, db, nw);
+    const long long T = (long long)tiles * N;
+    const int S = (int)std::min<long long>(T, kSumSplits);
+    float* mid = partial + T * E;   // the buffer holds (T + kSumSplits) E floats
+    hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((E + 255) / 256), S), dim3(256), 0, s,
+                       partial, T, E, S, mid);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_mid_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s, mid, S,
+                       E, dw, db, nw);
     return hipGetLastError();
 }
 
