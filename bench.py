@@ -32,7 +32,8 @@ def algorithmic_bytes_per_update(m, p, q, n, elem):
     return (2 * m * n + 2 * p * q + 2 * q * n + m + n + p) * elem
 
 
-KERNEL_SOURCES = ["paper_2408_05444_amd/csrc/solver.hip", "paper_2408_05444_amd/csrc/exchange.h",
+KERNEL_SOURCES = ["paper_2408_05444_amd/csrc/solver.hip", "paper_2408_05444_amd/csrc/select.h",
+                  "paper_2408_05444_amd/csrc/exchange.h",
                   "paper_2408_05444_amd/csrc/device_common.h"]
 
 
@@ -162,7 +163,74 @@ def blur_batch_forms(mek, workloads, torch):
             out[prec]["rel_diff_vs_fp64_same_indices"] = float(
                 torch.linalg.norm(Xm - X64r) / torch.linalg.norm(X64r))
             out[prec]["passes"] = res[0].passes
+    # The sparse-aware update on the same channels, variant, budget and draws:
+    # one work-group per channel.
+    plan = mek.mek_plan_create(A, B, update="sparse")
+    kw = dict(variant="rgrbk", theta=0.8, max_iters=K, X_ref=Xs, seed=2408054440, hist_cap=K)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    code, res = mek.mek_solve_batched(plan, C, **kw)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - ts
+    its = sum(r.iters for r in res)
+    Xsp = torch.stack([r.X for r in res])
+    same = int((res[0].idx_hist.to(torch.int32) == ref).sum())
+    ka, kb, kbt, kg = mek.mek_plan_sparse_widths(plan)
+    out["sparse_fp64"] = {
+        "time_s": te, "iters_per_s": its / te, "work_groups": len(res),
+        "rel_err_vs_image": [r.rel_err for r in res],
+        "kernel_us_per_update": res[0].kernel_ms * 1e3 / max(res[0].iters, 1),
+        "widths": [ka, kb, kbt, kg],
+        "algorithmic_bytes_per_update": sparse_update_bytes(512, 512, 512, 512, ka, kb, kbt, kg),
+        "rel_diff_vs_dense_fp64": float(torch.linalg.norm(Xsp - X64) / torch.linalg.norm(X64)),
+        "same_indices_as_dense_channel0": same / K}
+    mek.mek_plan_destroy(plan)
     return out
+
+
+def sparse_update_bytes(m, p, q, n, ka, kb, kbt, kg, elem=8):
+    """Bytes one sparse-aware update moves: R_{i_k} read (n), the index and
+    value of every ELL slot of B's rows and columns (q kb + n kbt), the
+    changed rows of X read and written plus X_ref read (3 ka q) and the
+    changed rows of R read and written (2 kg n)."""
+    return elem * n + (elem + 4) * (q * kb + n * kbt) + 3 * elem * ka * q + 2 * elem * kg * n
+
+
+def sparse_many_forms(mek, workloads, torch, n_images=32, budget=100 * 512):
+    """Many images at once with the sparse-aware update: n_images distinct
+    3-channel 512 x 512 synthetic images (seeds 100..), the blur of the
+    image form (sigma 2, 9 taps, noise 1e-3), every channel one instance of
+    one launch (one work-group each), ME-RGRBK theta 0.8, `budget` updates
+    per channel."""
+    dev = torch.device("cuda:0")
+    Cs, Xs = [], []
+    for i in range(n_images):
+        for ch in workloads.blurred_image(512, 3, 2.0, seed=100 + i, noise_std=1e-3):
+            Cs.append(ch.C)
+            Xs.append(ch.X_star)
+    A = torch.from_numpy(ch.A).to(dev)
+    B = torch.from_numpy(ch.B).to(dev)
+    C = torch.from_numpy(np.stack(Cs)).to(dev)
+    X = torch.from_numpy(np.stack(Xs)).to(dev)
+    del Cs, Xs
+    plan = mek.mek_plan_create(A, B, update="sparse")
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    code, res = mek.mek_solve_batched(plan, C, variant="rgrbk", theta=0.8, max_iters=budget,
+                                      X_ref=X, seed=2408054440)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - ts
+    its = sum(r.iters for r in res)
+    ka, kb, kbt, kg = mek.mek_plan_sparse_widths(plan)
+    per = sparse_update_bytes(512, 512, 512, 512, ka, kb, kbt, kg)
+    kms = res[0].kernel_ms
+    mek.mek_plan_destroy(plan)
+    return {"instances": len(res), "budget_per_instance": budget, "time_s": te,
+            "iters_per_s": its / te, "kernel_ms": kms,
+            "all_ran_budget": all(r.iters == budget for r in res),
+            "mean_rel_err_vs_image": float(np.mean([r.rel_err for r in res])),
+            "algorithmic_bytes_per_update": per,
+            "achieved_GB_s": per * its / (kms * 1e-3) / 1e9}
 
 
 def ragged_batch_forms(mek, workloads, torch, nb=64, budget=10_000):
@@ -280,6 +348,8 @@ def main():
                          "workload's sizes (for a kernel trace) and print them")
     ap.add_argument("--warm-start-only", action="store_true",
                     help="only run the learned warm-start form and print it")
+    ap.add_argument("--sparse-only", action="store_true",
+                    help="only run the image forms (dense and sparse-aware updates) and print them")
     ap.add_argument("--ragged-only", action="store_true",
                     help="only run the uneven-instance batch form and print it")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -312,6 +382,11 @@ def main():
     torch.cuda.synchronize()
     if args.warm_start_only:
         print(json.dumps({"warm_start": warm_start_forms(mek, workloads, torch)}), flush=True)
+        return
+    if args.sparse_only:
+        print(json.dumps({"blur3_batched": blur_batch_forms(mek, workloads, torch),
+                          "blur_sparse_96ch": sparse_many_forms(mek, workloads, torch)}),
+              flush=True)
         return
     if args.ragged_only:
         print(json.dumps({"ragged64_fp32": ragged_batch_forms(mek, workloads, torch)}), flush=True)
@@ -402,6 +477,7 @@ def main():
                              "status": r.status,
                              "kernel_us_per_step": r.kernel_ms * 1e3 / max(r.iters, 1)}
         forms["blur3_batched"] = blur_batch_forms(mek, workloads, torch)
+        forms["blur_sparse_96ch"] = sparse_many_forms(mek, workloads, torch)
         forms["ragged64_fp32"] = ragged_batch_forms(mek, workloads, torch)
         forms["warm_start"] = warm_start_forms(mek, workloads, torch)
         line["forms"] = forms

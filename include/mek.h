@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define MEK_ABI_VERSION 2
+#define MEK_ABI_VERSION 3
 
 /* Selection rules (Algs. 1-5), and the two-sided block projection. */
 #define MEK_BK 0
@@ -73,6 +73,17 @@ extern "C" {
 #define MEK_FP64 0
 #define MEK_FP32 1
 #define MEK_MIXED 2
+
+/* How an update is applied (mek_plan_opts.update). DENSE: every row of R
+ * and X, the work of an update split over a team of work-groups. SPARSE:
+ * only the rows of X where A_{i_k} is nonzero and the rows of R where
+ * column i_k of A A^T is nonzero, with v = R_{i_k} B^T and w = v B summed
+ * over the nonzeros of B; the terms left out are exactly zero, so the
+ * iteration is the same (Alg. 3's update with its zero terms skipped). One
+ * work-group runs each instance. For banded or otherwise sparse A and B
+ * (a blur), where an update touches a few rows instead of all of them. */
+#define MEK_UPDATE_DENSE 0
+#define MEK_UPDATE_SPARSE 1
 
 /* Status codes. */
 #define MEK_OK 0            /* stop rule met */
@@ -98,6 +109,13 @@ typedef struct {
                         solve (testing and tuning hook) */
     int r_in_lds;    /* -1: automatic; 0: keep R in device memory; 1: require R
                         resident in LDS (MEK_EUNSUPPORTED if it does not fit) */
+    int update;      /* MEK_UPDATE_DENSE (0) or MEK_UPDATE_SPARSE. A SPARSE plan
+                        takes FP64 or FP32 (MEK_MIXED: MEK_EUNSUPPORTED) and
+                        finds the nonzeros of A, B and A A^T at creation;
+                        MEK_EUNSUPPORTED when a row of A or A A^T, or a row or
+                        column of B, holds more than 1024 nonzeros, or when
+                        the per-instance state (8 (m + p) + 16 n + 8 q bytes
+                        plus 1 KiB) exceeds the LDS of one work-group */
 } mek_plan_opts;
 
 typedef struct {
@@ -182,6 +200,12 @@ int mek_plan_destroy(mek_plan plan);
 int mek_plan_query(mek_plan plan, double* row_norms, double* gram_a, double* gram_b,
                    double* alpha, void* stream);
 
+/* Nonzeros per line of a SPARSE plan's structure (host array of 4):
+ * widths[0] = max over rows of A, [1] = over rows of B, [2] = over columns
+ * of B, [3] = over columns of A A^T (an update touches widths[0] rows of X
+ * and widths[3] rows of R at most). MEK_EUNSUPPORTED for a DENSE plan. */
+int mek_plan_sparse_widths(mek_plan plan, int32_t* widths);
+
 /* Solve A X B = C with the plan's A and B. C (m x n), X0 (p x q, NULL means
  * zero) and X (p x q, output) are device pointers; X may alias X0. Runs
  * the whole iteration on the GPU in one persistent launch (MIXED: one per
@@ -203,7 +227,10 @@ int mek_solve(mek_plan plan, const double* C, const double* X0, const mek_solve_
  * launch(es). Returns a negative code if the call failed (nothing written)
  * or an instance failed; otherwise MEK_OK when every instance met the stop
  * rule, else the status of the first one that did not. Errors as mek_solve,
- * and MEK_EUNSUPPORTED when batch exceeds the device's compute units. */
+ * and MEK_EUNSUPPORTED when batch exceeds the device's compute units.
+ * With a SPARSE plan each instance is one work-group of one launch, and the
+ * batch is not bounded by the compute units (work-groups beyond them wait
+ * for a free one); the two-sided variant returns MEK_EUNSUPPORTED. */
 int mek_solve_batched(mek_plan plan, int64_t batch, const double* C, const double* X0,
                       const mek_solve_opts* opts, double* X, mek_report* reports, void* stream);
 
@@ -223,8 +250,8 @@ typedef struct mek_device_report {
  * (device memory) when the stream reaches it. Nothing in the call reads
  * device data on the host, so once the plan's workspace exists (after one
  * call of any solve on the plan) it can be captured into a graph. FP64 and
- * FP32 plans; MIXED, the two-sided variant and replay_idx return
- * MEK_EUNSUPPORTED. No finite check of the inputs is made (non-finite data
+ * FP32 plans; MIXED and SPARSE plans, the two-sided variant and replay_idx
+ * return MEK_EUNSUPPORTED. No finite check of the inputs is made (non-finite data
  * ends in MEK_EDIVERGED or a non-finite report). X, the histories and the
  * plan's workspace must not be touched until the stream has passed the
  * call; calls on one plan must be ordered on one stream. */
@@ -246,8 +273,8 @@ int mek_solve_async(mek_plan plan, const double* C, const double* X0, const mek_
  * (references come through X_ref); each history holds batch x hist_cap
  * entries, instance b from b * hist_cap. Returns as mek_solve_batched.
  * Errors: MEK_EINVAL for bad arguments, a repeated plan or mixed
- * precisions; MEK_EUNSUPPORTED for MEK_MIXED plans, replay_idx, the
- * two-sided variant or batch above the compute units. */
+ * precisions; MEK_EUNSUPPORTED for MEK_MIXED or SPARSE plans, replay_idx,
+ * the two-sided variant or batch above the compute units. */
 int mek_solve_multi(int64_t batch, const mek_plan* plans, const double* const* C,
                     const double* const* X0, const double* const* X_ref,
                     const mek_solve_opts* opts, double* const* X, mek_report* reports,

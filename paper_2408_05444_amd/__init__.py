@@ -27,6 +27,8 @@ VARIANTS = {"bk": MEK_BK, "rbk": MEK_RBK, "grbk": MEK_GRBK, "rgrbk": MEK_RGRBK, 
 MEK_STOP_NONE, MEK_STOP_REL_ERR, MEK_STOP_REL_RESID = 0, 1, 2
 STOPS = {"none": 0, "rel_err": 1, "rel_resid": 2}
 MEK_FP64, MEK_FP32, MEK_MIXED = 0, 1, 2
+MEK_UPDATE_DENSE, MEK_UPDATE_SPARSE = 0, 1
+UPDATES = {"dense": MEK_UPDATE_DENSE, "sparse": MEK_UPDATE_SPARSE}
 PRECISIONS = {"fp64": 0, "fp32": 1, "mixed": 2}
 MEK_OK, MEK_MAXITER, MEK_EXACT = 0, 1, 2
 MEK_EINVAL, MEK_ENOMEM, MEK_EHIP, MEK_ENONFINITE = -1, -2, -3, -4
@@ -41,7 +43,8 @@ class MekError(RuntimeError):
 
 class mek_plan_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("alpha", ctypes.c_double),
-                ("team_wgs", ctypes.c_int), ("r_in_lds", ctypes.c_int)]
+                ("team_wgs", ctypes.c_int), ("r_in_lds", ctypes.c_int),
+                ("update", ctypes.c_int)]
 
 
 class mek_solve_opts(ctypes.Structure):
@@ -89,6 +92,8 @@ def lib() -> ctypes.CDLL:
         L.mek_plan_destroy.restype = ci
         L.mek_plan_query.argtypes = [vp, vp, vp, vp, ctypes.POINTER(d), vp]
         L.mek_plan_query.restype = ci
+        L.mek_plan_sparse_widths.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.mek_plan_sparse_widths.restype = ci
         L.mek_solve.argtypes = [vp, vp, vp, ctypes.POINTER(mek_solve_opts), vp,
                                 ctypes.POINTER(mek_report), vp]
         L.mek_solve.restype = ci
@@ -179,11 +184,14 @@ class Plan:
 
 
 def mek_plan_create(A: torch.Tensor, B: torch.Tensor, precision="fp64", alpha: float = 0.0,
-                    team_wgs: int = 0, r_in_lds: int = -1) -> Plan:
+                    team_wgs: int = 0, r_in_lds: int = -1, update="dense") -> Plan:
+    """update "sparse": updates touch only the rows that the nonzeros of A,
+    B and A A^T reach, one work-group per instance."""
     m, p = A.shape
     q, n = B.shape
     prec = PRECISIONS.get(precision, precision)
-    o = mek_plan_opts(int(prec), float(alpha), int(team_wgs), int(r_in_lds))
+    o = mek_plan_opts(int(prec), float(alpha), int(team_wgs), int(r_in_lds),
+                      int(UPDATES.get(update, update)))
     h = ctypes.c_void_p()
     code = lib().mek_plan_create(ctypes.byref(h), m, p, q, n, _dev(A, name="A"), _dev(B, name="B"),
                                  ctypes.byref(o), _stream())
@@ -207,6 +215,14 @@ def mek_plan_query(plan: Plan):
     _check(lib().mek_plan_query(plan.handle, _dev(a), _dev(GA), _dev(GB), ctypes.byref(al),
                                 _stream()), "mek_plan_query")
     return a, GA, GB, al.value
+
+
+def mek_plan_sparse_widths(plan: Plan):
+    """Nonzeros per line of a sparse plan: (rows of A, rows of B, columns of
+    B, columns of A A^T)."""
+    w = (ctypes.c_int32 * 4)()
+    _check(lib().mek_plan_sparse_widths(plan.handle, w), "mek_plan_sparse_widths")
+    return tuple(int(x) for x in w)
 
 
 @dataclass
@@ -487,13 +503,14 @@ def mek_gram(M: torch.Tensor, transpose_first: bool) -> torch.Tensor:
 
 
 def solve(A, B, C, X0=None, variant="grbk", relaxation=0.5, tol=1e-6, seed=0, X_ref=None,
-          max_iters=10_000_000, precision="fp64", **kw) -> SolveResult:
+          max_iters=10_000_000, precision="fp64", update="dense", **kw) -> SolveResult:
     """One-shot solve(A, B, C, X0, variant, relaxation, tol, seed).
 
     With X_ref the rule is ||X - X_ref||_F <= tol ||X_ref||_F, otherwise
-    ||C - A X B||_F <= tol ||C||_F.
+    ||C - A X B||_F <= tol ||C||_F. update "sparse" for banded / sparse A
+    and B.
     """
-    plan = mek_plan_create(A, B, precision=precision)
+    plan = mek_plan_create(A, B, precision=precision, update=update)
     try:
         return mek_solve(plan, C, X0=X0, variant=variant, theta=relaxation,
                          stop="rel_err" if X_ref is not None else "rel_resid", tol=tol,

@@ -71,6 +71,14 @@ struct mek_plan_s {
     unsigned long long *hbuf = nullptr, *rbuf = nullptr, *cpart = nullptr, *gcol = nullptr,
                        *ebuf = nullptr, *epart = nullptr;
     float *A32 = nullptr, *B32 = nullptr, *BT32 = nullptr, *GA32 = nullptr, *GB32 = nullptr;
+    // SPARSE plans: the nonzeros of the rows of A, the rows and columns of B
+    // and the columns of A A^T in ELL form (values in the plan's precision),
+    // in one allocation.
+    int update = MEK_UPDATE_DENSE;
+    int ell_w[4] = {0, 0, 0, 0};    // ka, kb, kbt, kg
+    void* ell = nullptr;
+    int *a_idx = nullptr, *b_idx = nullptr, *bt_idx = nullptr, *g_idx = nullptr;
+    void *a_val = nullptr, *b_val = nullptr, *bt_val = nullptr, *g_val = nullptr;
     Workspace ws;
 };
 
@@ -198,7 +206,7 @@ int ensure_workspace(mek_plan_s* P, int64_t nb) {
 void free_plan(mek_plan_s* P) {
     if (!P) return;
     void* ptrs[] = {P->A, P->B, P->BT, P->GA, P->GB, P->a, P->bcol, P->active, P->A32, P->B32,
-                    P->BT32, P->GA32, P->GB32, P->ws.base, P->blk};
+                    P->BT32, P->GA32, P->GB32, P->ws.base, P->blk, P->ell};
     for (void* x : ptrs)
         if (x) (void)hipFree(x);
     delete P;
@@ -466,6 +474,167 @@ int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double a
     return st;
 }
 
+// Most nonzeros per line that a SPARSE plan accepts.
+constexpr int kSparseMaxWidth = 1024;
+
+// The ELL structure of a SPARSE plan, from the plan's dense A, B and A A^T
+// (entries of A A^T between rows of A with no common nonzero column are
+// sums of exact zeros, so its pattern is exact).
+int build_sparse(mek_plan_s* P, hipStream_t s) {
+    const int m = (int)P->m, p = (int)P->p, q = (int)P->q, n = (int)P->n;
+    if (m > kSelRows * kThreads) return MEK_EUNSUPPORTED;
+    const size_t elem = P->precision == MEK_FP64 ? 8 : 4;
+    if (sparse_lds_bytes(m, p, q, n, elem, false, 0, 0, 0, 0) > solve_lds_budget())
+        return MEK_EUNSUPPORTED;
+    int* wd_dev = P->ws.iscal + 2;
+    MEK_TRY(fill_zero_bytes(wd_dev, 4 * sizeof(int), s));
+    MEK_TRY(ell_width(P->A, m, p, p, 1, wd_dev + 0, s));
+    MEK_TRY(ell_width(P->B, q, n, n, 1, wd_dev + 1, s));
+    MEK_TRY(ell_width(P->B, n, q, 1, n, wd_dev + 2, s));
+    MEK_TRY(ell_width(P->GA, m, m, m, 1, wd_dev + 3, s));
+    MEK_TRY(hipMemcpyAsync(P->ell_w, wd_dev, sizeof(P->ell_w), hipMemcpyDeviceToHost, s));
+    MEK_TRY(hipStreamSynchronize(s));
+    for (int& x : P->ell_w) {
+        if (x > kSparseMaxWidth) return MEK_EUNSUPPORTED;
+        x = std::max(x, 1);
+    }
+    const int ka = P->ell_w[0], kb = P->ell_w[1], kbt = P->ell_w[2], kg = P->ell_w[3];
+    const size_t cnt[4] = {(size_t)m * ka, (size_t)q * kb, (size_t)n * kbt, (size_t)m * kg};
+    size_t need = 0;
+    for (size_t c : cnt) need += ((c * 4 + 255) & ~(size_t)255) + ((c * elem + 255) & ~(size_t)255);
+    MEK_TRY(hipMalloc(&P->ell, need));
+    char* cur = (char*)P->ell;
+    int** idx[4] = {&P->a_idx, &P->b_idx, &P->bt_idx, &P->g_idx};
+    void** val[4] = {&P->a_val, &P->b_val, &P->bt_val, &P->g_val};
+    for (int t = 0; t < 4; ++t) {
+        *idx[t] = carve<int>(cur, cnt[t]);
+        *val[t] = elem == 8 ? (void*)carve<double>(cur, cnt[t]) : (void*)carve<float>(cur, cnt[t]);
+    }
+    auto fill = [&](const double* M, int rows, int cols, long long rs, long long cs, int width,
+                    bool slot_major, int* ix, void* v) -> hipError_t {
+        return elem == 8 ? ell_fill<double>(M, rows, cols, rs, cs, width, slot_major, ix, (double*)v, s)
+                         : ell_fill<float>(M, rows, cols, rs, cs, width, slot_major, ix, (float*)v, s);
+    };
+    MEK_TRY(fill(P->A, m, p, p, 1, ka, false, P->a_idx, P->a_val));
+    MEK_TRY(fill(P->B, q, n, n, 1, kb, true, P->b_idx, P->b_val));
+    MEK_TRY(fill(P->B, n, q, 1, n, kbt, true, P->bt_idx, P->bt_val));
+    MEK_TRY(fill(P->GA, m, m, m, 1, kg, false, P->g_idx, P->g_val));
+    MEK_TRY(hipStreamSynchronize(s));
+    return MEK_OK;
+}
+
+// One launch of the sparse-update kernel for the instances in `slots` (their
+// residuals already in ws.R64), X0 (stacked, or NULL) as the start and X
+// (stacked) as the output.
+template <typename T>
+int run_sparse(mek_plan_s* P, const mek_solve_opts* o, double alpha,
+               const std::vector<InstSlot>& slots, const double* X0, double* X, hipStream_t s,
+               DevReport* out, double* kernel_ms) {
+    Workspace& w = P->ws;
+    const int nb = (int)slots.size();
+    const int64_t m = P->m, p = P->p, q = P->q, n = P->n;
+    const long long mn = m * n, pq = p * q;
+    const bool f64 = sizeof(T) == 8;
+    T* R = f64 ? (T*)w.R64 : (T*)w.R32;
+    T* Xs = f64 ? (T*)w.Xacc : (T*)w.Xt32;
+    if (!f64) MEK_TRY(convert_f64_f32(w.R64, nb * mn, w.R32, s));
+    if (X0) {
+        if (f64) MEK_TRY(copy_f64(X0, nb * pq, w.Xacc, s));
+        else MEK_TRY(convert_f64_f32(X0, nb * pq, w.Xt32, s));
+    } else {
+        MEK_TRY(fill_zero_bytes(Xs, nb * pq * (long long)sizeof(T), s));
+    }
+    SparseParams<T> K;
+    memset(&K, 0, sizeof(K));
+    K.m = (int)m; K.p = (int)p; K.q = (int)q; K.n = (int)n;
+    K.a_idx = P->a_idx;   K.a_val = (const T*)P->a_val;   K.ka = P->ell_w[0];
+    K.b_idx = P->b_idx;   K.b_val = (const T*)P->b_val;   K.kb = P->ell_w[1];
+    K.bt_idx = P->bt_idx; K.bt_val = (const T*)P->bt_val; K.kbt = P->ell_w[2];
+    K.g_idx = P->g_idx;   K.g_val = (const T*)P->g_val;   K.kg = P->ell_w[3];
+    K.a = P->a;
+    K.F_A = P->F_A;
+    K.active = P->active;
+    K.n_active = P->n_active;
+    K.R = R;
+    K.sR = mn;
+    K.X = Xs;
+    K.sX = pq;
+    K.Xref = o->X_ref;
+    K.report = w.report;
+    K.slots = w.slots;
+    K.nb = nb;
+    // LDS beyond the required state, taken in this order while it fits:
+    // ||A_i||^2 (read by every selection), B's ELL slots (every v and w),
+    // then those of A A^T and A (every update's row lists).
+    const size_t elem = sizeof(T);
+    const size_t budget = solve_lds_budget();
+    auto lds_for = [&](bool a_lds, bool b_lds, bool g_lds) {
+        return sparse_lds_bytes((int)m, (int)p, (int)q, (int)n, elem, a_lds,
+                                b_lds ? K.kb : 0, b_lds ? K.kbt : 0, g_lds ? K.ka : 0,
+                                g_lds ? K.kg : 0);
+    };
+    K.a_in_lds = lds_for(true, false, false) <= budget ? 1 : 0;
+    K.b_in_lds = lds_for(K.a_in_lds, true, false) <= budget ? 1 : 0;
+    K.g_in_lds = lds_for(K.a_in_lds, K.b_in_lds, true) <= budget ? 1 : 0;
+    const size_t lds = lds_for(K.a_in_lds, K.b_in_lds, K.g_in_lds);
+    K.variant = o->variant;
+    K.theta = o->theta;
+    K.alpha = alpha;
+    K.stop = o->stop;
+    K.tol = o->tol;
+    K.diverge = o->diverge;
+    K.seed = o->seed;
+    K.replay = o->replay_idx;
+    K.replay_len = o->replay_len;
+    K.resid_hist = o->resid_hist;
+    K.err_hist = o->err_hist;
+    K.idx_hist = o->idx_hist;
+    K.set_hist = o->set_hist;
+    K.hist_cap = o->hist_cap;
+    MEK_TRY(hipMemcpyAsync(w.slots, slots.data(), sizeof(InstSlot) * nb, hipMemcpyHostToDevice, s));
+    // MEK_PHASES=1: time the phases of each update on work-group 0 and print
+    // the averages to stderr (profiling aid).
+    static const bool phases = getenv("MEK_PHASES") && getenv("MEK_PHASES")[0] == '1';
+    K.phase = phases ? w.phase : nullptr;
+    if (phases) MEK_TRY(fill_zero_bytes(w.phase, 32 * 8, s));
+    hipEvent_t ev[2];
+    MEK_TRY(hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return MEK_EHIP;
+    }
+    hipError_t e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) e = launch_sparse(K, lds, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, w.report, sizeof(DevReport) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int st = hip_status(e);
+    float ms = 0.0f;
+    if (st == MEK_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess && kernel_ms)
+        *kernel_ms += (double)ms;
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (st) return st;
+    if (phases && out[0].iters > 0) {
+        unsigned long long h[6];
+        int rate_khz = 100000;
+        (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, P->device);
+        if (hipMemcpy(h, w.phase, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess) {
+            const char* names[6] = {"reduce", "select", "load", "v", "w_x", "r"};
+            fprintf(stderr, "[mek sparse phases] m=%lld n=%lld widths=%d,%d,%d,%d a_lds=%d b_lds=%d "
+                    "g_lds=%d iters=%lld us/update:", (long long)m, (long long)n, K.ka, K.kb, K.kbt,
+                    K.kg, K.a_in_lds, K.b_in_lds, K.g_in_lds, out[0].iters);
+            for (int i = 0; i < 6; ++i)
+                fprintf(stderr, " %s=%.2f", names[i], (double)h[i] / (rate_khz * 1e-3) / out[0].iters);
+            fprintf(stderr, " total_kernel=%.2f\n", ms * 1e3 / out[0].iters);
+        }
+    }
+    if (f64) MEK_TRY(copy_f64(w.Xacc, nb * pq, X, s));
+    else MEK_TRY(convert_f32_f64(w.Xt32, nb * pq, X, s));
+    return MEK_OK;
+}
+
 int read_scalar(const double* dev, double* host, hipStream_t s) {
     MEK_TRY(hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
     MEK_TRY(hipStreamSynchronize(s));
@@ -548,9 +717,11 @@ int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n, c
     if (m > INT32_MAX / 2 || p > INT32_MAX / 2 || q > INT32_MAX / 2 || n > INT32_MAX / 2)
         return MEK_EINVAL;
     if (!A || !B) return MEK_EINVAL;
-    mek_plan_opts o = {MEK_FP64, 0.0, 0, -1};
+    mek_plan_opts o = {MEK_FP64, 0.0, 0, -1, MEK_UPDATE_DENSE};
     if (opts) o = *opts;
     if (o.precision < MEK_FP64 || o.precision > MEK_MIXED) return MEK_EINVAL;
+    if (o.update != MEK_UPDATE_DENSE && o.update != MEK_UPDATE_SPARSE) return MEK_EINVAL;
+    if (o.update == MEK_UPDATE_SPARSE && o.precision == MEK_MIXED) return MEK_EUNSUPPORTED;
     if (o.team_wgs < 0 || o.r_in_lds < -1 || o.r_in_lds > 1) return MEK_EINVAL;
     if (!(o.alpha <= 0.0 || isfinite(o.alpha))) return MEK_EINVAL;
     int st = check_dev(A, (size_t)(m * p) * 8);
@@ -564,6 +735,7 @@ int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n, c
     P->precision = o.precision;
     P->team_wgs = o.team_wgs;
     P->r_in_lds = o.r_in_lds;
+    P->update = o.update;
     int dev = 0;
     (void)hipGetDevice(&dev);
     P->device = dev;
@@ -626,6 +798,7 @@ int mek_plan_create(mek_plan* out, int64_t m, int64_t p, int64_t q, int64_t n, c
             convert_f64_f32(P->GA, m * m, P->GA32, s) || convert_f64_f32(P->GB, n * n, P->GB32, s))
             return fail(MEK_EHIP);
     }
+    if (P->update == MEK_UPDATE_SPARSE && (st = build_sparse(P, s))) return fail(st);
     if (hipStreamSynchronize(s)) return fail(MEK_EHIP);
     *out = P;
     return MEK_OK;
@@ -658,6 +831,13 @@ int mek_plan_query(mek_plan P, double* row_norms, double* gram_a, double* gram_b
     }
     if (alpha) *alpha = P->alpha;
     MEK_TRY(hipStreamSynchronize(s));
+    return MEK_OK;
+}
+
+int mek_plan_sparse_widths(mek_plan P, int32_t* widths) {
+    if (!P || !widths) return MEK_EINVAL;
+    if (P->update != MEK_UPDATE_SPARSE) return MEK_EUNSUPPORTED;
+    for (int t = 0; t < 4; ++t) widths[t] = P->ell_w[t];
     return MEK_OK;
 }
 
@@ -846,10 +1026,13 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
     }
     const int prec = P->precision;
     const bool twosided = o->variant == MEK_TWOSIDED;
-    if (twosided && (prec != MEK_FP64 || nb != 1)) return MEK_EUNSUPPORTED;
+    const bool sparse = P->update == MEK_UPDATE_SPARSE;
+    if (twosided && (prec != MEK_FP64 || nb != 1 || sparse)) return MEK_EUNSUPPORTED;
     Layout L;
+    memset(&L, 0, sizeof(L));
+    L.W = 1;
     if (twosided) st = choose_layout_block2(P, o->block_rows, o->block_cols, &L);
-    else st = choose_layout(P, prec == MEK_FP64 ? 8 : 4, nb, &L);
+    else if (!sparse) st = choose_layout(P, prec == MEK_FP64 ? 8 : 4, nb, &L);
     if (st) return st;
     if ((st = ensure_workspace(P, nb))) return st;
     Workspace& w = P->ws;
@@ -923,7 +1106,15 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
     std::vector<int> passes(nb, 1);
     memset(rep.data(), 0, sizeof(DevReport) * nb);
     double kms = 0.0;
-    if (prec == MEK_FP64 || prec == MEK_FP32) {
+    if (sparse) {
+        // One work-group per instance; R^0 from the residual engine.
+        std::vector<InstSlot> slots(nb);
+        for (int64_t b = 0; b < nb; ++b) slots[b] = slot_for(b);
+        if ((st = residual_all_into_R64(X0))) return st;
+        st = prec == MEK_FP64 ? run_sparse<double>(P, o, alpha, slots, X0, X, s, rep.data(), &kms)
+                              : run_sparse<float>(P, o, alpha, slots, X0, X, s, rep.data(), &kms);
+        if (st) return st;
+    } else if (prec == MEK_FP64 || prec == MEK_FP32) {
         std::vector<InstSlot> slots(nb);
         if ((st = residual_all_into_R64(X0))) return st;
         for (int64_t b = 0; b < nb; ++b) {
@@ -1198,6 +1389,7 @@ int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
             if (Ps[c] == Ps[b]) return MEK_EINVAL;   // each instance needs its own workspace
         if (Ps[b]->precision != Ps[0]->precision || Ps[b]->device != Ps[0]->device)
             return MEK_EINVAL;
+        if (Ps[b]->update == MEK_UPDATE_SPARSE) return MEK_EUNSUPPORTED;
         mek_solve_opts ob = *o;
         ob.X_ref = Xref ? Xref[b] : nullptr;
         int st = validate_opts(Ps[b], &ob);
@@ -1395,7 +1587,8 @@ int enqueue_solve(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, const
 int solve_async_impl(mek_plan P, const double* C, const double* X0, const mek_solve_opts* o,
                      double* X, void* dev_report, hipStream_t s) {
     if (!P || !C || !X || !dev_report || !o) return MEK_EINVAL;
-    if (P->precision == MEK_MIXED || o->variant == MEK_TWOSIDED || o->replay_len > 0)
+    if (P->precision == MEK_MIXED || P->update == MEK_UPDATE_SPARSE ||
+        o->variant == MEK_TWOSIDED || o->replay_len > 0)
         return MEK_EUNSUPPORTED;
     int st = validate_opts(P, o);
     if (st) return st;

@@ -121,6 +121,59 @@ struct SolveParams {
     int wpw;    // entries of w per work-group
 };
 
+// Sparse-aware update (sparse.hip): one work-group per instance; the
+// nonzeros of A, B and A A^T in ELL form (index -1 pads a row).
+template <typename T>
+struct SparseParams {
+    int m, p, q, n;
+    const int* a_idx;  const T* a_val;  int ka;    // row i of A: m x ka, row-major
+    const int* b_idx;  const T* b_val;  int kb;    // row j of B: kb x q, slot-major
+    const int* bt_idx; const T* bt_val; int kbt;   // column l of B: kbt x n, slot-major
+    const int* g_idx;  const T* g_val;  int kg;    // column i of A A^T: m x kg, row-major
+    const double* a;   // m, ||A_i||^2
+    double F_A;
+    const int* active;
+    int n_active;
+    T* R;              // instance b at b * sR: m x n
+    long long sR;
+    T* X;              // instance b at b * sX: p x q, row-major
+    long long sX;
+    const double* Xref;   // p x q per instance (stride sX), or null
+    DevReport* report;    // indexed by instance
+    const InstSlot* slots;
+    int nb;               // work-groups = instances of this launch
+    int a_in_lds;         // ||A_i||^2 of all rows in LDS
+    int b_in_lds;         // the ELL slots of B's rows and columns in LDS
+    int g_in_lds;         // the ELL slots of A A^T and A in LDS
+    int variant;
+    double theta, alpha;
+    int stop;
+    double tol;
+    double diverge;
+    unsigned long long seed;
+    const int32_t* replay;
+    long long replay_len;
+    double* resid_hist;   // histories: instance b at b * hist_cap
+    double* err_hist;
+    int32_t* idx_hist;
+    int32_t* set_hist;
+    long long hist_cap;
+    unsigned long long* phase;   // optional: per-phase wall-clock ticks of work-group 0
+};
+hipError_t launch_sparse(const SparseParams<double>& P, size_t lds_bytes, hipStream_t s);
+hipError_t launch_sparse(const SparseParams<float>& P, size_t lds_bytes, hipStream_t s);
+// LDS of the sparse kernel; kb, kbt > 0 when B's ELL slots are cached, ka,
+// kg > 0 when those of A and A A^T are.
+size_t sparse_lds_bytes(int m, int p, int q, int n, size_t elem, bool a_in_lds, int kb, int kbt,
+                        int ka, int kg);
+// Largest count of nonzeros over the `rows` lines of M (line i: M[i*rs + j*cs],
+// j < cols), combined into *width_dev with atomicMax (clear it first).
+hipError_t ell_width(const double* M, int rows, int cols, long long rs, long long cs,
+                     int* width_dev, hipStream_t s);
+template <typename T>
+hipError_t ell_fill(const double* M, int rows, int cols, long long rs, long long cs, int width,
+                    bool slot_major, int* idx, T* val, hipStream_t s);
+
 // Two-sided block projection (block2.hip): at most kBlkCap rows and columns
 // per step.
 constexpr int kBlkCap = 32;
@@ -251,6 +304,7 @@ hipError_t transpose_to(const double* X, int rows, int cols, T* Xt, hipStream_t 
 template <typename T>
 hipError_t transpose_from(const T* Xt, int rows, int cols, double* X, hipStream_t s);
 hipError_t convert_f64_f32(const double* x, long long len, float* y, hipStream_t s);
+hipError_t convert_f32_f64(const float* x, long long len, double* y, hipStream_t s);
 hipError_t copy_f64(const double* x, long long len, double* y, hipStream_t s);
 hipError_t fill_zero_bytes(void* x, long long bytes, hipStream_t s);
 // out = a x + b y elementwise (out may alias x or y).

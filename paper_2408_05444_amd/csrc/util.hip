@@ -175,6 +175,11 @@ __global__ void convert_kernel(const double* __restrict__ x, long long len, floa
          e += (long long)gridDim.x * blockDim.x)
         y[e] = (float)x[e];
 }
+__global__ void widen_kernel(const float* __restrict__ x, long long len, double* __restrict__ y) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+         e += (long long)gridDim.x * blockDim.x)
+        y[e] = (double)x[e];
+}
 __global__ void copy_kernel(const double* __restrict__ x, long long len, double* __restrict__ y) {
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < len;
          e += (long long)gridDim.x * blockDim.x)
@@ -201,6 +206,10 @@ static dim3 ew_grid(long long len) {
 
 hipError_t convert_f64_f32(const double* x, long long len, float* y, hipStream_t s) {
     hipLaunchKernelGGL(convert_kernel, ew_grid(len), dim3(256), 0, s, x, len, y);
+    return hipGetLastError();
+}
+hipError_t convert_f32_f64(const float* x, long long len, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(widen_kernel, ew_grid(len), dim3(256), 0, s, x, len, y);
     return hipGetLastError();
 }
 hipError_t copy_f64(const double* x, long long len, double* y, hipStream_t s) {

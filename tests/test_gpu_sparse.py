@@ -1,0 +1,217 @@
+"""GPU parity of the sparse-aware update (MEK_UPDATE_SPARSE) through the C
+ABI, against the CPU oracle (which always applies the full update of
+Alg. 3: the sparse form leaves out only terms that are exactly zero) and
+against the dense GPU form.
+
+Tolerances as for the dense path: index sequences identical, norms within
+1e-8 relative, iterates within 1e-9 relative after a few thousand FP64
+updates (O(u) relative error per update, damped by the contraction), and
+1e-12 between the dense and sparse GPU forms under one forced index
+sequence (the two differ only in the summation order of v and w, whose
+terms outside the nonzeros are zero).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2408_05444_amd as mek
+import workloads
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs an MI355X")]
+
+
+def cuda(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+CASES = {
+    "banded64": lambda: workloads.banded_gaussian(64, seed=3),
+    "sparse_irregular": lambda: workloads.sparse_random(300, 120, 90, 257, seed=1,
+                                                        empty_rows=20),
+    # m above 512: several rows of the selection per thread.
+    "sparse_tall": lambda: workloads.sparse_random(1100, 70, 40, 130, seed=2, empty_rows=7),
+}
+
+VARIANTS = [("grbk", 0.5), ("rgrbk", 0.8), ("rgrbk", 1.0), ("mwrbk", 0.5), ("rbk", 0.5),
+            ("bk", 0.5)]
+
+
+def _sparse_plan(inst, alpha, **kw):
+    return mek.mek_plan_create(cuda(inst.A), cuda(inst.B), alpha=alpha, update="sparse", **kw)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("variant,theta", VARIANTS)
+def test_sparse_trajectory_matches_oracle(case, variant, theta):
+    inst = CASES[case]()
+    K = 2000
+    alpha = oracle.spectral_alpha(inst.B)
+    ref = oracle.solve(inst.A, inst.B, inst.C, variant=variant, theta=theta, alpha=alpha,
+                       max_iters=K, seed=31, Xref=inst.X_star)
+    plan = _sparse_plan(inst, alpha)
+    res = mek.mek_solve(plan, cuda(inst.C), variant=variant, theta=theta, alpha=alpha,
+                        max_iters=K, seed=31, hist_cap=K + 1, X_ref=cuda(inst.X_star))
+    assert res.status == mek.MEK_MAXITER and res.iters == K
+    assert res.team_wgs == 1 and not res.r_in_lds
+    assert host(res.idx_hist).tolist() == ref.idx.tolist()
+    assert np.allclose(host(res.resid_hist), ref.s_hist, rtol=1e-8, atol=0)
+    assert np.allclose(host(res.err_hist), ref.e_hist, rtol=1e-8, atol=0)
+    assert rel(host(res.X), ref.X) <= 1e-9
+    if variant in ("grbk", "rgrbk"):
+        assert host(res.set_hist).tolist() == ref.set_sizes.tolist()
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_sparse_widths_are_the_nonzero_counts(case):
+    inst = CASES[case]()
+    plan = _sparse_plan(inst, 0.0)
+    G = inst.A @ inst.A.T
+    want = (int((inst.A != 0).sum(1).max()), int((inst.B != 0).sum(1).max()),
+            int((inst.B != 0).sum(0).max()), int((G != 0).sum(0).max()))
+    assert mek.mek_plan_sparse_widths(plan) == want
+
+
+def test_sparse_equals_dense_under_one_index_sequence():
+    inst = CASES["sparse_irregular"]()
+    alpha = oracle.spectral_alpha(inst.B)
+    seq = oracle.solve(inst.A, inst.B, inst.C, variant="rbk", alpha=alpha, max_iters=3000,
+                       seed=4).idx
+    idx = cuda(seq, torch.int32)
+    kw = dict(variant="grbk", alpha=alpha, max_iters=3000, replay_idx=idx, hist_cap=3001)
+    dense = mek.mek_solve(mek.mek_plan_create(cuda(inst.A), cuda(inst.B), alpha=alpha),
+                          cuda(inst.C), **kw)
+    sparse = mek.mek_solve(_sparse_plan(inst, alpha), cuda(inst.C), **kw)
+    assert host(sparse.idx_hist).tolist() == seq.tolist()
+    assert rel(host(sparse.X), host(dense.X)) <= 1e-12
+    assert np.allclose(host(sparse.resid_hist), host(dense.resid_hist), rtol=1e-11)
+
+
+def test_sparse_warm_start_trajectory():
+    inst = CASES["banded64"]()
+    X0 = np.random.default_rng(5).standard_normal((64, 64))
+    alpha = oracle.spectral_alpha(inst.B)
+    ref = oracle.solve(inst.A, inst.B, inst.C, X0=X0, alpha=alpha, max_iters=1500, seed=6,
+                       Xref=inst.X_star)
+    res = mek.mek_solve(_sparse_plan(inst, alpha), cuda(inst.C), X0=cuda(X0), alpha=alpha,
+                        max_iters=1500, seed=6, hist_cap=1501, X_ref=cuda(inst.X_star))
+    assert host(res.idx_hist).tolist() == ref.idx.tolist()
+    assert rel(host(res.X), ref.X) <= 1e-9
+
+
+@pytest.mark.parametrize("variant,theta", [("grbk", 0.5), ("mwrbk", 0.5)])
+def test_sparse_converges_like_oracle(variant, theta):
+    # A blurred 64 x 64 image (sigma 0.7, 9 taps; cond(A) = 5.6), X_ref the
+    # generating image.
+    inst = workloads.blurred_image(64, 1, 0.7, seed=8)[0]
+    alpha = oracle.spectral_alpha(inst.B)
+    ref = oracle.solve(inst.A, inst.B, inst.C, variant=variant, theta=theta, alpha=alpha,
+                       stop=oracle.STOP_REL_ERR, tol=1e-6, Xref=inst.X_star, max_iters=10 ** 6,
+                       seed=12)
+    res = mek.mek_solve(_sparse_plan(inst, alpha), cuda(inst.C), variant=variant, theta=theta,
+                        alpha=alpha, stop="rel_err", tol=1e-6, X_ref=cuda(inst.X_star),
+                        max_iters=10 ** 6, seed=12)
+    assert ref.status == oracle.OK and res.status == mek.MEK_OK
+    assert rel(host(res.X), inst.X_star) <= 1e-6
+    assert abs(res.iters - ref.iters) <= max(2, 0.02 * ref.iters)
+
+
+def test_sparse_empty_rows_never_selected():
+    # The 64 x 64 blur (sigma 0.7) with four zero rows inserted into A: the
+    # zero rows are never selected and the limit is still X* (A keeps full
+    # column rank).
+    base = workloads.blurred_image(64, 1, 0.7, seed=8)[0]
+    A = np.ascontiguousarray(np.insert(base.A, [5, 20, 20, 63], 0.0, axis=0))
+    C = A @ base.X_star @ base.B
+    plan = mek.mek_plan_create(cuda(A), cuda(base.B), update="sparse")
+    res = mek.mek_solve(plan, cuda(C), stop="rel_err", tol=1e-7, X_ref=cuda(base.X_star),
+                        max_iters=3_000_000, seed=2, hist_cap=5000)
+    assert res.status == mek.MEK_OK
+    assert rel(host(res.X), base.X_star) <= 1e-7
+    empty = {5, 21, 22, 66}
+    assert all(np.abs(A[i]).sum() == 0 for i in empty)
+    assert not empty & set(host(res.idx_hist).tolist())
+
+
+def test_sparse_fp32():
+    # First updates against the oracle on the banded Gaussian instance; then
+    # convergence to 1e-4 (FP32's reach) on the well-conditioned blur
+    # (64 x 64, sigma 0.7).
+    inst = CASES["banded64"]()
+    alpha = oracle.spectral_alpha(inst.B)
+    ref = oracle.solve(inst.A, inst.B, inst.C, alpha=alpha, max_iters=40, seed=3)
+    plan = _sparse_plan(inst, alpha, precision="fp32")
+    first = mek.mek_solve(plan, cuda(inst.C), alpha=alpha, max_iters=40, seed=3, hist_cap=41)
+    assert host(first.idx_hist).tolist() == ref.idx.tolist()
+    img = workloads.blurred_image(64, 1, 0.7, seed=8)[0]
+    plan = _sparse_plan(img, 0.0, precision="fp32")
+    res = mek.mek_solve(plan, cuda(img.C), stop="rel_err", tol=1e-4, X_ref=cuda(img.X_star),
+                        max_iters=3_000_000, seed=3)
+    assert res.status == mek.MEK_OK
+    assert rel(host(res.X), img.X_star) <= 1e-4
+
+
+@pytest.mark.parametrize("nb", [3, 300])
+def test_sparse_batch_equals_single_solves(nb):
+    # One work-group per instance; 300 instances exceed the compute units.
+    base = workloads.banded_gaussian(40, seed=9, sigma=0.7)
+    rng = np.random.default_rng(10)
+    Xs = rng.standard_normal((nb, 40, 40))
+    C = np.stack([base.A @ X @ base.B for X in Xs])
+    alpha = oracle.spectral_alpha(base.B)
+    plan = _sparse_plan(base, alpha)
+    kw = dict(variant="rgrbk", theta=0.6, alpha=alpha, stop="rel_err", tol=1e-5,
+              max_iters=200000, seed=13, instance=100)
+    st, res = mek.mek_solve_batched(plan, cuda(C), X_ref=cuda(Xs), **kw)
+    assert st == mek.MEK_OK and all(r.status == mek.MEK_OK for r in res)
+    for b in sorted({0, 1, nb - 1}):
+        one = mek.mek_solve(plan, cuda(C[b]), X_ref=cuda(Xs[b]), **{**kw, "instance": 100 + b})
+        assert res[b].iters == one.iters and one.status == mek.MEK_OK
+        assert torch.equal(res[b].X, one.X)
+
+
+def test_sparse_rel_resid_and_exact_stops():
+    inst = workloads.blurred_image(64, 1, 0.7, seed=8)[0]
+    plan = _sparse_plan(inst, 0.0)
+    res = mek.mek_solve(plan, cuda(inst.C), stop="rel_resid", tol=1e-3, max_iters=10 ** 6, seed=1)
+    assert res.status == mek.MEK_OK
+    R = inst.C - inst.A @ host(res.X) @ inst.B
+    assert np.linalg.norm(R) <= 1e-3 * np.linalg.norm(inst.C) * (1 + 1e-6)
+    zero = mek.mek_solve(plan, cuda(np.zeros_like(inst.C)), max_iters=100)
+    assert zero.status == mek.MEK_EXACT and zero.iters == 0
+
+
+def test_sparse_refusals():
+    inst = CASES["banded64"]()
+    plan = _sparse_plan(inst, 0.0)
+    with pytest.raises(mek.MekError) as e:
+        mek.mek_solve(plan, cuda(inst.C), variant="twosided", max_iters=5)
+    assert e.value.code == mek.MEK_EUNSUPPORTED
+    with pytest.raises(mek.MekError) as e:
+        mek.mek_solve_async(plan, cuda(inst.C), max_iters=5)
+    assert e.value.code == mek.MEK_EUNSUPPORTED
+    with pytest.raises(mek.MekError) as e:
+        mek.mek_solve_multi([plan], [cuda(inst.C)], max_iters=5)
+    assert e.value.code == mek.MEK_EUNSUPPORTED
+    dense = mek.mek_plan_create(cuda(inst.A), cuda(inst.B))
+    with pytest.raises(mek.MekError) as e:
+        mek.mek_plan_sparse_widths(dense)
+    assert e.value.code == mek.MEK_EUNSUPPORTED
+    # A dense A: each column of A A^T has 1100 nonzeros, above the cap.
+    rng = np.random.default_rng(1)
+    with pytest.raises(mek.MekError) as e:
+        mek.mek_plan_create(cuda(rng.standard_normal((1100, 20))),
+                            cuda(rng.standard_normal((20, 30))), update="sparse")
+    assert e.value.code == mek.MEK_EUNSUPPORTED
+    with pytest.raises(mek.MekError) as e:
+        mek.mek_plan_create(cuda(inst.A), cuda(inst.B), precision="mixed", update="sparse")
+    assert e.value.code == mek.MEK_EUNSUPPORTED

@@ -27,7 +27,8 @@ def test_header_declares_the_boundary():
                  "mek_plan_query", "mek_solve", "mek_solve_batched", "mek_philox_uniform", "mek_select",
                  "mek_residual", "mek_residual_batched", "mek_gram", "mek_solve_multi", "mek_solve_async",
                  "mek_cnn_conv3x3", "mek_cnn_conv3x3_grad_input", "mek_cnn_conv3x3_grad_weight",
-                 "mek_cnn_mse_grad", "mek_cnn_adam", "mek_cnn_to_bf16", "mek_cnn_round_bf16"]:
+                 "mek_cnn_mse_grad", "mek_cnn_adam", "mek_cnn_to_bf16", "mek_cnn_round_bf16",
+                 "mek_plan_sparse_widths"]:
         assert want in names
 
 
@@ -71,6 +72,7 @@ def test_struct_layouts_match_c():
       F(mek_solve_opts, X_ref) F(mek_solve_opts, max_iters) F(mek_solve_opts, replay_len)
       F(mek_solve_opts, hist_cap) F(mek_solve_opts, inner_iters) F(mek_solve_opts, set_hist)
       F(mek_report, passes) F(mek_report, alpha) F(mek_plan_opts, r_in_lds)
+      F(mek_plan_opts, update)
       F(mek_solve_opts, block_rows) F(mek_solve_opts, tau) F(mek_solve_opts, cols_hist)
       return 0;
     }
@@ -104,6 +106,13 @@ def test_host_validation_rejects_before_any_gpu_work():
     assert L.mek_plan_create(ctypes.byref(h), 2, 2, 2, 2, vp(1), vp(1), ctypes.byref(bad), None) == EINVAL
     bad = mek.mek_plan_opts(0, float("nan"), 0, -1)
     assert L.mek_plan_create(ctypes.byref(h), 2, 2, 2, 2, vp(1), vp(1), ctypes.byref(bad), None) == EINVAL
+    bad = mek.mek_plan_opts(0, 0.0, 0, -1, 5)
+    assert L.mek_plan_create(ctypes.byref(h), 2, 2, 2, 2, vp(1), vp(1), ctypes.byref(bad), None) == EINVAL
+    mixed_sparse = mek.mek_plan_opts(mek.MEK_MIXED, 0.0, 0, -1, mek.MEK_UPDATE_SPARSE)
+    assert L.mek_plan_create(ctypes.byref(h), 2, 2, 2, 2, vp(1), vp(1), ctypes.byref(mixed_sparse),
+                             None) == mek.MEK_EUNSUPPORTED
+    w4 = (ctypes.c_int32 * 4)()
+    assert L.mek_plan_sparse_widths(None, w4) == EINVAL
     assert L.mek_solve(None, vp(1), None, None, vp(1), None, None) == EINVAL
     assert L.mek_select(9, 10, vp(1), vp(1), 1.0, 0.5, 0, 0, 0, 1, vp(1), None, None, None, None) == EINVAL
     assert L.mek_select(2, 10, vp(1), vp(1), 1.0, 1.5, 0, 0, 0, 1, vp(1), None, None, None, None) == EINVAL

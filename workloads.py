@@ -178,6 +178,44 @@ def blur_toeplitz(size: int, sigma: float, half_width: int = 4) -> np.ndarray:
     return _c(K)
 
 
+def banded_gaussian(size: int, seed: int, sigma: float = 2.0, half_width: int = 4) -> Instance:
+    """The blur pair A = blur_toeplitz(size, sigma, half_width), B = A^T with
+    X* iid N(0,1) from default_rng(seed) (no flat regions, so no ties in the
+    greedy ratios) and C = A X* B."""
+    A = blur_toeplitz(size, sigma, half_width)
+    B = _c(A.T)
+    X = np.random.default_rng(seed).standard_normal((size, size))
+    return Instance(f"banded gaussian size={size} sigma={sigma} seed={seed}", A, B, _c(A @ X @ B),
+                    _c(X))
+
+
+def sparse_random(m: int, p: int, q: int, n: int, seed: int, row_nnz=(2, 4),
+                  col_nnz=(1, 3), empty_rows: int = 0) -> Instance:
+    """Irregular sparse A (m x p): each row holds a number of N(0,1) entries
+    drawn uniformly from row_nnz (inclusive) at distinct random columns,
+    then `empty_rows` distinct random rows are cleared. B (q x n): each
+    column holds col_nnz entries at distinct random rows. X* iid N(0,1);
+    C = A X* B. All from default_rng(seed) in that order. With at least two
+    entries per row, no two rows of A are parallel (parallel rows have equal
+    ratios ||R_i||^2 / ||A_i||^2 at every update, an exact tie)."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((m, p))
+    for i in range(m):
+        k = int(rng.integers(row_nnz[0], row_nnz[1] + 1))
+        cols = rng.choice(p, size=k, replace=False)
+        A[i, cols] = rng.standard_normal(k)
+    if empty_rows:
+        A[rng.choice(m, size=empty_rows, replace=False)] = 0.0
+    B = np.zeros((q, n))
+    for j in range(n):
+        k = int(rng.integers(col_nnz[0], col_nnz[1] + 1))
+        rows = rng.choice(q, size=k, replace=False)
+        B[rows, j] = rng.standard_normal(k)
+    X = rng.standard_normal((p, q))
+    return Instance(f"sparse random m={m} p={p} q={q} n={n} seed={seed}", _c(A), _c(B),
+                    _c(A @ X @ B), _c(X))
+
+
 def synthetic_image(h: int, w: int, channels: int, seed: int,
                     n_rect: int = 8, n_disc: int = 8) -> np.ndarray:
     """channels x h x w image in [0,1]: a per-channel linear gradient, then
