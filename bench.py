@@ -188,6 +188,56 @@ def blur_batch_forms(mek, workloads, torch):
     return out
 
 
+def paper_table_forms(mek, workloads, torch, trials=20):
+    """The paper's Example 5.2 / Table 4 on its two Gaussian sets (Set 2: A
+    140 x 30, B 70 x 160; Set 5: A 230 x 50, B 110 x 240) and Example 5.1 /
+    Table 2 Set 2 (ME-BK, A 110 x 45, B 50 x 140, X0 = 1e-5 I), `trials`
+    random instances each (data seeds of workloads.paper_table*), alpha =
+    1/||B||_2^2, stop at squared relative error 1e-6 (relative error 1e-3)
+    against X* (the limit here: A has full column rank and B full row rank).
+    Per method: mean updates, mean wall time of a solve (plan set-up
+    excluded, host checks and copies included), kernel time per update, and
+    the paper's speed-up time(ME-RBK) / time(method)."""
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    out = {}
+
+    def run(make, variants, X0_of=None):
+        acc = {v: {"iters": [], "wall": [], "kms": []} for v in variants}
+        for tr in range(trials):
+            inst = make(tr)
+            A, B, C, Xs = t(inst.A), t(inst.B), t(inst.C), t(inst.X_star)
+            X0 = t(X0_of(inst)) if X0_of else None
+            plan = mek.mek_plan_create(A, B)
+            for v in variants:
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                r = mek.mek_solve(plan, C, X0=X0, variant=v, stop="rel_err", tol=1e-3,
+                                  X_ref=Xs, max_iters=10 ** 7, seed=100 + tr)
+                torch.cuda.synchronize()
+                acc[v]["wall"].append(time.perf_counter() - ts)
+                acc[v]["iters"].append(r.iters)
+                acc[v]["kms"].append(r.kernel_ms)
+                assert r.status == mek.MEK_OK
+            mek.mek_plan_destroy(plan)
+        res = {}
+        for v in variants:
+            its, wall, kms = (np.array(acc[v][k]) for k in ("iters", "wall", "kms"))
+            res[v] = {"mean_iters": float(its.mean()), "mean_wall_ms": float(wall.mean() * 1e3),
+                      "kernel_us_per_update": float(kms.sum() * 1e3 / its.sum())}
+        if "rbk" in variants:
+            for v in variants:
+                res[v]["speedup_vs_rbk"] = res["rbk"]["mean_wall_ms"] / res[v]["mean_wall_ms"]
+        return res
+
+    out["table4_set2"] = run(workloads.paper_table3_set2, ["rbk", "grbk", "mwrbk"])
+    out["table4_set5"] = run(workloads.paper_table3_set5, ["rbk", "grbk", "mwrbk"])
+    out["table2_set2_bk"] = run(workloads.paper_table1_set2, ["bk"],
+                                X0_of=lambda inst: 1e-5 * np.eye(*inst.X_star.shape))
+    out["trials"] = trials
+    return out
+
+
 def sparse_update_bytes(m, p, q, n, ka, kb, kbt, kg, elem=8):
     """Bytes one sparse-aware update moves: R_{i_k} read (n), the index and
     value of every ELL slot of B's rows and columns (q kb + n kbt), the
@@ -348,6 +398,8 @@ def main():
                          "workload's sizes (for a kernel trace) and print them")
     ap.add_argument("--warm-start-only", action="store_true",
                     help="only run the learned warm-start form and print it")
+    ap.add_argument("--paper-only", action="store_true",
+                    help="only run the paper's Table 4 / Table 2 Gaussian sets and print them")
     ap.add_argument("--sparse-only", action="store_true",
                     help="only run the image forms (dense and sparse-aware updates) and print them")
     ap.add_argument("--ragged-only", action="store_true",
@@ -382,6 +434,9 @@ def main():
     torch.cuda.synchronize()
     if args.warm_start_only:
         print(json.dumps({"warm_start": warm_start_forms(mek, workloads, torch)}), flush=True)
+        return
+    if args.paper_only:
+        print(json.dumps({"paper_tables": paper_table_forms(mek, workloads, torch)}), flush=True)
         return
     if args.sparse_only:
         print(json.dumps({"blur3_batched": blur_batch_forms(mek, workloads, torch),
@@ -478,6 +533,7 @@ def main():
                              "kernel_us_per_step": r.kernel_ms * 1e3 / max(r.iters, 1)}
         forms["blur3_batched"] = blur_batch_forms(mek, workloads, torch)
         forms["blur_sparse_96ch"] = sparse_many_forms(mek, workloads, torch)
+        forms["paper_tables"] = paper_table_forms(mek, workloads, torch)
         forms["ragged64_fp32"] = ragged_batch_forms(mek, workloads, torch)
         forms["warm_start"] = warm_start_forms(mek, workloads, torch)
         line["forms"] = forms

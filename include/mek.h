@@ -254,7 +254,10 @@ typedef struct mek_device_report {
  * return MEK_EUNSUPPORTED. No finite check of the inputs is made (non-finite data
  * ends in MEK_EDIVERGED or a non-finite report). X, the histories and the
  * plan's workspace must not be touched until the stream has passed the
- * call; calls on one plan must be ordered on one stream. */
+ * call; calls on one plan must be ordered on one stream. A later call that
+ * grows the plan's workspace (a uniform batch larger than any before on the
+ * plan) moves it, after which graphs captured on the plan must not be
+ * replayed. */
 int mek_solve_async(mek_plan plan, const double* C, const double* X0, const mek_solve_opts* opts,
                     double* X, mek_device_report* dev_report, void* stream);
 
@@ -279,6 +282,27 @@ int mek_solve_multi(int64_t batch, const mek_plan* plans, const double* const* C
                     const double* const* X0, const double* const* X_ref,
                     const mek_solve_opts* opts, double* const* X, mek_report* reports,
                     void* stream);
+
+/* Stream-ordered ragged batch: the iteration and results of mek_solve_multi
+ * (same arguments, same layout of work-groups), with every step enqueued on
+ * `stream` and no host wait; instance b's report goes to dev_reports[b]
+ * (device memory, batch entries) when the stream reaches it. The parameter
+ * table of the launch reaches the device through kernel arguments, so once
+ * every plan has a workspace and the first plan holds a table for this
+ * batch size (one earlier mek_solve_multi or mek_solve_multi_async call on
+ * the same plans), the call can be captured into a graph and replayed; a
+ * captured call that would need either returns MEK_EUNSUPPORTED (outside
+ * capture they are allocated). No finite check of the inputs is made.
+ * Other errors and refusals as mek_solve_multi. X, the histories and the
+ * plans' workspaces must not be touched until the stream has passed the
+ * call; calls sharing a plan must be ordered on one stream. A later call
+ * that grows a plan's workspace (a uniform batch larger than any before on
+ * that plan) moves it, after which graphs captured on that plan must not be
+ * replayed; the parameter table never moves. */
+int mek_solve_multi_async(int64_t batch, const mek_plan* plans, const double* const* C,
+                          const double* const* X0, const double* const* X_ref,
+                          const mek_solve_opts* opts, double* const* X,
+                          mek_device_report* dev_reports, void* stream);
 
 /* ---- Unit entry points: the hot path's stages run on their own. ---- */
 

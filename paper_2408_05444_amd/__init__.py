@@ -105,6 +105,9 @@ def lib() -> ctypes.CDLL:
         L.mek_solve_multi.restype = ci
         L.mek_solve_async.argtypes = [vp, vp, vp, ctypes.POINTER(mek_solve_opts), vp, vp, vp]
         L.mek_solve_async.restype = ci
+        L.mek_solve_multi_async.argtypes = [i64, vp, vp, vp, vp, ctypes.POINTER(mek_solve_opts),
+                                            vp, vp, vp]
+        L.mek_solve_multi_async.restype = ci
         L.mek_cnn_conv3x3.argtypes = [i64, i64, i64, i64, i64, vp, vp, vp, ci, vp, vp, vp, vp]
         L.mek_cnn_conv3x3.restype = ci
         L.mek_cnn_conv3x3_grad_input.argtypes = [i64, i64, i64, i64, i64, vp, vp, vp, vp, vp]
@@ -390,13 +393,15 @@ def mek_solve_async(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = No
     return X, rep
 
 
-def make_histories(cap: int, device="cuda") -> dict:
-    """Device history buffers for mek_solve_async (cap entries each)."""
+def make_histories(cap: int, device="cuda", nb: Optional[int] = None) -> dict:
+    """Device history buffers for the stream-ordered solves: cap entries
+    each, or (nb, cap) for a batch."""
+    shp = (cap,) if nb is None else (nb, cap)
     return {"cap": cap,
-            "resid_hist": torch.full((cap,), float("nan"), dtype=torch.float64, device=device),
-            "err_hist": torch.full((cap,), float("nan"), dtype=torch.float64, device=device),
-            "idx_hist": torch.full((cap,), -1, dtype=torch.int32, device=device),
-            "set_hist": torch.zeros(cap, dtype=torch.int32, device=device)}
+            "resid_hist": torch.full(shp, float("nan"), dtype=torch.float64, device=device),
+            "err_hist": torch.full(shp, float("nan"), dtype=torch.float64, device=device),
+            "idx_hist": torch.full(shp, -1, dtype=torch.int32, device=device),
+            "set_hist": torch.zeros(shp, dtype=torch.int32, device=device)}
 
 
 def read_device_report(rep: torch.Tensor) -> dict:
@@ -440,6 +445,44 @@ def mek_solve_multi(plans, C, X0=None, X_ref=None, variant="grbk", theta: float 
         raise MekError(code, "mek_solve_multi")
     return int(code), [_result(X[b], reps[b].status, reps[b], hists, b, hist_cap)
                        for b in range(nb)]
+
+
+def mek_solve_multi_async(plans, C, X0=None, X_ref=None, variant="grbk", theta: float = 0.5,
+                          alpha: float = 0.0, stop="none", tol: float = 0.0,
+                          max_iters: int = 100000, seed: int = 0, instance: int = 0,
+                          diverge: float = 0.0, X_out=None, reports=None, hist=None):
+    """Stream-ordered ragged batch on the current stream; returns (X list,
+    reports) where reports is an (nb, 32) uint8 device tensor, row b holding
+    instance b's mek_device_report (decode with read_device_report once the
+    stream has passed the call). X_out (list) and reports may be given, for
+    instance to capture the call into a graph; hist = make_histories(cap,
+    nb=nb) records the histories."""
+    nb = len(plans)
+    if len(C) != nb:
+        raise ValueError("one C per plan")
+    dev = C[0].device
+    pq = [(P.p, P.q) for P in plans]
+    X = X_out if X_out is not None else [torch.empty(p, q, dtype=torch.float64, device=dev)
+                                         for p, q in pq]
+    rep = reports if reports is not None else torch.zeros(nb, DEVICE_REPORT_BYTES,
+                                                          dtype=torch.uint8, device=dev)
+    handles = (ctypes.c_void_p * nb)(*[P.handle for P in plans])
+    Cp = _ptr_array(C, [(P.m, P.n) for P in plans], "C")
+    X0p = _ptr_array(X0, pq, "X0") if X0 is not None else None
+    Xrp = _ptr_array(X_ref, pq, "X_ref") if X_ref is not None else None
+    Xp = _ptr_array(X, pq, "X")
+    o, _ = _solve_opts(nb, dev, variant, theta, alpha, stop, tol, None, max_iters, seed,
+                       instance, None, diverge, 0, 0)
+    if hist is not None:
+        o.hist_cap = hist["cap"]
+        o.resid_hist = _dev(hist["resid_hist"])
+        o.err_hist = _dev(hist["err_hist"])
+        o.idx_hist = _dev(hist["idx_hist"], dtype=torch.int32)
+        o.set_hist = _dev(hist["set_hist"], dtype=torch.int32)
+    _check(lib().mek_solve_multi_async(nb, handles, Cp, X0p, Xrp, ctypes.byref(o), Xp,
+                                       _dev(rep, dtype=torch.uint8), _stream()),
+           "mek_solve_multi_async")
+    return X, rep
 
 
 def mek_philox_uniform(seed: int, instance: int, k0: int, count: int) -> torch.Tensor:

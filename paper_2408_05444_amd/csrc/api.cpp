@@ -79,6 +79,10 @@ struct mek_plan_s {
     void* ell = nullptr;
     int *a_idx = nullptr, *b_idx = nullptr, *bt_idx = nullptr, *g_idx = nullptr;
     void *a_val = nullptr, *b_val = nullptr, *bt_val = nullptr, *g_val = nullptr;
+    // Parameter table of a ragged launch whose first instance is this plan
+    // (kept across calls, so that stream-ordered calls allocate nothing).
+    void* mtab = nullptr;
+    size_t mtab_bytes = 0;
     Workspace ws;
 };
 
@@ -206,7 +210,7 @@ int ensure_workspace(mek_plan_s* P, int64_t nb) {
 void free_plan(mek_plan_s* P) {
     if (!P) return;
     void* ptrs[] = {P->A, P->B, P->BT, P->GA, P->GB, P->a, P->bcol, P->active, P->A32, P->B32,
-                    P->BT32, P->GA32, P->GB32, P->ws.base, P->blk, P->ell};
+                    P->BT32, P->GA32, P->GB32, P->ws.base, P->blk, P->ell, P->mtab};
     for (void* x : ptrs)
         if (x) (void)hipFree(x);
     delete P;
@@ -1282,11 +1286,36 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
 // persistent launch of the MULTI kernel form. Teams get work-groups in
 // proportion to their per-update work (R and X touched), within one
 // work-group per CU for the whole grid; R stays in device memory.
+// True while `s` is being captured into a graph (which must not allocate).
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
+// The ragged launch's parameter table in the first plan, allocated once at
+// the size of the largest batch (one instance per compute unit), so that it
+// never moves under a captured graph; never allocated during capture.
+int ensure_multi_table(mek_plan_s* P, size_t bytes, hipStream_t s) {
+    if (P->mtab && P->mtab_bytes >= bytes) return MEK_OK;
+    if (P->mtab) return MEK_EINVAL;   // larger than any batch the launch takes
+    if (capturing(s)) return MEK_EUNSUPPORTED;
+    const size_t nmax = (size_t)std::max(1, P->cus);
+    const size_t want = std::max<size_t>(
+        bytes, nmax * sizeof(SolveParams<double>) + (((nmax + 1) * sizeof(int) + 7) & ~(size_t)7));
+    MEK_TRY(hipMalloc(&P->mtab, want));
+    P->mtab_bytes = want;
+    return MEK_OK;
+}
+
 template <typename T>
 int run_multi(int64_t nb, mek_plan_s* const* plans, const std::vector<Layout>& Ls,
               const mek_solve_opts* o, const std::vector<double>& C2,
               const std::vector<double>& ref2, const double* const* Xref, hipStream_t s,
-              std::vector<DevReport>& rep, double* kernel_ms) {
+              std::vector<DevReport>& rep, double* kernel_ms, DevReport* dev_reports = nullptr) {
     std::vector<SolveParams<T>> K(nb);
     std::vector<int> start(nb + 1, 0);
     size_t lds = 0;
@@ -1320,6 +1349,10 @@ int run_multi(int64_t nb, mek_plan_s* const* plans, const std::vector<Layout>& L
         k.ref2 = ref2[b];
         k.S_target = 0.0;
         k.inst = o->instance + (uint64_t)b;
+        if (dev_reports) {
+            k.norms = w.scal + 2;   // {||C_b||^2, ||X_ref,b||^2} computed on the device
+            k.report = dev_reports + b;
+        }
         const size_t hc = (size_t)b * (size_t)std::max<int64_t>(o->hist_cap, 0);
         k.resid_hist = o->resid_hist ? o->resid_hist + hc : nullptr;
         k.err_hist = o->err_hist ? o->err_hist + hc : nullptr;
@@ -1340,9 +1373,24 @@ int run_multi(int64_t nb, mek_plan_s* const* plans, const std::vector<Layout>& L
         MEK_TRY(fill_zero_bytes((char*)w.vbuf, P->q * 8, s));
     }
     const size_t pbytes = sizeof(SolveParams<T>) * (size_t)nb;
-    char* dbuf = nullptr;
-    MEK_TRY(hipMalloc((void**)&dbuf, pbytes + sizeof(int) * (size_t)(nb + 1)));
-    int st = MEK_OK;
+    const size_t tbytes = pbytes + ((sizeof(int) * (size_t)(nb + 1) + 7) & ~(size_t)7);
+    int st = ensure_multi_table(plans[0], tbytes, s);
+    if (st) return st;
+    char* dbuf = (char*)plans[0]->mtab;
+    SolveParams<T> head = K[0];
+    head.multi = reinterpret_cast<const SolveParams<T>*>(dbuf);
+    head.multi_start = reinterpret_cast<const int*>(dbuf + pbytes);
+    head.multi_n = (int)nb;
+    head.multi_wgs = start[nb];
+    if (dev_reports) {
+        // Stream-ordered: the table goes in through kernel arguments, the
+        // kernel reads the norms from device memory and writes the reports
+        // to the caller's structs; nothing waits.
+        MEK_TRY(store_bytes(K.data(), pbytes, dbuf, s));
+        MEK_TRY(store_bytes(start.data(), sizeof(int) * (size_t)(nb + 1), dbuf + pbytes, s));
+        MEK_TRY(launch_solve_multi(head, max_m, lds, s));
+        return MEK_OK;
+    }
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipError_t e = hipMemcpyAsync(dbuf, K.data(), pbytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -1350,11 +1398,6 @@ int run_multi(int64_t nb, mek_plan_s* const* plans, const std::vector<Layout>& L
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipEventCreate(&ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&ev[1]);
-    SolveParams<T> head = K[0];
-    head.multi = reinterpret_cast<const SolveParams<T>*>(dbuf);
-    head.multi_start = reinterpret_cast<const int*>(dbuf + pbytes);
-    head.multi_n = (int)nb;
-    head.multi_wgs = start[nb];
     if (e == hipSuccess) e = hipEventRecord(ev[0], s);
     if (e == hipSuccess) e = launch_solve_multi(head, max_m, lds, s);
     if (e == hipSuccess) e = hipEventRecord(ev[1], s);
@@ -1368,20 +1411,19 @@ int run_multi(int64_t nb, mek_plan_s* const* plans, const std::vector<Layout>& L
         *kernel_ms += (double)ms;
     for (hipEvent_t x : ev)
         if (x) (void)hipEventDestroy(x);
-    (void)hipFree(dbuf);
     return st;
 }
 
-int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
-                     const double* const* X0, const double* const* Xref,
-                     const mek_solve_opts* o, double* const* X, mek_report* reports,
-                     hipStream_t s) {
+// Checks and team layouts of a ragged batch (host only, nothing enqueued).
+int multi_setup(int64_t nb, const mek_plan* plans, const double* const* C,
+                const double* const* X0, const double* const* Xref, const mek_solve_opts* o,
+                double* const* X, std::vector<mek_plan_s*>& Ps, std::vector<Layout>& Ls) {
     if (nb < 1 || !plans || !C || !X || !o) return MEK_EINVAL;
     // References come per instance through Xref; forced indices and the
     // two-sided projection are single-instance features.
     if (o->X_ref) return MEK_EINVAL;
     if (o->replay_len > 0 || o->variant == MEK_TWOSIDED) return MEK_EUNSUPPORTED;
-    std::vector<mek_plan_s*> Ps(nb);
+    Ps.assign(nb, nullptr);
     for (int64_t b = 0; b < nb; ++b) {
         Ps[b] = plans[b];
         if (!Ps[b] || !C[b] || !X[b]) return MEK_EINVAL;
@@ -1434,9 +1476,21 @@ int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
         ++cap[best];
     }
     const size_t elem = prec == MEK_FP64 ? 8 : 4;
-    std::vector<Layout> Ls(nb);
+    Ls.assign(nb, Layout());
     for (int64_t b = 0; b < nb; ++b)
         if ((st = choose_layout_cap(Ps[b], elem, cap[b], false, &Ls[b]))) return st;
+    return MEK_OK;
+}
+
+int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
+                     const double* const* X0, const double* const* Xref,
+                     const mek_solve_opts* o, double* const* X, mek_report* reports,
+                     hipStream_t s) {
+    std::vector<mek_plan_s*> Ps;
+    std::vector<Layout> Ls;
+    int st = multi_setup(nb, plans, C, X0, Xref, o, X, Ps, Ls);
+    if (st) return st;
+    const int prec = Ps[0]->precision;
     // Per instance: workspace, the finite checks, ||C||^2, ||X_ref||^2, the
     // starting residual, X^0 and X_ref transposed.
     std::vector<double> C2(nb, 0.0), ref2(nb, 1.0);
@@ -1508,6 +1562,74 @@ int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
         else if (ret >= 0 && sb < 0) ret = sb;
     }
     return ret;
+}
+
+// Stream-ordered ragged batch: the steps of solve_multi_impl without a host
+// wait (norms on the device, table through kernel arguments, reports to the
+// caller's device structs). Every plan's workspace and the first plan's
+// table must exist (one earlier call on the same plans).
+int solve_multi_async_impl(int64_t nb, const mek_plan* plans, const double* const* C,
+                           const double* const* X0, const double* const* Xref,
+                           const mek_solve_opts* o, double* const* X, void* dev_reports,
+                           hipStream_t s) {
+    if (!dev_reports) return MEK_EINVAL;
+    std::vector<mek_plan_s*> Ps;
+    std::vector<Layout> Ls;
+    int st = multi_setup(nb, plans, C, X0, Xref, o, X, Ps, Ls);
+    if (st) return st;
+    if ((st = check_dev(dev_reports, sizeof(DevReport) * (size_t)nb))) return st;
+    const int prec = Ps[0]->precision;
+    const bool cap = capturing(s);
+    for (int64_t b = 0; b < nb; ++b) {
+        if (Ps[b]->ws.base) continue;
+        if (cap) return MEK_EUNSUPPORTED;   // a captured call must not allocate
+        if ((st = ensure_workspace(Ps[b], 1))) return st;
+    }
+    for (int64_t b = 0; b < nb; ++b) {
+        mek_plan_s* P = Ps[b];
+        const int64_t m = P->m, p = P->p, q = P->q, n = P->n;
+        const double* x0 = X0 ? X0[b] : nullptr;
+        const double* xr = Xref ? Xref[b] : nullptr;
+        Workspace& w = P->ws;
+        MEK_TRY(sq_norm(C[b], m * n, w.scal + 2, w.red, s));
+        if (xr) {
+            MEK_TRY(sq_norm(xr, p * q, w.scal + 3, w.red, s));
+            MEK_TRY(transpose_to<double>(xr, (int)p, (int)q, w.Xref_t, s));
+        } else {
+            MEK_TRY(fill_zero_bytes(w.scal + 3, 8, s));
+        }
+        if (x0) {
+            MEK_TRY(gemm_f64((int)m, (int)q, (int)p, 1.0, P->A, p, 1, x0, q, 1, 0.0, nullptr, 0,
+                             w.T64, q, s));
+            MEK_TRY(gemm_f64((int)m, (int)n, (int)q, -1.0, w.T64, q, 1, P->B, n, 1, 1.0, C[b], n,
+                             w.R64, n, s));
+        } else {
+            MEK_TRY(copy_f64(C[b], m * n, w.R64, s));
+        }
+        if (prec == MEK_FP64) {
+            if (x0) MEK_TRY(transpose_to<double>(x0, (int)p, (int)q, w.Xt64, s));
+            else MEK_TRY(fill_zero_bytes(w.Xt64, (long long)(p * q) * 8, s));
+        } else {
+            MEK_TRY(convert_f64_f32(w.R64, m * n, w.R32, s));
+            if (x0) MEK_TRY(transpose_to<float>(x0, (int)p, (int)q, w.Xt32, s));
+            else MEK_TRY(fill_zero_bytes(w.Xt32, (long long)(p * q) * 4, s));
+        }
+    }
+    std::vector<double> C2(nb, 1.0), ref2(nb, 1.0);
+    std::vector<DevReport> rep(nb);
+    DevReport* dr = (DevReport*)dev_reports;
+    st = prec == MEK_FP64
+             ? run_multi<double>(nb, Ps.data(), Ls, o, C2, ref2, Xref, s, rep, nullptr, dr)
+             : run_multi<float>(nb, Ps.data(), Ls, o, C2, ref2, Xref, s, rep, nullptr, dr);
+    if (st) return st;
+    for (int64_t b = 0; b < nb; ++b) {
+        mek_plan_s* P = Ps[b];
+        if (prec == MEK_FP64)
+            MEK_TRY(transpose_from<double>(P->ws.Xt64, (int)P->p, (int)P->q, X[b], s));
+        else
+            MEK_TRY(transpose_from<float>(P->ws.Xt32, (int)P->p, (int)P->q, X[b], s));
+    }
+    return MEK_OK;
 }
 
 // Stream-ordered solve (FP64 / FP32, one instance): every step is a kernel
@@ -1620,6 +1742,13 @@ extern "C" {
 int mek_solve_async(mek_plan P, const double* C, const double* X0, const mek_solve_opts* o,
                     double* X, mek_device_report* dev_report, void* stream) {
     return solve_async_impl(P, C, X0, o, X, dev_report, (hipStream_t)stream);
+}
+
+int mek_solve_multi_async(int64_t nb, const mek_plan* plans, const double* const* C,
+                          const double* const* X0, const double* const* X_ref,
+                          const mek_solve_opts* o, double* const* X, mek_device_report* dev_reports,
+                          void* stream) {
+    return solve_multi_async_impl(nb, plans, C, X0, X_ref, o, X, dev_reports, (hipStream_t)stream);
 }
 
 int mek_solve_multi(int64_t nb, const mek_plan* plans, const double* const* C,

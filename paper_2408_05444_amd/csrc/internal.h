@@ -307,6 +307,10 @@ hipError_t convert_f64_f32(const double* x, long long len, float* y, hipStream_t
 hipError_t convert_f32_f64(const float* x, long long len, double* y, hipStream_t s);
 hipError_t copy_f64(const double* x, long long len, double* y, hipStream_t s);
 hipError_t fill_zero_bytes(void* x, long long bytes, hipStream_t s);
+// Store `bytes` of host data at dst (device, 8-byte aligned, room for bytes
+// rounded up to 8) through kernel arguments, kBlobWords words per launch.
+constexpr int kBlobWords = 64;
+hipError_t store_bytes(const void* src, size_t bytes, void* dst, hipStream_t s);
 // out = a x + b y elementwise (out may alias x or y).
 hipError_t lincomb_f64(double a, const double* x, double b, const double* y, long long len,
                        double* out, hipStream_t s);

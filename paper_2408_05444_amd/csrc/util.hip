@@ -2,6 +2,8 @@
 // the active-row list and the column pick of the repeated squaring for ||B||_2^2.
 #include "internal.h"
 
+#include <string.h>
+
 #include <math.h>
 
 namespace mek {
@@ -222,6 +224,32 @@ hipError_t fill_zero_bytes(void* x, long long bytes, hipStream_t s) {
     const long long words = (bytes + 3) / 4;
     hipLaunchKernelGGL(zero_kernel, ew_grid(words), dim3(256), 0, s, (unsigned int*)x, words);
     return hipGetLastError();
+}
+// Bytes carried in a launch's arguments and stored by the kernel: a host
+// table reaches device memory through kernel nodes only (no copy node that
+// would read host memory again when a captured graph is replayed).
+struct ArgBlob {
+    unsigned long long w[kBlobWords];
+};
+__global__ void store_blob_kernel(ArgBlob b, int words, unsigned long long* __restrict__ dst) {
+    const int t = threadIdx.x;
+    if (t < words) dst[t] = b.w[t];
+}
+hipError_t store_bytes(const void* src, size_t bytes, void* dst, hipStream_t s) {
+    const unsigned char* in = (const unsigned char*)src;
+    unsigned long long* out = (unsigned long long*)dst;
+    for (size_t off = 0; off < bytes; off += kBlobWords * 8) {
+        ArgBlob b;
+        memset(&b, 0, sizeof(b));
+        const size_t len = bytes - off < (size_t)kBlobWords * 8 ? bytes - off : (size_t)kBlobWords * 8;
+        memcpy(&b, in + off, len);
+        const int words = (int)((len + 7) / 8);
+        hipLaunchKernelGGL(store_blob_kernel, dim3(1), dim3(kBlobWords), 0, s, b, words,
+                           out + off / 8);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 hipError_t lincomb_f64(double a, const double* x, double b, const double* y, long long len,
                        double* out, hipStream_t s) {

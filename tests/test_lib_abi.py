@@ -28,7 +28,7 @@ def test_header_declares_the_boundary():
                  "mek_residual", "mek_residual_batched", "mek_gram", "mek_solve_multi", "mek_solve_async",
                  "mek_cnn_conv3x3", "mek_cnn_conv3x3_grad_input", "mek_cnn_conv3x3_grad_weight",
                  "mek_cnn_mse_grad", "mek_cnn_adam", "mek_cnn_to_bf16", "mek_cnn_round_bf16",
-                 "mek_plan_sparse_widths"]:
+                 "mek_plan_sparse_widths", "mek_solve_multi_async"]:
         assert want in names
 
 
@@ -126,6 +126,7 @@ def test_host_validation_rejects_before_any_gpu_work():
     assert L.mek_residual_batched(0, 1, 1, 1, 1, vp(8), vp(8), vp(8), vp(8), vp(64), None) == EINVAL
     assert L.mek_solve_multi(0, None, None, None, None, None, None, None, None) == EINVAL
     assert L.mek_solve_async(None, vp(8), None, None, vp(8), vp(8), None) == EINVAL
+    assert L.mek_solve_multi_async(0, None, None, None, None, None, None, vp(8), None) == EINVAL
     assert L.mek_cnn_conv3x3(1, 4, 8, 8, 32, vp(2), vp(4), None, 1, vp(8), None, None, None) == EINVAL
     assert L.mek_cnn_conv3x3(1, 3, 8, 8, 32, vp(2), vp(4), None, 1, vp(8), vp(16), None, None) == EINVAL
     assert L.mek_cnn_conv3x3(1, 3, 8, 8, 32, vp(2), vp(4), None, 1, vp(8), None, vp(8), None) == EINVAL
