@@ -275,9 +275,14 @@ int mek_solve_async(mek_plan plan, const double* C, const double* X0, const mek_
  * output) are device pointers. opts is shared; opts->X_ref must be NULL
  * (references come through X_ref); each history holds batch x hist_cap
  * entries, instance b from b * hist_cap. Returns as mek_solve_batched.
- * Errors: MEK_EINVAL for bad arguments, a repeated plan or mixed
- * precisions; MEK_EUNSUPPORTED for MEK_MIXED or SPARSE plans, replay_idx,
- * the two-sided variant or batch above the compute units. */
+ * SPARSE plans (all plans SPARSE, or none): every instance is one
+ * work-group of one launch, the batch is not bounded by the compute units,
+ * and instances may share a plan (the j-th instance on a plan uses the
+ * j-th slice of its workspace, which grows to hold them).
+ * Errors: MEK_EINVAL for bad arguments, a repeated DENSE plan, or mixed
+ * precisions or update modes; MEK_EUNSUPPORTED for MEK_MIXED plans,
+ * replay_idx, the two-sided variant or a DENSE batch above the compute
+ * units. */
 int mek_solve_multi(int64_t batch, const mek_plan* plans, const double* const* C,
                     const double* const* X0, const double* const* X_ref,
                     const mek_solve_opts* opts, double* const* X, mek_report* reports,

@@ -83,6 +83,9 @@ struct mek_plan_s {
     // (kept across calls, so that stream-ordered calls allocate nothing).
     void* mtab = nullptr;
     size_t mtab_bytes = 0;
+    // Parameter table of a ragged launch of sparse plans (grown as needed).
+    void* stab = nullptr;
+    size_t stab_bytes = 0;
     Workspace ws;
 };
 
@@ -210,7 +213,7 @@ int ensure_workspace(mek_plan_s* P, int64_t nb) {
 void free_plan(mek_plan_s* P) {
     if (!P) return;
     void* ptrs[] = {P->A, P->B, P->BT, P->GA, P->GB, P->a, P->bcol, P->active, P->A32, P->B32,
-                    P->BT32, P->GA32, P->GB32, P->ws.base, P->blk, P->ell, P->mtab};
+                    P->BT32, P->GA32, P->GB32, P->ws.base, P->blk, P->ell, P->mtab, P->stab};
     for (void* x : ptrs)
         if (x) (void)hipFree(x);
     delete P;
@@ -530,25 +533,11 @@ int build_sparse(mek_plan_s* P, hipStream_t s) {
 // One launch of the sparse-update kernel for the instances in `slots` (their
 // residuals already in ws.R64), X0 (stacked, or NULL) as the start and X
 // (stacked) as the output.
+// The kernel parameters of a sparse plan's solve (R, X and X_ref pointers,
+// reports, slots and batch size are the caller's); returns the LDS bytes.
 template <typename T>
-int run_sparse(mek_plan_s* P, const mek_solve_opts* o, double alpha,
-               const std::vector<InstSlot>& slots, const double* X0, double* X, hipStream_t s,
-               DevReport* out, double* kernel_ms) {
-    Workspace& w = P->ws;
-    const int nb = (int)slots.size();
+size_t fill_sparse(const mek_plan_s* P, const mek_solve_opts* o, double alpha, SparseParams<T>& K) {
     const int64_t m = P->m, p = P->p, q = P->q, n = P->n;
-    const long long mn = m * n, pq = p * q;
-    const bool f64 = sizeof(T) == 8;
-    T* R = f64 ? (T*)w.R64 : (T*)w.R32;
-    T* Xs = f64 ? (T*)w.Xacc : (T*)w.Xt32;
-    if (!f64) MEK_TRY(convert_f64_f32(w.R64, nb * mn, w.R32, s));
-    if (X0) {
-        if (f64) MEK_TRY(copy_f64(X0, nb * pq, w.Xacc, s));
-        else MEK_TRY(convert_f64_f32(X0, nb * pq, w.Xt32, s));
-    } else {
-        MEK_TRY(fill_zero_bytes(Xs, nb * pq * (long long)sizeof(T), s));
-    }
-    SparseParams<T> K;
     memset(&K, 0, sizeof(K));
     K.m = (int)m; K.p = (int)p; K.q = (int)q; K.n = (int)n;
     K.a_idx = P->a_idx;   K.a_val = (const T*)P->a_val;   K.ka = P->ell_w[0];
@@ -559,14 +548,8 @@ int run_sparse(mek_plan_s* P, const mek_solve_opts* o, double alpha,
     K.F_A = P->F_A;
     K.active = P->active;
     K.n_active = P->n_active;
-    K.R = R;
-    K.sR = mn;
-    K.X = Xs;
-    K.sX = pq;
-    K.Xref = o->X_ref;
-    K.report = w.report;
-    K.slots = w.slots;
-    K.nb = nb;
+    K.sR = m * n;
+    K.sX = p * q;
     // LDS beyond the required state, taken in this order while it fits:
     // ||A_i||^2 (read by every selection), B's ELL slots (every v and w),
     // then those of A A^T and A (every update's row lists).
@@ -580,7 +563,6 @@ int run_sparse(mek_plan_s* P, const mek_solve_opts* o, double alpha,
     K.a_in_lds = lds_for(true, false, false) <= budget ? 1 : 0;
     K.b_in_lds = lds_for(K.a_in_lds, true, false) <= budget ? 1 : 0;
     K.g_in_lds = lds_for(K.a_in_lds, K.b_in_lds, true) <= budget ? 1 : 0;
-    const size_t lds = lds_for(K.a_in_lds, K.b_in_lds, K.g_in_lds);
     K.variant = o->variant;
     K.theta = o->theta;
     K.alpha = alpha;
@@ -595,6 +577,48 @@ int run_sparse(mek_plan_s* P, const mek_solve_opts* o, double alpha,
     K.idx_hist = o->idx_hist;
     K.set_hist = o->set_hist;
     K.hist_cap = o->hist_cap;
+    return lds_for(K.a_in_lds, K.b_in_lds, K.g_in_lds);
+}
+
+// R^0 already in ws.R64 (nb instances): the start X^0 into the kernel's X
+// buffer (row-major p x q per instance), R in the kernel's precision.
+template <typename T>
+int sparse_state(mek_plan_s* P, int nb, const double* X0, T** R, T** Xs, hipStream_t s) {
+    Workspace& w = P->ws;
+    const long long mn = P->m * P->n, pq = P->p * P->q;
+    const bool f64 = sizeof(T) == 8;
+    *R = f64 ? (T*)w.R64 : (T*)w.R32;
+    *Xs = f64 ? (T*)w.Xacc : (T*)w.Xt32;
+    if (!f64) MEK_TRY(convert_f64_f32(w.R64, nb * mn, w.R32, s));
+    if (X0) {
+        if (f64) MEK_TRY(copy_f64(X0, nb * pq, w.Xacc, s));
+        else MEK_TRY(convert_f64_f32(X0, nb * pq, w.Xt32, s));
+    } else {
+        MEK_TRY(fill_zero_bytes(*Xs, nb * pq * (long long)sizeof(T), s));
+    }
+    return MEK_OK;
+}
+
+template <typename T>
+int run_sparse(mek_plan_s* P, const mek_solve_opts* o, double alpha,
+               const std::vector<InstSlot>& slots, const double* X0, double* X, hipStream_t s,
+               DevReport* out, double* kernel_ms) {
+    Workspace& w = P->ws;
+    const int nb = (int)slots.size();
+    const int64_t m = P->m, n = P->n;
+    const long long pq = P->p * P->q;
+    const bool f64 = sizeof(T) == 8;
+    T *R = nullptr, *Xs = nullptr;
+    int st0 = sparse_state<T>(P, nb, X0, &R, &Xs, s);
+    if (st0) return st0;
+    SparseParams<T> K;
+    const size_t lds = fill_sparse<T>(P, o, alpha, K);
+    K.R = R;
+    K.X = Xs;
+    K.Xref = o->X_ref;
+    K.report = w.report;
+    K.slots = w.slots;
+    K.nb = nb;
     MEK_TRY(hipMemcpyAsync(w.slots, slots.data(), sizeof(InstSlot) * nb, hipMemcpyHostToDevice, s));
     // MEK_PHASES=1: time the phases of each update on work-group 0 and print
     // the averages to stderr (profiling aid).
@@ -1414,6 +1438,169 @@ int run_multi(int64_t nb, mek_plan_s* const* plans, const std::vector<Layout>& L
     return st;
 }
 
+// Ragged batch of sparse plans: every instance one work-group of one plain
+// launch, its complete parameters in a table in the first plan. Instances
+// may share a plan: the j-th instance on a plan uses the j-th per-instance
+// slice of that plan's workspace (R, X, slot, report).
+template <typename T>
+int run_sparse_multi(int64_t nb, mek_plan_s* const* Ps, const mek_solve_opts* o,
+                     const double* const* C, const double* const* X0, const double* const* Xref,
+                     double* const* X, hipStream_t s, std::vector<DevReport>& rep,
+                     double* kernel_ms) {
+    // Occurrence of each instance on its plan, and the workspaces.
+    std::vector<int> occ(nb, 0);
+    {
+        std::vector<std::pair<mek_plan_s*, int>> seen;
+        for (int64_t b = 0; b < nb; ++b) {
+            int j = 0;
+            for (auto& pr : seen)
+                if (pr.first == Ps[b]) j = ++pr.second;
+            if (j == 0) seen.push_back({Ps[b], 0});
+            occ[b] = j;
+        }
+        for (auto& pr : seen) {
+            int st = ensure_workspace(pr.first, pr.second + 1);
+            if (st) return st;
+        }
+    }
+    std::vector<SparseParams<T>> K(nb);
+    std::vector<InstSlot> slots(nb);
+    size_t lds = 0;
+    int max_m = 1;
+    const bool f64 = sizeof(T) == 8;
+    for (int64_t b = 0; b < nb; ++b) {
+        mek_plan_s* P = Ps[b];
+        Workspace& w = P->ws;
+        const int j = occ[b];
+        const int64_t m = P->m, p = P->p, q = P->q, n = P->n;
+        const long long mn = m * n, pq = p * q;
+        const double* x0 = X0 ? X0[b] : nullptr;
+        const double* xr = Xref ? Xref[b] : nullptr;
+        int st;
+        if ((st = finite_check(C[b], mn, w.iscal, s))) return st;
+        if (x0 && (st = finite_check(x0, pq, w.iscal, s))) return st;
+        if (xr && (st = finite_check(xr, pq, w.iscal, s))) return st;
+        InstSlot& sl = slots[b];
+        memset(&sl, 0, sizeof(sl));
+        MEK_TRY(sq_norm(C[b], mn, w.scal + 2, w.red, s));
+        if ((st = read_scalar(w.scal + 2, &sl.C2, s))) return st;
+        sl.ref2 = 1.0;
+        if (xr) {
+            MEK_TRY(sq_norm(xr, pq, w.scal + 3, w.red, s));
+            if ((st = read_scalar(w.scal + 3, &sl.ref2, s))) return st;
+            if (!(sl.ref2 > 0.0)) sl.ref2 = 1.0;
+        }
+        sl.id = 0;
+        sl.max_iters = o->max_iters;
+        sl.inst = o->instance + (uint64_t)b;
+        // R^0 = C - A X^0 B (or C) into slice j, then the kernel's state.
+        double* R64 = w.R64 + (size_t)j * mn;
+        if (x0) {
+            MEK_TRY(gemm_f64((int)m, (int)q, (int)p, 1.0, P->A, p, 1, x0, q, 1, 0.0, nullptr, 0,
+                             w.T64, q, s));
+            MEK_TRY(gemm_f64((int)m, (int)n, (int)q, -1.0, w.T64, q, 1, P->B, n, 1, 1.0, C[b], n,
+                             R64, n, s));
+        } else {
+            MEK_TRY(copy_f64(C[b], mn, R64, s));
+        }
+        T* R = f64 ? (T*)R64 : (T*)(w.R32 + (size_t)j * mn);
+        T* Xs = f64 ? (T*)(w.Xacc + (size_t)j * pq) : (T*)(w.Xt32 + (size_t)j * pq);
+        if (!f64) MEK_TRY(convert_f64_f32(R64, mn, (float*)R, s));
+        if (x0) {
+            if (f64) MEK_TRY(copy_f64(x0, pq, (double*)Xs, s));
+            else MEK_TRY(convert_f64_f32(x0, pq, (float*)Xs, s));
+        } else {
+            MEK_TRY(fill_zero_bytes(Xs, pq * (long long)sizeof(T), s));
+        }
+        lds = std::max(lds, fill_sparse<T>(P, o, o->alpha > 0.0 ? o->alpha : P->alpha, K[b]));
+        SparseParams<T>& k = K[b];
+        k.R = R;
+        k.X = Xs;
+        k.Xref = xr;
+        k.report = w.report + j;
+        k.slots = w.slots + j;
+        k.nb = 1;
+        const size_t hc = (size_t)b * (size_t)std::max<int64_t>(o->hist_cap, 0);
+        k.resid_hist = o->resid_hist ? o->resid_hist + hc : nullptr;
+        k.err_hist = o->err_hist ? o->err_hist + hc : nullptr;
+        k.idx_hist = o->idx_hist ? o->idx_hist + hc : nullptr;
+        k.set_hist = o->set_hist ? o->set_hist + hc : nullptr;
+        MEK_TRY(hipMemcpyAsync(w.slots + j, &sl, sizeof(sl), hipMemcpyHostToDevice, s));
+        max_m = std::max(max_m, (int)m);
+    }
+    mek_plan_s* P0 = Ps[0];
+    const size_t tbytes = sizeof(SparseParams<T>) * (size_t)nb;
+    if (!P0->stab || P0->stab_bytes < tbytes) {
+        if (P0->stab) {
+            MEK_TRY(hipDeviceSynchronize());
+            (void)hipFree(P0->stab);
+            P0->stab = nullptr;
+            P0->stab_bytes = 0;
+        }
+        MEK_TRY(hipMalloc(&P0->stab, tbytes));
+        P0->stab_bytes = tbytes;
+    }
+    MEK_TRY(hipMemcpyAsync(P0->stab, K.data(), tbytes, hipMemcpyHostToDevice, s));
+    SparseParams<T> head = K[0];
+    head.m = max_m;   // sizes the selection chunk of every instance
+    head.nb = (int)nb;
+    head.multi = (const SparseParams<T>*)P0->stab;
+    hipEvent_t ev[2];
+    MEK_TRY(hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return MEK_EHIP;
+    }
+    hipError_t e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) e = launch_sparse(head, lds, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    for (int64_t b = 0; b < nb && e == hipSuccess; ++b)
+        e = hipMemcpyAsync(&rep[b], Ps[b]->ws.report + occ[b], sizeof(DevReport),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int st = hip_status(e);
+    float ms = 0.0f;
+    if (st == MEK_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess && kernel_ms)
+        *kernel_ms += (double)ms;
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (st) return st;
+    for (int64_t b = 0; b < nb; ++b) {
+        const mek_plan_s* P = Ps[b];
+        const long long pq = P->p * P->q;
+        if (f64) MEK_TRY(copy_f64(P->ws.Xacc + (size_t)occ[b] * pq, pq, X[b], s));
+        else MEK_TRY(convert_f32_f64(P->ws.Xt32 + (size_t)occ[b] * pq, pq, X[b], s));
+    }
+    return MEK_OK;
+}
+
+// Host reports of a ragged batch and its combined status: MEK_OK when every
+// instance met the stop rule, else the first failing status (errors first).
+int finish_reports(int64_t nb, mek_plan_s* const* Ps, const std::vector<Layout>& Ls,
+                   const mek_solve_opts* o, const double* const* Xref,
+                   const std::vector<DevReport>& rep, double kms, mek_report* reports,
+                   bool sparse) {
+    int ret = MEK_OK;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (reports) {
+            mek_report& r = reports[b];
+            r.iters = rep[b].iters;
+            r.status = rep[b].status;
+            r.resid2 = rep[b].S;
+            r.rel_err = (Xref && Xref[b]) ? rep[b].err : NAN;
+            r.alpha = o->alpha > 0.0 ? o->alpha : Ps[b]->alpha;
+            r.team_wgs = sparse ? 1 : Ls[b].W;
+            r.r_in_lds = 0;
+            r.passes = 1;
+            r.kernel_ms = kms;
+        }
+        const int sb = rep[b].status;
+        if (ret == MEK_OK && sb != MEK_OK) ret = sb;
+        else if (ret >= 0 && sb < 0) ret = sb;
+    }
+    return ret;
+}
+
 // Checks and team layouts of a ragged batch (host only, nothing enqueued).
 int multi_setup(int64_t nb, const mek_plan* plans, const double* const* C,
                 const double* const* X0, const double* const* Xref, const mek_solve_opts* o,
@@ -1427,11 +1614,12 @@ int multi_setup(int64_t nb, const mek_plan* plans, const double* const* C,
     for (int64_t b = 0; b < nb; ++b) {
         Ps[b] = plans[b];
         if (!Ps[b] || !C[b] || !X[b]) return MEK_EINVAL;
-        for (int64_t c = 0; c < b; ++c)
-            if (Ps[c] == Ps[b]) return MEK_EINVAL;   // each instance needs its own workspace
+        if (Ps[b]->update != MEK_UPDATE_SPARSE)
+            for (int64_t c = 0; c < b; ++c)
+                if (Ps[c] == Ps[b]) return MEK_EINVAL;   // a team needs its plan's workspace
         if (Ps[b]->precision != Ps[0]->precision || Ps[b]->device != Ps[0]->device)
             return MEK_EINVAL;
-        if (Ps[b]->update == MEK_UPDATE_SPARSE) return MEK_EUNSUPPORTED;
+        if (Ps[b]->update != Ps[0]->update) return MEK_EINVAL;
         mek_solve_opts ob = *o;
         ob.X_ref = Xref ? Xref[b] : nullptr;
         int st = validate_opts(Ps[b], &ob);
@@ -1439,8 +1627,10 @@ int multi_setup(int64_t nb, const mek_plan* plans, const double* const* C,
     }
     const int prec = Ps[0]->precision;
     if (prec == MEK_MIXED) return MEK_EUNSUPPORTED;
+    const bool sparse = Ps[0]->update == MEK_UPDATE_SPARSE;
     const int cus = std::max(1, Ps[0]->cus);
-    if (nb > cus) return MEK_EUNSUPPORTED;
+    if (!sparse && nb > cus) return MEK_EUNSUPPORTED;
+    if (nb > INT32_MAX / 2) return MEK_EINVAL;
     int st;
     for (int64_t b = 0; b < nb; ++b) {
         const mek_plan_s* P = Ps[b];
@@ -1456,6 +1646,8 @@ int multi_setup(int64_t nb, const mek_plan* plans, const double* const* C,
         if (o->idx_hist && (st = check_dev(o->idx_hist, hc * 4))) return st;
         if (o->set_hist && (st = check_dev(o->set_hist, hc * 4))) return st;
     }
+    Ls.assign(nb, Layout());
+    if (sparse) return MEK_OK;   // one work-group per instance, no team layout
     // Work-group caps: starting from one each, every further work-group goes
     // to the instance with the most elements per work-group that one update
     // touches (R, B twice for v and w, X), so the slowest team is as fast as
@@ -1491,6 +1683,18 @@ int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
     int st = multi_setup(nb, plans, C, X0, Xref, o, X, Ps, Ls);
     if (st) return st;
     const int prec = Ps[0]->precision;
+    const bool sparse = Ps[0]->update == MEK_UPDATE_SPARSE;
+    if (sparse) {
+        std::vector<DevReport> rep(nb);
+        memset(rep.data(), 0, sizeof(DevReport) * nb);
+        double kms = 0.0;
+        st = prec == MEK_FP64
+                 ? run_sparse_multi<double>(nb, Ps.data(), o, C, X0, Xref, X, s, rep, &kms)
+                 : run_sparse_multi<float>(nb, Ps.data(), o, C, X0, Xref, X, s, rep, &kms);
+        if (st) return st;
+        MEK_TRY(hipStreamSynchronize(s));
+        return finish_reports(nb, Ps.data(), Ls, o, Xref, rep, kms, reports, true);
+    }
     // Per instance: workspace, the finite checks, ||C||^2, ||X_ref||^2, the
     // starting residual, X^0 and X_ref transposed.
     std::vector<double> C2(nb, 0.0), ref2(nb, 1.0);
@@ -1543,25 +1747,7 @@ int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
             MEK_TRY(transpose_from<float>(P->ws.Xt32, (int)P->p, (int)P->q, X[b], s));
     }
     MEK_TRY(hipStreamSynchronize(s));
-    int ret = MEK_OK;
-    for (int64_t b = 0; b < nb; ++b) {
-        if (reports) {
-            mek_report& r = reports[b];
-            r.iters = rep[b].iters;
-            r.status = rep[b].status;
-            r.resid2 = rep[b].S;
-            r.rel_err = (Xref && Xref[b]) ? rep[b].err : NAN;
-            r.alpha = o->alpha > 0.0 ? o->alpha : Ps[b]->alpha;
-            r.team_wgs = Ls[b].W;
-            r.r_in_lds = 0;
-            r.passes = 1;
-            r.kernel_ms = kms;
-        }
-        const int sb = rep[b].status;
-        if (ret == MEK_OK && sb != MEK_OK) ret = sb;
-        else if (ret >= 0 && sb < 0) ret = sb;
-    }
-    return ret;
+    return finish_reports(nb, Ps.data(), Ls, o, Xref, rep, kms, reports, false);
 }
 
 // Stream-ordered ragged batch: the steps of solve_multi_impl without a host
@@ -1578,6 +1764,7 @@ int solve_multi_async_impl(int64_t nb, const mek_plan* plans, const double* cons
     int st = multi_setup(nb, plans, C, X0, Xref, o, X, Ps, Ls);
     if (st) return st;
     if ((st = check_dev(dev_reports, sizeof(DevReport) * (size_t)nb))) return st;
+    if (Ps[0]->update == MEK_UPDATE_SPARSE) return MEK_EUNSUPPORTED;
     const int prec = Ps[0]->precision;
     const bool cap = capturing(s);
     for (int64_t b = 0; b < nb; ++b) {

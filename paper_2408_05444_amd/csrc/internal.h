@@ -159,6 +159,9 @@ struct SparseParams {
     int32_t* set_hist;
     long long hist_cap;
     unsigned long long* phase;   // optional: per-phase wall-clock ticks of work-group 0
+    // Ragged batch: nb instances, work-group b taking the complete
+    // parameters multi[b] (whose slots hold one slot, of index 0).
+    const SparseParams* multi;
 };
 hipError_t launch_sparse(const SparseParams<double>& P, size_t lds_bytes, hipStream_t s);
 hipError_t launch_sparse(const SparseParams<float>& P, size_t lds_bytes, hipStream_t s);

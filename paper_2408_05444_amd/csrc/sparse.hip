@@ -146,7 +146,11 @@ template <typename T, int SR>
 __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     __shared__ BlockScratch sc;
-    const InstSlot sl = P.slots[blockIdx.x];
+    // Ragged batch: work-group b runs instance b with its own parameters
+    // (own plan, sizes, state and slot).
+    const bool ragged = P.multi != nullptr;
+    if (ragged) P = P.multi[blockIdx.x];
+    const InstSlot sl = P.slots[ragged ? 0 : blockIdx.x];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int m = P.m, n = P.n, p = P.p, q = P.q;
     T* const R = P.R + (size_t)sl.id * P.sR;

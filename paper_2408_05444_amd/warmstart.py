@@ -148,61 +148,97 @@ class WarmStartNet:
         return hist
 
 
+def _instances(images):
+    return [(i, c) for i in range(len(images)) for c in range(images[i][2].shape[0])]
+
+
 def solver_labels(mek, images, tau: float, max_iters: int = 1_000_000, seed: int = 0,
-                  chunk: int = 63):
+                  chunk: int = 768):
     """Training labels produced by the solver itself: for each image
-    (A, B, C) with C (3, H, W) on the GPU, the FP64 ME-GRBK iterate from
-    X0 = 0 at relative residual ||C - A X B||_F <= tau ||C||_F (or after
-    max_iters), every channel an instance of ragged launches of up to
-    `chunk` instances. Returns a list of (3, H, W) tensors."""
-    inst = [(i, c) for i in range(len(images)) for c in range(images[i][2].shape[0])]
-    out = [torch.empty_like(images[i][2]) for i in range(len(images))]
+    (A, B, C) with C (channels, H, W) on the GPU, the FP64 ME-GRBK iterate
+    from X0 = 0 at relative residual ||C - A X B||_F <= tau ||C||_F (or after
+    max_iters). Every image is one sparse-update plan shared by its
+    channels, every channel one instance (one work-group) of ragged launches
+    of up to `chunk` instances; instance k of the list of (image, channel)
+    pairs draws under Philox key (seed, k). Returns a list of tensors shaped
+    like the C's."""
+    inst = _instances(images)
+    out = [torch.empty_like(im[2]) for im in images]
     for s0 in range(0, len(inst), chunk):
         part = inst[s0:s0 + chunk]
-        plans = [mek.mek_plan_create(images[i][0], images[i][1]) for i, _ in part]
+        plans = {}
         try:
-            _, res = mek.mek_solve_multi(plans, [images[i][2][c].contiguous() for i, c in part],
+            for i, _ in part:
+                if i not in plans:
+                    plans[i] = mek.mek_plan_create(images[i][0], images[i][1], update="sparse")
+            _, res = mek.mek_solve_multi([plans[i] for i, _ in part],
+                                         [images[i][2][c].contiguous() for i, c in part],
                                          variant="grbk", stop="rel_resid", tol=tau,
                                          max_iters=max_iters, seed=seed, instance=s0)
             for (i, c), r in zip(part, res):
                 out[i][c].copy_(r.X)
         finally:
-            for P in plans:
+            for P in plans.values():
                 mek.mek_plan_destroy(P)
     return out
 
 
-def compare_warm_start(mek, net: WarmStartNet, A, B, C, tau: float, max_iters: int = 1_000_000,
-                       seed: int = 0):
-    """Solve the channels of one image (uniform batch sharing A and B) to
-    relative residual tau from X0 = 0 and from X0 = C + f(C). A channel
-    falls back to X0 = 0 when ||C - A X0 B||_F >= ||C||_F. Returns a dict of
-    iterations, times, start residuals and fallbacks."""
-    plan = mek.mek_plan_create(A, B)
+def compare_warm_start(mek, net: WarmStartNet, images, tau: float, max_iters: int = 1_000_000,
+                       seed: int = 0, chunk: int = 768, predict_batch: int = 32):
+    """Solve every channel of the held-out images [(A, B, C)] to relative
+    residual tau from X0 = 0 and from X0 = C + f(C), in ragged launches of
+    sparse-update plans (one per image, created before the clocks start). A
+    channel falls back to X0 = 0 when ||C - A X0 B||_F >= ||C||_F. Returns
+    per-channel iterations, statuses, start residuals and fallbacks, and the
+    wall time of each side (the warm side includes the network's
+    prediction and the residual check)."""
+    inst = _instances(images)
+    plans = [mek.mek_plan_create(A, B, update="sparse") for A, B, _ in images]
     try:
         kw = dict(variant="grbk", stop="rel_resid", tol=tau, max_iters=max_iters, seed=seed)
+
+        def solve_all(X0s=None, iters=None):
+            res = []
+            for s0 in range(0, len(inst), chunk):
+                part = inst[s0:s0 + chunk]
+                k = dict(kw, instance=s0)
+                if iters is not None:
+                    k["max_iters"] = iters
+                _, r = mek.mek_solve_multi(
+                    [plans[i] for i, _ in part], [images[i][2][c].contiguous() for i, c in part],
+                    X0=None if X0s is None else [X0s[i][c].contiguous() for i, c in part], **k)
+                res += r
+            return res
+
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        _, base = mek.mek_solve_batched(plan, C, **kw)
+        base = solve_all()
         torch.cuda.synchronize()
         t_base = time.perf_counter() - ts
         ts = time.perf_counter()
-        X0 = net.predict(C.unsqueeze(0).contiguous())[0].contiguous()
-        # The judge of the prediction: the residual it leaves (no update made).
-        _, r0 = mek.mek_solve_batched(plan, C, X0=X0, max_iters=0)
-        _, z0 = mek.mek_solve_batched(plan, C, max_iters=0)
-        fallback = [r0[c].resid2 >= z0[c].resid2 for c in range(C.shape[0])]
-        for c, fb in enumerate(fallback):
+        X0s = []
+        for b0 in range(0, len(images), predict_batch):
+            C = torch.stack([images[i][2] for i in range(b0, min(len(images), b0 + predict_batch))])
+            X0s += list(net.predict(C.contiguous()))
+        # The judge of the prediction: the residual it leaves against the
+        # zero start's, both from solves that make no update.
+        r0 = solve_all(X0s, iters=0)
+        z0 = solve_all(None, iters=0)
+        fallback = []
+        for (i, c), r, z in zip(inst, r0, z0):
+            fb = not (r.resid2 < z.resid2)
+            fallback.append(fb)
             if fb:
-                X0[c].zero_()
-        _, warm = mek.mek_solve_batched(plan, C, X0=X0, **kw)
+                X0s[i][c].zero_()
+        warm = solve_all(X0s)
         torch.cuda.synchronize()
         t_warm = time.perf_counter() - ts
         return {"iters_zero": [r.iters for r in base], "iters_warm": [r.iters for r in warm],
                 "status_zero": [r.status for r in base], "status_warm": [r.status for r in warm],
                 "time_zero_s": t_base, "time_warm_s": t_warm,
-                "start_rel_resid_warm": [float(np.sqrt(r0[c].resid2 / z0[c].resid2))
-                                         for c in range(C.shape[0])],
+                "start_rel_resid_warm": [float(np.sqrt(r.resid2 / z.resid2))
+                                         for r, z in zip(r0, z0)],
                 "fallback": fallback}
     finally:
-        mek.mek_plan_destroy(plan)
+        for P in plans:
+            mek.mek_plan_destroy(P)

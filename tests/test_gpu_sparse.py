@@ -200,8 +200,12 @@ def test_sparse_refusals():
         mek.mek_solve_async(plan, cuda(inst.C), max_iters=5)
     assert e.value.code == mek.MEK_EUNSUPPORTED
     with pytest.raises(mek.MekError) as e:
-        mek.mek_solve_multi([plan], [cuda(inst.C)], max_iters=5)
+        mek.mek_solve_multi_async([plan], [cuda(inst.C)], max_iters=5)
     assert e.value.code == mek.MEK_EUNSUPPORTED
+    dense_plan = mek.mek_plan_create(cuda(inst.A), cuda(inst.B))
+    with pytest.raises(mek.MekError) as e:
+        mek.mek_solve_multi([plan, dense_plan], [cuda(inst.C), cuda(inst.C)], max_iters=5)
+    assert e.value.code == mek.MEK_EINVAL
     dense = mek.mek_plan_create(cuda(inst.A), cuda(inst.B))
     with pytest.raises(mek.MekError) as e:
         mek.mek_plan_sparse_widths(dense)
@@ -215,3 +219,68 @@ def test_sparse_refusals():
     with pytest.raises(mek.MekError) as e:
         mek.mek_plan_create(cuda(inst.A), cuda(inst.B), precision="mixed", update="sparse")
     assert e.value.code == mek.MEK_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# Ragged batches of sparse plans (mek_solve_multi): one work-group per
+# instance, plans of different sizes, plans shared between instances.
+# ---------------------------------------------------------------------------
+
+def test_sparse_ragged_equals_single_solves():
+    insts = [workloads.banded_gaussian(40, seed=1, sigma=0.7), CASES["sparse_irregular"](),
+             CASES["sparse_tall"](), workloads.banded_gaussian(64, seed=2, sigma=0.7)]
+    plans = [_sparse_plan(i, oracle.spectral_alpha(i.B)) for i in insts]
+    # plan 0 twice (a second instance of the same A, B with its own C), plan 3 twice
+    rng = np.random.default_rng(3)
+    X2 = rng.standard_normal(insts[0].X_star.shape)
+    X5 = rng.standard_normal(insts[3].X_star.shape)
+    order = [0, 1, 2, 3, 0, 3]
+    Cs = [insts[0].C, insts[1].C, insts[2].C, insts[3].C, insts[0].A @ X2 @ insts[0].B,
+          insts[3].A @ X5 @ insts[3].B]
+    Xr = [insts[0].X_star, insts[1].X_star, insts[2].X_star, insts[3].X_star, X2, X5]
+    kw = dict(variant="grbk", max_iters=1500, seed=17, instance=40)
+    st, res = mek.mek_solve_multi([plans[i] for i in order], [cuda(c) for c in Cs],
+                                  X_ref=[cuda(x) for x in Xr], hist_cap=1501, **kw)
+    assert st == mek.MEK_MAXITER
+    for b, (i, C, x) in enumerate(zip(order, Cs, Xr)):
+        one = mek.mek_solve(plans[i], cuda(C), X_ref=cuda(x), hist_cap=1501,
+                            **{**kw, "instance": 40 + b})
+        assert res[b].iters == one.iters == 1500 and res[b].team_wgs == 1
+        assert torch.equal(res[b].X, one.X)
+        assert torch.equal(res[b].idx_hist, one.idx_hist)
+        assert res[b].rel_err == one.rel_err
+
+
+def test_sparse_ragged_against_oracle_with_warm_start():
+    insts = [CASES["sparse_irregular"](), workloads.banded_gaussian(48, seed=4, sigma=0.7)]
+    alphas = [oracle.spectral_alpha(i.B) for i in insts]
+    plans = [_sparse_plan(i, a) for i, a in zip(insts, alphas)]
+    rng = np.random.default_rng(8)
+    X0 = [rng.standard_normal(i.X_star.shape) for i in insts]
+    st, res = mek.mek_solve_multi(plans, [cuda(i.C) for i in insts], X0=[cuda(x) for x in X0],
+                                  X_ref=[cuda(i.X_star) for i in insts], variant="rgrbk",
+                                  theta=0.7, max_iters=1000, seed=5, hist_cap=1001)
+    for b, (inst, a) in enumerate(zip(insts, alphas)):
+        ref = oracle.solve(inst.A, inst.B, inst.C, X0=X0[b], variant="rgrbk", theta=0.7, alpha=a,
+                           max_iters=1000, seed=5, inst=b, Xref=inst.X_star)
+        assert host(res[b].idx_hist).tolist() == ref.idx.tolist()
+        assert rel(host(res[b].X), ref.X) <= 1e-9
+
+
+def test_sparse_ragged_many_instances_on_shared_plans():
+    # 300 instances (above the compute units) on 3 plans, 100 each.
+    bases = [workloads.banded_gaussian(32, seed=s, sigma=0.7) for s in range(3)]
+    plans = [_sparse_plan(b, 0.0) for b in bases]
+    rng = np.random.default_rng(9)
+    order = [b % 3 for b in range(300)]
+    Xs = [rng.standard_normal((32, 32)) for _ in order]
+    Cs = [bases[i].A @ x @ bases[i].B for i, x in zip(order, Xs)]
+    st, res = mek.mek_solve_multi([plans[i] for i in order], [cuda(c) for c in Cs],
+                                  X_ref=[cuda(x) for x in Xs], stop="rel_err", tol=1e-6,
+                                  max_iters=400000, seed=2)
+    assert st == mek.MEK_OK
+    for b in (0, 1, 2, 150, 299):
+        assert rel(host(res[b].X), Xs[b]) <= 1e-6
+        one = mek.mek_solve(plans[order[b]], cuda(Cs[b]), X_ref=cuda(Xs[b]), stop="rel_err",
+                            tol=1e-6, max_iters=400000, seed=2, instance=b)
+        assert torch.equal(res[b].X, one.X) and res[b].iters == one.iters
