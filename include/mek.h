@@ -108,14 +108,18 @@ typedef struct {
     int team_wgs;    /* 0: automatic; > 0: number of work-groups that share one
                         solve (testing and tuning hook) */
     int r_in_lds;    /* -1: automatic; 0: keep R in device memory; 1: require R
-                        resident in LDS (MEK_EUNSUPPORTED if it does not fit) */
+                        resident in LDS (MEK_EUNSUPPORTED if it does not fit).
+                        SPARSE plans: 0 keeps the row norms and row errors in
+                        device memory (the form taken automatically when
+                        8 (m + p) bytes of them do not fit in LDS or m is
+                        above 8192), otherwise ignored */
     int update;      /* MEK_UPDATE_DENSE (0) or MEK_UPDATE_SPARSE. A SPARSE plan
                         takes FP64 or FP32 (MEK_MIXED: MEK_EUNSUPPORTED) and
                         finds the nonzeros of A, B and A A^T at creation;
                         MEK_EUNSUPPORTED when a row of A or A A^T, or a row or
                         column of B, holds more than 1024 nonzeros, or when
-                        the per-instance state (8 (m + p) + 16 n + 8 q bytes
-                        plus 1 KiB) exceeds the LDS of one work-group */
+                        16 n + 8 q bytes plus 1 KiB exceed the LDS of one
+                        work-group */
 } mek_plan_opts;
 
 typedef struct {

@@ -34,6 +34,7 @@ struct Workspace {
     double* Xtmp = nullptr;    // p x q
     double* Xref_t = nullptr;  // q x p
     double* r = nullptr;       // m
+    double* r2 = nullptr;      // 2m: {||R_i||^2, ratio} pairs of the sparse form in device memory
     void* rowbuf = nullptr;    // n * 8 bytes
     void* wbuf = nullptr;      // n * 8 bytes
     void* vbuf = nullptr;      // q * 8 bytes
@@ -168,6 +169,7 @@ int ensure_workspace(mek_plan_s* P, int64_t nb) {
     add(B * p * q * 8);
     add(B * q * p * 8);
     add(B * m * 8);
+    add(B * m * 16);
     add(B * n * 8);
     add(B * n * 8);
     add(B * q * 8);
@@ -195,6 +197,7 @@ int ensure_workspace(mek_plan_s* P, int64_t nb) {
     w.Xtmp = carve<double>(cur, B * p * q);
     w.Xref_t = carve<double>(cur, B * q * p);
     w.r = carve<double>(cur, B * m);
+    w.r2 = carve<double>(cur, B * m * 2);
     w.rowbuf = carve<double>(cur, B * n);
     w.wbuf = carve<double>(cur, B * n);
     w.vbuf = carve<double>(cur, B * q);
@@ -489,9 +492,8 @@ constexpr int kSparseMaxWidth = 1024;
 // sums of exact zeros, so its pattern is exact).
 int build_sparse(mek_plan_s* P, hipStream_t s) {
     const int m = (int)P->m, p = (int)P->p, q = (int)P->q, n = (int)P->n;
-    if (m > kSelRows * kThreads) return MEK_EUNSUPPORTED;
     const size_t elem = P->precision == MEK_FP64 ? 8 : 4;
-    if (sparse_lds_bytes(m, p, q, n, elem, false, 0, 0, 0, 0) > solve_lds_budget())
+    if (sparse_lds_bytes(m, p, q, n, elem, false, false, 0, 0, 0, 0) > solve_lds_budget())
         return MEK_EUNSUPPORTED;
     int* wd_dev = P->ws.iscal + 2;
     MEK_TRY(fill_zero_bytes(wd_dev, 4 * sizeof(int), s));
@@ -536,7 +538,8 @@ int build_sparse(mek_plan_s* P, hipStream_t s) {
 // The kernel parameters of a sparse plan's solve (R, X and X_ref pointers,
 // reports, slots and batch size are the caller's); returns the LDS bytes.
 template <typename T>
-size_t fill_sparse(const mek_plan_s* P, const mek_solve_opts* o, double alpha, SparseParams<T>& K) {
+size_t fill_sparse(const mek_plan_s* P, const mek_solve_opts* o, double alpha, SparseParams<T>& K,
+                   bool norms_mem = false) {
     const int64_t m = P->m, p = P->p, q = P->q, n = P->n;
     memset(&K, 0, sizeof(K));
     K.m = (int)m; K.p = (int)p; K.q = (int)q; K.n = (int)n;
@@ -550,16 +553,24 @@ size_t fill_sparse(const mek_plan_s* P, const mek_solve_opts* o, double alpha, S
     K.n_active = P->n_active;
     K.sR = m * n;
     K.sX = p * q;
-    // LDS beyond the required state, taken in this order while it fits:
-    // ||A_i||^2 (read by every selection), B's ELL slots (every v and w),
-    // then those of A A^T and A (every update's row lists).
+    // The row norms and row errors stay in LDS when they fit and the
+    // selection's register chunks cover m (the plan's r_in_lds = 0 keeps them
+    // in device memory: the form for instances too large for LDS). The LDS
+    // left is taken in this order while it fits: ||A_i||^2 (read by every
+    // selection), B's ELL slots (every v and w), then those of A A^T and A
+    // (every update's row lists).
     const size_t elem = sizeof(T);
     const size_t budget = solve_lds_budget();
+    K.norms_in_lds = 1;
     auto lds_for = [&](bool a_lds, bool b_lds, bool g_lds) {
-        return sparse_lds_bytes((int)m, (int)p, (int)q, (int)n, elem, a_lds,
+        return sparse_lds_bytes((int)m, (int)p, (int)q, (int)n, elem, K.norms_in_lds != 0, a_lds,
                                 b_lds ? K.kb : 0, b_lds ? K.kbt : 0, g_lds ? K.ka : 0,
                                 g_lds ? K.kg : 0);
     };
+    K.norms_in_lds = (!norms_mem && P->r_in_lds != 0 && m <= (int64_t)kSelRows * kThreads &&
+                      lds_for(false, false, false) <= budget) ? 1 : 0;
+    K.r_glob = P->ws.r2;
+    K.e_glob = P->ws.Xtmp;
     K.a_in_lds = lds_for(true, false, false) <= budget ? 1 : 0;
     K.b_in_lds = lds_for(K.a_in_lds, true, false) <= budget ? 1 : 0;
     K.g_in_lds = lds_for(K.a_in_lds, K.b_in_lds, true) <= budget ? 1 : 0;
@@ -1468,6 +1479,14 @@ int run_sparse_multi(int64_t nb, mek_plan_s* const* Ps, const mek_solve_opts* o,
     size_t lds = 0;
     int max_m = 1;
     const bool f64 = sizeof(T) == 8;
+    // One launch has one selection form: if any instance needs its norms in
+    // device memory, every instance keeps them there.
+    bool norms_mem = false;
+    for (int64_t b = 0; b < nb; ++b) {
+        SparseParams<T> probe;
+        fill_sparse<T>(Ps[b], o, 1.0, probe);
+        norms_mem = norms_mem || !probe.norms_in_lds;
+    }
     for (int64_t b = 0; b < nb; ++b) {
         mek_plan_s* P = Ps[b];
         Workspace& w = P->ws;
@@ -1512,11 +1531,14 @@ int run_sparse_multi(int64_t nb, mek_plan_s* const* Ps, const mek_solve_opts* o,
         } else {
             MEK_TRY(fill_zero_bytes(Xs, pq * (long long)sizeof(T), s));
         }
-        lds = std::max(lds, fill_sparse<T>(P, o, o->alpha > 0.0 ? o->alpha : P->alpha, K[b]));
+        lds = std::max(lds, fill_sparse<T>(P, o, o->alpha > 0.0 ? o->alpha : P->alpha, K[b],
+                                           norms_mem));
         SparseParams<T>& k = K[b];
         k.R = R;
         k.X = Xs;
         k.Xref = xr;
+        k.r_glob = w.r2 + (size_t)j * 2 * m;
+        k.e_glob = w.Xtmp + (size_t)j * pq;
         k.report = w.report + j;
         k.slots = w.slots + j;
         k.nb = 1;

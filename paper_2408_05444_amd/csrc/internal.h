@@ -145,6 +145,10 @@ struct SparseParams {
     int a_in_lds;         // ||A_i||^2 of all rows in LDS
     int b_in_lds;         // the ELL slots of B's rows and columns in LDS
     int g_in_lds;         // the ELL slots of A A^T and A in LDS
+    int norms_in_lds;     // row norms and row errors in LDS (else in r_glob / e_glob)
+    double* r_glob;       // {||R_i||^2, ||R_i||^2/||A_i||^2} pairs per instance (stride 2m),
+                          // when not in LDS
+    double* e_glob;       // p row errors per instance (stride sX), when not in LDS
     int variant;
     double theta, alpha;
     int stop;
@@ -167,8 +171,8 @@ hipError_t launch_sparse(const SparseParams<double>& P, size_t lds_bytes, hipStr
 hipError_t launch_sparse(const SparseParams<float>& P, size_t lds_bytes, hipStream_t s);
 // LDS of the sparse kernel; kb, kbt > 0 when B's ELL slots are cached, ka,
 // kg > 0 when those of A and A A^T are.
-size_t sparse_lds_bytes(int m, int p, int q, int n, size_t elem, bool a_in_lds, int kb, int kbt,
-                        int ka, int kg);
+size_t sparse_lds_bytes(int m, int p, int q, int n, size_t elem, bool norms_in_lds, bool a_in_lds,
+                        int kb, int kbt, int ka, int kg);
 // Largest count of nonzeros over the `rows` lines of M (line i: M[i*rs + j*cs],
 // j < cols), combined into *width_dev with atomicMax (clear it first).
 hipError_t ell_width(const double* M, int rows, int cols, long long rs, long long cs,

@@ -130,6 +130,160 @@ __device__ __forceinline__ double ell_dot(const int* idx, const T* val, int slot
     return acc;
 }
 
+constexpr int kMemBatch = 16;   // rows loaded per batch in the device-memory selection
+
+// Rows [b, b + cnt) of the {r_i, rho_i} pairs (rho_i = r_i / ||A_i||^2, -1
+// for rows with A_i = 0) in batches of kMemBatch 16-byte loads, visited in
+// ascending order; fn(i, r_i, rho_i) returns true to stop.
+template <typename Fn>
+__device__ __forceinline__ void visit_rows(const double2* __restrict__ r2, int b, int cnt, Fn fn) {
+    for (int j0 = 0; j0 < cnt; j0 += kMemBatch) {
+        double2 v[kMemBatch];
+#pragma unroll
+        for (int u = 0; u < kMemBatch; ++u) {
+            const int j = j0 + u;
+            v[u] = j < cnt ? r2[b + j] : make_double2(0.0, -1.0);
+        }
+#pragma unroll
+        for (int u = 0; u < kMemBatch; ++u)
+            if (j0 + u < cnt && fn(b + j0 + u, v[u].x, v[u].y)) return;
+    }
+}
+
+// The same over ||A_i||^2 alone (the weights of Alg. 1).
+template <typename Fn>
+__device__ __forceinline__ void visit_norms(const double* __restrict__ a, int b, int cnt, Fn fn) {
+    for (int j0 = 0; j0 < cnt; j0 += kMemBatch) {
+        double v[kMemBatch];
+#pragma unroll
+        for (int u = 0; u < kMemBatch; ++u) {
+            const int j = j0 + u;
+            v[u] = j < cnt ? a[b + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kMemBatch; ++u)
+            if (j0 + u < cnt && fn(b + j0 + u, v[u])) return;
+    }
+}
+
+// The selection step of Algs. 1-5 over norms held in device memory (an
+// instance whose row norms do not fit in LDS): thread t reads its rows
+// [b, b + cnt) where select_rows would hold them in registers, and every
+// decision, sum and scan follows select_rows in the same order, so the two
+// forms pick the same rows with the same arithmetic. rho_i >= 0 exactly for
+// the rows with ||A_i|| > 0.
+__device__ SelectOut select_rows_mem(int variant, int b, int cnt, const double2* __restrict__ r2,
+                                     const double* __restrict__ a, double S, double M, double F_A,
+                                     double theta, double u, long long k,
+                                     const int* __restrict__ active, int n_active,
+                                     BlockScratch& sc) {
+    SelectOut o;
+    o.setsize = 0;
+    o.t = 0.0;
+    o.T = 0.0;
+    if (variant == kBK) {
+        o.idx = active[k % n_active];
+        return o;
+    }
+    if (variant == kMWRBK) {
+        int cand = INT_MAX;
+        visit_rows(r2, b, cnt, [&](int i, double, double rho) {
+            if (rho >= 0.0 && rho == M) {
+                cand = i;
+                return true;
+            }
+            return false;
+        });
+        if (threadIdx.x == 0) sc.out_i[2] = INT_MAX;
+        cand = wave_min_int(cand);
+        __syncthreads();
+        if ((threadIdx.x & (kWave - 1)) == 0 && cand != INT_MAX) atomicMin(&sc.out_i[2], cand);
+        __syncthreads();
+        o.idx = sc.out_i[2];
+        __syncthreads();
+        o.setsize = 1;
+        o.t = M;
+        return o;
+    }
+    const bool greedy = variant == kGRBK || variant == kRGRBK;
+    double t = 0.0;
+    if (greedy) {
+#pragma clang fp contract(off)
+        const double th = (variant == kGRBK) ? 0.5 : theta;
+        t = th * M + (1.0 - th) * (S / F_A);
+        if (t > M) t = M;
+    }
+    // Members: a_i > 0 and, greedy, r_i / a_i >= t; weights r_i (greedy) or
+    // a_i (Alg. 1).
+    double ws = 0.0;
+    int c = 0, lastm = -1;
+    if (greedy)
+        visit_rows(r2, b, cnt, [&](int i, double ri, double rho) {
+            if (rho >= 0.0 && rho >= t) {
+                ws += ri;
+                ++c;
+                lastm = i;
+            }
+            return false;
+        });
+    else
+        visit_norms(a, b, cnt, [&](int i, double ai) {
+            if (ai > 0.0) {
+                ws += ai;
+                ++c;
+                lastm = i;
+            }
+            return false;
+        });
+    if (threadIdx.x == 0) {
+        sc.out_i[2] = INT_MAX;
+        sc.out_i[3] = -1;
+    }
+    double pre_w, T;
+    int pre_c, tot_c;
+    block_excl_scan(ws, c, pre_w, pre_c, T, tot_c, sc);
+    const double target = u * T;
+    int cand = INT_MAX;
+    if (c > 0) {
+        double run = pre_w;
+        if (greedy)
+            visit_rows(r2, b, cnt, [&](int i, double ri, double rho) {
+                if (rho >= 0.0 && rho >= t) {
+                    run += ri;
+                    if (run > target) {
+                        cand = i;
+                        return true;
+                    }
+                }
+                return false;
+            });
+        else
+            visit_norms(a, b, cnt, [&](int i, double ai) {
+                if (ai > 0.0) {
+                    run += ai;
+                    if (run > target) {
+                        cand = i;
+                        return true;
+                    }
+                }
+                return false;
+            });
+    }
+    cand = wave_min_int(cand);
+    lastm = wave_max_int(lastm);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (cand != INT_MAX) atomicMin(&sc.out_i[2], cand);
+        if (lastm >= 0) atomicMax(&sc.out_i[3], lastm);
+    }
+    __syncthreads();
+    o.idx = (sc.out_i[2] != INT_MAX) ? sc.out_i[2] : sc.out_i[3];
+    o.setsize = tot_c;
+    o.t = t;
+    o.T = T;
+    __syncthreads();
+    return o;
+}
+
 // Optional phase timing (work-group 0, thread 0): wall-clock ticks per phase
 // of an update, summed over the solve.
 enum { kSpPhReduce, kSpPhSelect, kSpPhLoad, kSpPhV, kSpPhWX, kSpPhR, kSpPhCount };
@@ -161,10 +315,16 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
 
     // LDS: [r: m row norms] [e: p row errors] [Philox draws] [||A_i||^2 when
     // P.a_in_lds] [R_{i_k}: n] [v: q] [w: n] [the ELL slots of B's rows and
-    // columns, indices then values, when P.b_in_lds].
-    double* r_l = reinterpret_cast<double*>(dyn_smem);
-    double* e_l = r_l + m;
-    double* u_tab = e_l + p;
+    // columns, indices then values, when P.b_in_lds] [those of A A^T and A,
+    // when P.g_in_lds]. SR = 0: r and e stay in device memory (instances
+    // whose norms do not fit in LDS) and the selection reads them there.
+    constexpr bool kNormsLds = SR > 0;
+    constexpr int kSR = SR > 0 ? SR : 1;
+    double* const lds_d = reinterpret_cast<double*>(dyn_smem);
+    double* r_l = lds_d;   // LDS form
+    double2* const r2g = reinterpret_cast<double2*>(P.r_glob) + (size_t)sl.id * m;   // memory form
+    double* e_l = kNormsLds ? lds_d + m : P.e_glob + (size_t)sl.id * P.sX;
+    double* u_tab = kNormsLds ? lds_d + m + p : lds_d;
     double* a_l = u_tab + kUTable;
     T* rowv = reinterpret_cast<T*>(a_l + (P.a_in_lds ? m : 0));
     T* vv = rowv + ((n + 1) & ~1);
@@ -220,7 +380,10 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
             acc += v * v;
         }
         acc = wave_sum(acc);
-        if (lane == 0) r_l[i] = acc;
+        if (lane == 0) {
+            if constexpr (kNormsLds) r_l[i] = acc;
+            else r2g[i] = make_double2(acc, asrc[i] > 0.0 ? acc / asrc[i] : -1.0);
+        }
     }
     for (int x = wv; x < p; x += kWaves) {
         double acc = 0.0;
@@ -254,16 +417,27 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
         }
         const double u_k = u_tab[k % kUTable];
         // ---- Global quantities and the stop test.
-        double rr[SR], aa[SR], rho[SR];
+        double rr[kSR], aa[kSR], rho[kSR];
         double Sp = 0.0, Mp = -1.0, Ep = 0.0;
+        if constexpr (kNormsLds) {
 #pragma unroll
-        for (int j = 0; j < SR; ++j) {
-            rr[j] = (j < scnt) ? r_l[sb + j] : 0.0;
-            aa[j] = (j < scnt) ? asrc[sb + j] : 0.0;
-            rho[j] = (j < scnt && aa[j] > 0.0) ? rr[j] / aa[j] : -1.0;
-            Sp += rr[j];
-            Mp = fmax(Mp, rho[j]);
+            for (int j = 0; j < SR; ++j) {
+                rr[j] = (j < scnt) ? r_l[sb + j] : 0.0;
+                aa[j] = (j < scnt) ? asrc[sb + j] : 0.0;
+                rho[j] = (j < scnt && aa[j] > 0.0) ? rr[j] / aa[j] : -1.0;
+                Sp += rr[j];
+                Mp = fmax(Mp, rho[j]);
+            }
+        } else {
+            // The same sums and maximum; the register form's padding adds
+            // +0 and -1, which change neither.
+            visit_rows(r2g, sb, scnt, [&](int, double rj, double rho) {
+                Sp += rj;
+                Mp = fmax(Mp, rho);
+                return false;
+            });
         }
+#pragma unroll 8
         for (int j = 0; j < ecnt; ++j) Ep += e_l[eb + j];
         block_sum_max_sum(Sp, Mp, Ep, sc);
         S = Sp;
@@ -289,9 +463,13 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
             ik = P.replay[k];
             last_set = 0;
         } else {
-            const SelectOut so = select_rows<SR>(P.variant, sb, scnt, rr, aa, rho, S, M, P.F_A,
-                                                 P.theta, u_k, k, P.active, P.n_active, sc,
-                                                 nullptr, nullptr);
+            SelectOut so;
+            if constexpr (kNormsLds)
+                so = select_rows<kSR>(P.variant, sb, scnt, rr, aa, rho, S, M, P.F_A, P.theta, u_k, k,
+                                      P.active, P.n_active, sc, nullptr, nullptr);
+            else
+                so = select_rows_mem(P.variant, sb, scnt, r2g, asrc, S, M, P.F_A, P.theta, u_k, k,
+                                     P.active, P.n_active, sc);
             ik = so.idx;
             last_set = so.setsize;
         }
@@ -371,7 +549,10 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
                 acc += (double)nv * (double)nv;
             }
             acc = wave_sum(acc);
-            if (lane == 0) r_l[i] = acc;
+            if (lane == 0) {
+                if constexpr (kNormsLds) r_l[i] = acc;
+                else r2g[i] = make_double2(acc, asrc[i] > 0.0 ? acc / asrc[i] : -1.0);
+            }
         };
 #pragma unroll
         for (int u = 0; u < kSpX; ++u) {
@@ -440,9 +621,9 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
     }
 }
 
-size_t sparse_lds_bytes(int m, int p, int q, int n, size_t elem, bool a_in_lds, int kb,
-                        int kbt, int ka, int kg) {
-    size_t b = (size_t)(m + p + kUTable + (a_in_lds ? m : 0)) * sizeof(double);
+size_t sparse_lds_bytes(int m, int p, int q, int n, size_t elem, bool norms_in_lds,
+                        bool a_in_lds, int kb, int kbt, int ka, int kg) {
+    size_t b = (size_t)((norms_in_lds ? m + p : 0) + kUTable + (a_in_lds ? m : 0)) * sizeof(double);
     b += (size_t)(2 * ((n + 1) & ~1) + ((q + 1) & ~1)) * elem;
     if (kb > 0)   // the ELL slots of B cached in LDS
         b += (size_t)(((kb * q + 1) & ~1) + ((kbt * n + 1) & ~1)) * sizeof(int) +
@@ -465,6 +646,7 @@ static hipError_t launch_sparse_sr(const SparseParams<T>& P, size_t lds_bytes, h
 
 template <typename T>
 static hipError_t launch_sparse_t(const SparseParams<T>& P, size_t lds_bytes, hipStream_t s) {
+    if (!P.norms_in_lds) return launch_sparse_sr<T, 0>(P, lds_bytes, s);
     switch (sel_rows_for(P.m)) {
         case 1: return launch_sparse_sr<T, 1>(P, lds_bytes, s);
         case 2: return launch_sparse_sr<T, 2>(P, lds_bytes, s);

@@ -284,3 +284,89 @@ def test_sparse_ragged_many_instances_on_shared_plans():
         one = mek.mek_solve(plans[order[b]], cuda(Cs[b]), X_ref=cuda(Xs[b]), stop="rel_err",
                             tol=1e-6, max_iters=400000, seed=2, instance=b)
         assert torch.equal(res[b].X, one.X) and res[b].iters == one.iters
+
+
+# ---------------------------------------------------------------------------
+# Row norms and row errors in device memory (instances whose norms do not fit
+# in LDS, or m above the selection's register chunks; forced on small cases
+# with the plan's r_in_lds = 0): the same selection arithmetic as the LDS
+# form, so the two agree bit for bit.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("variant,theta", [("grbk", 0.5), ("rgrbk", 0.8), ("mwrbk", 0.5),
+                                           ("rbk", 0.5), ("bk", 0.5)])
+def test_sparse_norms_in_memory_equal_lds(case, variant, theta):
+    inst = CASES[case]()
+    alpha = oracle.spectral_alpha(inst.B)
+    kw = dict(variant=variant, theta=theta, alpha=alpha, max_iters=1500, seed=23, hist_cap=1501,
+              X_ref=cuda(inst.X_star))
+    a = mek.mek_solve(_sparse_plan(inst, alpha), cuda(inst.C), **kw)
+    b = mek.mek_solve(_sparse_plan(inst, alpha, r_in_lds=0), cuda(inst.C), **kw)
+    assert torch.equal(a.X, b.X)
+    assert torch.equal(a.idx_hist, b.idx_hist) and torch.equal(a.set_hist, b.set_hist)
+    assert torch.equal(a.resid_hist, b.resid_hist) and torch.equal(a.err_hist, b.err_hist)
+
+
+def test_sparse_rows_beyond_lds_match_oracle():
+    # 12 000 rows: above what the selection holds in registers, so the norms
+    # live in device memory. 200 columns keep A A^T sparse (about 540
+    # nonzeros per column); the oracle runs its literal form (R = C - A X B
+    # recomputed every update, no m x m Gram matrix), which its own pins tie
+    # to the maintained-residual form.
+    inst = workloads.sparse_random(12000, 200, 5, 20, seed=3, empty_rows=50)
+    alpha = oracle.spectral_alpha(inst.B)
+    for variant, theta in [("grbk", 0.5), ("rgrbk", 0.8), ("rbk", 0.5)]:
+        ref = oracle.solve(inst.A, inst.B, inst.C, variant=variant, theta=theta, alpha=alpha,
+                           max_iters=300, seed=5, Xref=inst.X_star, literal=True)
+        res = mek.mek_solve(_sparse_plan(inst, alpha), cuda(inst.C), variant=variant,
+                            theta=theta, alpha=alpha, max_iters=300, seed=5, hist_cap=301,
+                            X_ref=cuda(inst.X_star))
+        assert host(res.idx_hist).tolist() == ref.idx.tolist(), variant
+        assert np.allclose(host(res.resid_hist), ref.s_hist, rtol=1e-8, atol=0)
+        assert rel(host(res.X), ref.X) <= 1e-9
+
+
+def test_sparse_norms_in_memory_batch_and_ragged():
+    base = workloads.banded_gaussian(40, seed=9, sigma=0.7)
+    rng = np.random.default_rng(12)
+    Xs = rng.standard_normal((3, 40, 40))
+    C = np.stack([base.A @ X @ base.B for X in Xs])
+    kw = dict(variant="grbk", max_iters=800, seed=3, instance=7)
+    mem = _sparse_plan(base, 0.0, r_in_lds=0)
+    lds = _sparse_plan(base, 0.0)
+    _, rb = mek.mek_solve_batched(mem, cuda(C), **kw)
+    _, rl = mek.mek_solve_batched(lds, cuda(C), **kw)
+    for b in range(3):
+        assert torch.equal(rb[b].X, rl[b].X)
+    # A ragged batch mixing an instance that needs memory norms with one that
+    # would fit: both run the memory form and still match their own solves.
+    tall = workloads.sparse_random(9000, 200, 6, 30, seed=4, empty_rows=20)
+    pt = _sparse_plan(tall, 0.0)
+    st, res = mek.mek_solve_multi([pt, lds], [cuda(tall.C), cuda(C[0])], variant="grbk",
+                                  max_iters=800, seed=3, instance=7)
+    one_t = mek.mek_solve(pt, cuda(tall.C), variant="grbk", max_iters=800, seed=3, instance=7)
+    one_s = mek.mek_solve(lds, cuda(C[0]), variant="grbk", max_iters=800, seed=3, instance=8)
+    assert torch.equal(res[0].X, one_t.X) and torch.equal(res[1].X, one_s.X)
+
+
+# ---------------------------------------------------------------------------
+# The paper's colour-image model: A (hw x hw) the 2-D Gaussian blur (5 x 5
+# taps, sigma 6, zero padding), B = A_c^T (3 x 3, printed in the paper).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant,theta", [("grbk", 0.5), ("rgrbk", 0.8), ("mwrbk", 0.5),
+                                           ("rbk", 0.5)])
+def test_paper_image_model_matches_oracle(variant, theta):
+    inst = workloads.paper_image_model(18, 15, seed=5, random_image=True)
+    alpha = oracle.spectral_alpha(inst.B)
+    ref = oracle.solve(inst.A, inst.B, inst.C, variant=variant, theta=theta, alpha=alpha,
+                       max_iters=2000, seed=31, Xref=inst.X_star)
+    plan = _sparse_plan(inst, alpha)
+    assert mek.mek_plan_sparse_widths(plan) == (25, 3, 3, 81)
+    for p in (plan, _sparse_plan(inst, alpha, r_in_lds=0)):
+        res = mek.mek_solve(p, cuda(inst.C), variant=variant, theta=theta, alpha=alpha,
+                            max_iters=2000, seed=31, hist_cap=2001, X_ref=cuda(inst.X_star))
+        assert host(res.idx_hist).tolist() == ref.idx.tolist()
+        assert np.allclose(host(res.resid_hist), ref.s_hist, rtol=1e-8, atol=0)
+        assert rel(host(res.X), ref.X) <= 1e-9

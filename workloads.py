@@ -216,6 +216,52 @@ def sparse_random(m: int, p: int, q: int, n: int, seed: int, row_nnz=(2, 4),
                     _c(A @ X @ B), _c(X))
 
 
+def gaussian_taps(size: int = 5, sigma: float = 6.0) -> np.ndarray:
+    """The 1-D factor g of the size x size Gaussian kernel exp(-(x^2 + y^2) /
+    (2 sigma^2)) normalised to sum 1: the 2-D kernel is the outer product
+    g g^T (g itself sums to 1)."""
+    x = np.arange(size) - (size - 1) / 2.0
+    g = np.exp(-x ** 2 / (2.0 * sigma ** 2))
+    return g / g.sum()
+
+
+def blur_factor(n: int, taps: np.ndarray) -> np.ndarray:
+    """n x n Toeplitz matrix applying the centred 1-D taps with zero
+    padding (no renormalisation at the border)."""
+    h = len(taps) // 2
+    T = np.zeros((n, n))
+    for i in range(n):
+        for d in range(-h, h + 1):
+            if 0 <= i + d < n:
+                T[i, i + d] = taps[d + h]
+    return T
+
+
+# The cross-channel blurring matrix printed in the paper's colour image
+# example (rows: output channel R, G, B).
+CROSS_CHANNEL = np.array([[0.9, 0.05, 0.05], [0.0, 0.9, 0.1], [0.05, 0.1, 0.85]])
+
+
+def paper_image_model(h: int, w: int, seed: int, size: int = 5, sigma: float = 6.0,
+                      random_image: bool = False) -> Instance:
+    """The paper's colour-image model A X A_c^T = C on a synthetic h x w x 3
+    image: X (hw x 3) holds the column-major vectorised channels, A (hw x hw)
+    = T_w kron T_h is the 2-D Gaussian blur (size x size taps, sigma, zero
+    padding), B = A_c^T (3 x 3). Built densely (for the sizes of tests).
+    random_image: X iid N(0,1) from default_rng(seed) instead of the
+    synthetic picture (whose flat regions give rows with equal ratios, exact
+    ties that rounding breaks differently in different summation orders)."""
+    g = gaussian_taps(size, sigma)
+    A = np.kron(blur_factor(w, g), blur_factor(h, g))
+    if random_image:
+        X = np.random.default_rng(seed).standard_normal((h * w, 3))
+    else:
+        img = synthetic_image(h, w, 3, seed)
+        X = np.stack([img[c].T.reshape(-1) for c in range(3)], axis=1)
+    B = CROSS_CHANNEL.T.copy()
+    return Instance(f"paper image model {h}x{w} seed={seed}", _c(A), _c(B), _c(A @ X @ B), _c(X))
+
+
 def synthetic_image(h: int, w: int, channels: int, seed: int,
                     n_rect: int = 8, n_disc: int = 8) -> np.ndarray:
     """channels x h x w image in [0,1]: a per-channel linear gradient, then
