@@ -188,6 +188,44 @@ def blur_batch_forms(mek, workloads, torch):
     return out
 
 
+def variant_sweep_forms(mek, workloads, torch, A, B, C, Xs, seed):
+    """The variant sweep on the large workload: ME-GRBK, ME-RGRBK (theta 0.5
+    and 1) and ME-MWRBK in FP64 (to relative error 1e-6) and FP32 (to 1e-4,
+    its reach); then ME-GRBK in FP64 on the rank-deficient case A = U V
+    (rank 250, data seed 3) to 1e-6 against the least-norm solution
+    A^+ C B^+ = V^T (V V^T)^-1 V X* (B has full row rank and U full column
+    rank, so A^+ A is the projector onto the rows of V). Wall time of plan
+    set-up + solve."""
+    out = {}
+
+    def run(key, A_, B_, C_, Xr, prec, v, th, tol):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        plan = mek.mek_plan_create(A_, B_, precision=prec)
+        r = mek.mek_solve(plan, C_, variant=v, theta=th, stop="rel_err", tol=tol, X_ref=Xr,
+                          max_iters=5_000_000, seed=seed)
+        mek.mek_plan_destroy(plan)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - ts
+        out[key] = {"tol": tol, "time_to_tol_s": te, "iters": r.iters,
+                    "iters_per_s": r.iters / te, "rel_err": r.rel_err, "status": r.status,
+                    "kernel_us_per_update": r.kernel_ms * 1e3 / max(r.iters, 1)}
+
+    for prec, tol in [("fp64", 1e-6), ("fp32", 1e-4)]:
+        for v, th in [("grbk", 0.5), ("rgrbk", 0.5), ("rgrbk", 1.0), ("mwrbk", 0.5)]:
+            run(f"{prec}_{v}_theta{th}", A, B, C, Xs, prec, v, th, tol)
+    rd = workloads.large_rankdef()
+    rng = np.random.default_rng(3)
+    U = rng.standard_normal((2000, 250))
+    V = rng.standard_normal((250, 500))
+    assert np.allclose(U @ V, rd.A)
+    Xln = V.T @ np.linalg.solve(V @ V.T, V @ rd.X_star)
+    dev = A.device
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    run("fp64_grbk_rank250", t(rd.A), t(rd.B), t(rd.C), t(Xln), "fp64", "grbk", 0.5, 1e-6)
+    return out
+
+
 def paper_table_forms(mek, workloads, torch, trials=20):
     """The paper's Example 5.2 / Table 4 on its two Gaussian sets (Set 2: A
     140 x 30, B 70 x 160; Set 5: A 230 x 50, B 110 x 240) and Example 5.1 /
@@ -460,6 +498,8 @@ def main():
     ap.add_argument("--test-images", type=int, default=0,
                     help="warm-start form: held-out images (0: the default)")
     ap.add_argument("--epochs", type=int, default=0, help="warm-start form: epochs (0: the default)")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only run the variant sweep on the large workload and print it")
     ap.add_argument("--image-only", action="store_true",
                     help="only run the paper's colour-image model at its image sizes and print it")
     ap.add_argument("--images", default="",
@@ -508,6 +548,10 @@ def main():
         if args.epochs:
             kw["epochs"] = args.epochs
         print(json.dumps({"warm_start": warm_start_forms(mek, workloads, torch, **kw)}), flush=True)
+        return
+    if args.sweep_only:
+        print(json.dumps({"variant_sweep": variant_sweep_forms(mek, workloads, torch, A, B, C, Xs,
+                                                               seed)}), flush=True)
         return
     if args.image_only:
         names = args.images.split(",") if args.images else ("face", "bird", "mandril")
@@ -610,6 +654,7 @@ def main():
                              "time_to_tol_s": te, "steps": r.iters, "rel_err": r.rel_err,
                              "status": r.status,
                              "kernel_us_per_step": r.kernel_ms * 1e3 / max(r.iters, 1)}
+        forms["variant_sweep"] = variant_sweep_forms(mek, workloads, torch, A, B, C, Xs, seed)
         forms["blur3_batched"] = blur_batch_forms(mek, workloads, torch)
         forms["blur_sparse_96ch"] = sparse_many_forms(mek, workloads, torch)
         forms["paper_tables"] = paper_table_forms(mek, workloads, torch)
