@@ -654,13 +654,19 @@ def main():
                              "time_to_tol_s": te, "steps": r.iters, "rel_err": r.rel_err,
                              "status": r.status,
                              "kernel_us_per_step": r.kernel_ms * 1e3 / max(r.iters, 1)}
-        forms["variant_sweep"] = variant_sweep_forms(mek, workloads, torch, A, B, C, Xs, seed)
-        forms["blur3_batched"] = blur_batch_forms(mek, workloads, torch)
-        forms["blur_sparse_96ch"] = sparse_many_forms(mek, workloads, torch)
-        forms["paper_tables"] = paper_table_forms(mek, workloads, torch)
-        forms["paper_images"] = paper_image_forms(mek, workloads, torch)
-        forms["ragged64_fp32"] = ragged_batch_forms(mek, workloads, torch)
-        forms["warm_start"] = warm_start_forms(mek, workloads, torch)
+        # Each form reports to stderr when it ends (the run takes minutes).
+        for name, fn in [
+                ("variant_sweep", lambda: variant_sweep_forms(mek, workloads, torch, A, B, C, Xs, seed)),
+                ("blur3_batched", lambda: blur_batch_forms(mek, workloads, torch)),
+                ("blur_sparse_96ch", lambda: sparse_many_forms(mek, workloads, torch)),
+                ("paper_tables", lambda: paper_table_forms(mek, workloads, torch)),
+                ("paper_images", lambda: paper_image_forms(mek, workloads, torch)),
+                ("ragged64_fp32", lambda: ragged_batch_forms(mek, workloads, torch)),
+                ("warm_start", lambda: warm_start_forms(mek, workloads, torch))]:
+            t0 = time.perf_counter()
+            forms[name] = fn()
+            print(f"[bench] form {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
         line["forms"] = forms
         line["gemm_mfma_f64"] = gemm_forms(mek, torch, A, B, Xs, C,
                                            blur=blur_tensors(workloads, torch))
