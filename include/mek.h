@@ -254,8 +254,8 @@ typedef struct mek_device_report {
  * (device memory) when the stream reaches it. Nothing in the call reads
  * device data on the host, so once the plan's workspace exists (after one
  * call of any solve on the plan) it can be captured into a graph. FP64 and
- * FP32 plans; MIXED and SPARSE plans, the two-sided variant and replay_idx
- * return MEK_EUNSUPPORTED. No finite check of the inputs is made (non-finite data
+ * FP32 plans, DENSE or SPARSE; MIXED plans, the two-sided variant and
+ * replay_idx return MEK_EUNSUPPORTED. No finite check of the inputs is made (non-finite data
  * ends in MEK_EDIVERGED or a non-finite report). X, the histories and the
  * plan's workspace must not be touched until the stream has passed the
  * call; calls on one plan must be ordered on one stream. A later call that

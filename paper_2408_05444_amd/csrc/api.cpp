@@ -1915,11 +1915,56 @@ int enqueue_solve(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, const
     return MEK_OK;
 }
 
+// Stream-ordered solve of a SPARSE plan: the steps of run_sparse with the
+// norms computed on the device and the instance slot stored through kernel
+// arguments, the report written to the caller's device struct.
+template <typename T>
+int enqueue_sparse(mek_plan_s* P, const mek_solve_opts* o, const double* C, const double* X0,
+                   double* X, DevReport* dev_report, hipStream_t s) {
+    Workspace& w = P->ws;
+    const int64_t m = P->m, p = P->p, q = P->q, n = P->n;
+    MEK_TRY(sq_norm(C, m * n, w.scal + 2, w.red, s));
+    if (o->X_ref) MEK_TRY(sq_norm(o->X_ref, p * q, w.scal + 3, w.red, s));
+    else MEK_TRY(fill_zero_bytes(w.scal + 3, 8, s));
+    if (X0) {
+        MEK_TRY(gemm_f64((int)m, (int)q, (int)p, 1.0, P->A, p, 1, X0, q, 1, 0.0, nullptr, 0, w.T64,
+                         q, s));
+        MEK_TRY(gemm_f64((int)m, (int)n, (int)q, -1.0, w.T64, q, 1, P->B, n, 1, 1.0, C, n, w.R64, n,
+                         s));
+    } else {
+        MEK_TRY(copy_f64(C, m * n, w.R64, s));
+    }
+    T *R = nullptr, *Xs = nullptr;
+    int st = sparse_state<T>(P, 1, X0, &R, &Xs, s);
+    if (st) return st;
+    SparseParams<T> K;
+    const size_t lds = fill_sparse<T>(P, o, o->alpha > 0.0 ? o->alpha : P->alpha, K);
+    K.R = R;
+    K.X = Xs;
+    K.Xref = o->X_ref;
+    K.report = dev_report;
+    K.slots = w.slots;
+    K.nb = 1;
+    K.norms = w.scal + 2;
+    InstSlot sl;
+    memset(&sl, 0, sizeof(sl));
+    sl.id = 0;
+    sl.C2 = 1.0;
+    sl.ref2 = 1.0;
+    sl.max_iters = o->max_iters;
+    sl.inst = o->instance;
+    MEK_TRY(store_bytes(&sl, sizeof(sl), w.slots, s));
+    MEK_TRY(launch_sparse(K, lds, s));
+    const long long pq = p * q;
+    if (sizeof(T) == 8) MEK_TRY(copy_f64(w.Xacc, pq, X, s));
+    else MEK_TRY(convert_f32_f64(w.Xt32, pq, X, s));
+    return MEK_OK;
+}
+
 int solve_async_impl(mek_plan P, const double* C, const double* X0, const mek_solve_opts* o,
                      double* X, void* dev_report, hipStream_t s) {
     if (!P || !C || !X || !dev_report || !o) return MEK_EINVAL;
-    if (P->precision == MEK_MIXED || P->update == MEK_UPDATE_SPARSE ||
-        o->variant == MEK_TWOSIDED || o->replay_len > 0)
+    if (P->precision == MEK_MIXED || o->variant == MEK_TWOSIDED || o->replay_len > 0)
         return MEK_EUNSUPPORTED;
     int st = validate_opts(P, o);
     if (st) return st;
@@ -1936,8 +1981,13 @@ int solve_async_impl(mek_plan P, const double* C, const double* X0, const mek_so
         if (o->idx_hist && (st = check_dev(o->idx_hist, hc * 4))) return st;
         if (o->set_hist && (st = check_dev(o->set_hist, hc * 4))) return st;
     }
-    Layout L;
     const bool f64 = P->precision == MEK_FP64;
+    if (P->update == MEK_UPDATE_SPARSE) {
+        if ((st = ensure_workspace(P, 1))) return st;
+        return f64 ? enqueue_sparse<double>(P, o, C, X0, X, (DevReport*)dev_report, s)
+                   : enqueue_sparse<float>(P, o, C, X0, X, (DevReport*)dev_report, s);
+    }
+    Layout L;
     if ((st = choose_layout(P, f64 ? 8 : 4, 1, &L))) return st;
     if ((st = ensure_workspace(P, 1))) return st;
     return f64 ? enqueue_solve<double>(P, o, L, C, X0, X, (DevReport*)dev_report, s)

@@ -166,6 +166,10 @@ struct SparseParams {
     // Ragged batch: nb instances, work-group b taking the complete
     // parameters multi[b] (whose slots hold one slot, of index 0).
     const SparseParams* multi;
+    // Optional (stream-ordered solves, one instance): {||C||_F^2,
+    // ||X_ref||_F^2} read from device memory instead of the slot's C2 and
+    // ref2 (0 for the second means no reference).
+    const double* norms;
 };
 hipError_t launch_sparse(const SparseParams<double>& P, size_t lds_bytes, hipStream_t s);
 hipError_t launch_sparse(const SparseParams<float>& P, size_t lds_bytes, hipStream_t s);

@@ -304,7 +304,11 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
     // (own plan, sizes, state and slot).
     const bool ragged = P.multi != nullptr;
     if (ragged) P = P.multi[blockIdx.x];
-    const InstSlot sl = P.slots[ragged ? 0 : blockIdx.x];
+    InstSlot sl = P.slots[ragged ? 0 : blockIdx.x];
+    if (P.norms) {   // stream-ordered solves: the norms were computed on the device
+        sl.C2 = P.norms[0];
+        sl.ref2 = P.norms[1] > 0.0 ? P.norms[1] : 1.0;
+    }
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int m = P.m, n = P.n, p = P.p, q = P.q;
     T* const R = P.R + (size_t)sl.id * P.sR;

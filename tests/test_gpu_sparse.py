@@ -197,9 +197,6 @@ def test_sparse_refusals():
         mek.mek_solve(plan, cuda(inst.C), variant="twosided", max_iters=5)
     assert e.value.code == mek.MEK_EUNSUPPORTED
     with pytest.raises(mek.MekError) as e:
-        mek.mek_solve_async(plan, cuda(inst.C), max_iters=5)
-    assert e.value.code == mek.MEK_EUNSUPPORTED
-    with pytest.raises(mek.MekError) as e:
         mek.mek_solve_multi_async([plan], [cuda(inst.C)], max_iters=5)
     assert e.value.code == mek.MEK_EUNSUPPORTED
     dense_plan = mek.mek_plan_create(cuda(inst.A), cuda(inst.B))
@@ -370,3 +367,53 @@ def test_paper_image_model_matches_oracle(variant, theta):
         assert host(res.idx_hist).tolist() == ref.idx.tolist()
         assert np.allclose(host(res.resid_hist), ref.s_hist, rtol=1e-8, atol=0)
         assert rel(host(res.X), ref.X) <= 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Stream-ordered solves of sparse plans (mek_solve_async): the same result as
+# mek_solve, and capture into a graph replayed with eager work in between.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,mem", [("fp64", False), ("fp32", False), ("fp64", True)])
+def test_sparse_async_equals_sync(precision, mem):
+    inst = workloads.blurred_image(64, 1, 0.7, seed=8)[0]
+    kw = {"r_in_lds": 0} if mem else {}
+    plan = _sparse_plan(inst, 0.0, precision=precision, **kw)
+    X0 = cuda(np.full(inst.X_star.shape, 0.05))
+    opts = dict(variant="rgrbk", theta=0.8, stop="rel_err", tol=1e-4, X_ref=cuda(inst.X_star),
+                max_iters=200000, seed=6, instance=3)
+    one = mek.mek_solve(plan, cuda(inst.C), X0=X0, hist_cap=64, **opts)
+    hist = mek.make_histories(64)
+    X, rep = mek.mek_solve_async(plan, cuda(inst.C), X0=X0, hist=hist, **opts)
+    torch.cuda.synchronize()
+    r = mek.read_device_report(rep)
+    assert r["status"] == one.status == mek.MEK_OK and r["iters"] == one.iters
+    assert r["resid2"] == one.resid2 and r["rel_err"] == one.rel_err
+    assert torch.equal(X, one.X)
+    assert torch.equal(hist["idx_hist"][:64], one.idx_hist[:64])
+
+
+def test_sparse_async_graph_capture_and_replay():
+    inst = workloads.blurred_image(64, 1, 0.7, seed=9)[0]
+    plan = _sparse_plan(inst, 0.0)
+    C, Xr = cuda(inst.C), cuda(inst.X_star)
+    kw = dict(variant="grbk", stop="rel_err", tol=1e-5, X_ref=Xr, max_iters=400000, seed=12)
+    X_e, rep_e = mek.mek_solve_async(plan, C, **kw)   # eager first: the workspace exists
+    torch.cuda.synchronize()
+    eager = mek.read_device_report(rep_e)
+    assert eager["status"] == mek.MEK_OK
+    Xg = torch.empty_like(X_e)
+    repg = torch.zeros(mek.DEVICE_REPORT_BYTES, dtype=torch.uint8, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        mek.mek_solve_async(plan, C, X_out=Xg, report=repg, **kw)
+    for rep_i in range(3):
+        Xg.fill_(float(rep_i))
+        repg.zero_()
+        junk = mek.mek_solve(plan, C, variant="rbk", max_iters=60, seed=rep_i)
+        assert junk.iters == 60
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert mek.read_device_report(repg) == eager
+        assert torch.equal(Xg, X_e)
