@@ -301,7 +301,11 @@ int mek_solve_multi(int64_t batch, const mek_plan* plans, const double* const* C
  * batch size (one earlier mek_solve_multi or mek_solve_multi_async call on
  * the same plans), the call can be captured into a graph and replayed; a
  * captured call that would need either returns MEK_EUNSUPPORTED (outside
- * capture they are allocated). No finite check of the inputs is made.
+ * capture they are allocated). SPARSE plans as in mek_solve_multi (shared
+ * plans, any batch size); their table holds at least 1024 instances and
+ * moves only for a larger batch, after which graphs captured earlier on
+ * that first plan must not be replayed. No finite check of the inputs is
+ * made.
  * Other errors and refusals as mek_solve_multi. X, the histories and the
  * plans' workspaces must not be touched until the stream has passed the
  * call; calls sharing a plan must be ordered on one stream. A later call

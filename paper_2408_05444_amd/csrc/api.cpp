@@ -1457,7 +1457,12 @@ template <typename T>
 int run_sparse_multi(int64_t nb, mek_plan_s* const* Ps, const mek_solve_opts* o,
                      const double* const* C, const double* const* X0, const double* const* Xref,
                      double* const* X, hipStream_t s, std::vector<DevReport>& rep,
-                     double* kernel_ms) {
+                     double* kernel_ms, DevReport* dev_reports = nullptr) {
+    // Stream-ordered (dev_reports set): no host reads or waits; the norms go
+    // to the kernel through device memory, slots and table through kernel
+    // arguments, and nothing is allocated while the stream is captured.
+    const bool async = dev_reports != nullptr;
+    const bool cap = async && capturing(s);
     // Occurrence of each instance on its plan, and the workspaces.
     std::vector<int> occ(nb, 0);
     {
@@ -1470,6 +1475,8 @@ int run_sparse_multi(int64_t nb, mek_plan_s* const* Ps, const mek_solve_opts* o,
             occ[b] = j;
         }
         for (auto& pr : seen) {
+            if (cap && (!pr.first->ws.base || pr.first->ws.cap < pr.second + 1))
+                return MEK_EUNSUPPORTED;   // a captured call must not allocate
             int st = ensure_workspace(pr.first, pr.second + 1);
             if (st) return st;
         }
@@ -1496,18 +1503,26 @@ int run_sparse_multi(int64_t nb, mek_plan_s* const* Ps, const mek_solve_opts* o,
         const double* x0 = X0 ? X0[b] : nullptr;
         const double* xr = Xref ? Xref[b] : nullptr;
         int st;
-        if ((st = finite_check(C[b], mn, w.iscal, s))) return st;
-        if (x0 && (st = finite_check(x0, pq, w.iscal, s))) return st;
-        if (xr && (st = finite_check(xr, pq, w.iscal, s))) return st;
         InstSlot& sl = slots[b];
         memset(&sl, 0, sizeof(sl));
-        MEK_TRY(sq_norm(C[b], mn, w.scal + 2, w.red, s));
-        if ((st = read_scalar(w.scal + 2, &sl.C2, s))) return st;
         sl.ref2 = 1.0;
-        if (xr) {
-            MEK_TRY(sq_norm(xr, pq, w.scal + 3, w.red, s));
-            if ((st = read_scalar(w.scal + 3, &sl.ref2, s))) return st;
-            if (!(sl.ref2 > 0.0)) sl.ref2 = 1.0;
+        double* norms = w.errpart + (size_t)j * kErrStride;   // unused by this kernel otherwise
+        if (async) {
+            sl.C2 = 1.0;
+            MEK_TRY(sq_norm(C[b], mn, norms, w.red, s));
+            if (xr) MEK_TRY(sq_norm(xr, pq, norms + 1, w.red, s));
+            else MEK_TRY(fill_zero_bytes(norms + 1, 8, s));
+        } else {
+            if ((st = finite_check(C[b], mn, w.iscal, s))) return st;
+            if (x0 && (st = finite_check(x0, pq, w.iscal, s))) return st;
+            if (xr && (st = finite_check(xr, pq, w.iscal, s))) return st;
+            MEK_TRY(sq_norm(C[b], mn, w.scal + 2, w.red, s));
+            if ((st = read_scalar(w.scal + 2, &sl.C2, s))) return st;
+            if (xr) {
+                MEK_TRY(sq_norm(xr, pq, w.scal + 3, w.red, s));
+                if ((st = read_scalar(w.scal + 3, &sl.ref2, s))) return st;
+                if (!(sl.ref2 > 0.0)) sl.ref2 = 1.0;
+            }
         }
         sl.id = 0;
         sl.max_iters = o->max_iters;
@@ -1539,34 +1554,51 @@ int run_sparse_multi(int64_t nb, mek_plan_s* const* Ps, const mek_solve_opts* o,
         k.Xref = xr;
         k.r_glob = w.r2 + (size_t)j * 2 * m;
         k.e_glob = w.Xtmp + (size_t)j * pq;
-        k.report = w.report + j;
+        k.report = async ? dev_reports + b : w.report + j;
         k.slots = w.slots + j;
         k.nb = 1;
+        if (async) k.norms = norms;
         const size_t hc = (size_t)b * (size_t)std::max<int64_t>(o->hist_cap, 0);
         k.resid_hist = o->resid_hist ? o->resid_hist + hc : nullptr;
         k.err_hist = o->err_hist ? o->err_hist + hc : nullptr;
         k.idx_hist = o->idx_hist ? o->idx_hist + hc : nullptr;
         k.set_hist = o->set_hist ? o->set_hist + hc : nullptr;
-        MEK_TRY(hipMemcpyAsync(w.slots + j, &sl, sizeof(sl), hipMemcpyHostToDevice, s));
+        if (async) MEK_TRY(store_bytes(&sl, sizeof(sl), w.slots + j, s));
+        else MEK_TRY(hipMemcpyAsync(w.slots + j, &sl, sizeof(sl), hipMemcpyHostToDevice, s));
         max_m = std::max(max_m, (int)m);
     }
+    // The table, in the first plan: at least 1024 entries, so that batches
+    // up to that size never move it under a captured graph.
     mek_plan_s* P0 = Ps[0];
     const size_t tbytes = sizeof(SparseParams<T>) * (size_t)nb;
     if (!P0->stab || P0->stab_bytes < tbytes) {
+        if (cap) return MEK_EUNSUPPORTED;
         if (P0->stab) {
             MEK_TRY(hipDeviceSynchronize());
             (void)hipFree(P0->stab);
             P0->stab = nullptr;
             P0->stab_bytes = 0;
         }
-        MEK_TRY(hipMalloc(&P0->stab, tbytes));
-        P0->stab_bytes = tbytes;
+        const size_t want = std::max(tbytes, sizeof(SparseParams<double>) * (size_t)1024);
+        MEK_TRY(hipMalloc(&P0->stab, want));
+        P0->stab_bytes = want;
     }
-    MEK_TRY(hipMemcpyAsync(P0->stab, K.data(), tbytes, hipMemcpyHostToDevice, s));
     SparseParams<T> head = K[0];
     head.m = max_m;   // sizes the selection chunk of every instance
     head.nb = (int)nb;
     head.multi = (const SparseParams<T>*)P0->stab;
+    if (async) {
+        MEK_TRY(store_bytes(K.data(), tbytes, P0->stab, s));
+        MEK_TRY(launch_sparse(head, lds, s));
+        for (int64_t b = 0; b < nb; ++b) {
+            const mek_plan_s* P = Ps[b];
+            const long long pq = P->p * P->q;
+            if (f64) MEK_TRY(copy_f64(P->ws.Xacc + (size_t)occ[b] * pq, pq, X[b], s));
+            else MEK_TRY(convert_f32_f64(P->ws.Xt32 + (size_t)occ[b] * pq, pq, X[b], s));
+        }
+        return MEK_OK;
+    }
+    MEK_TRY(hipMemcpyAsync(P0->stab, K.data(), tbytes, hipMemcpyHostToDevice, s));
     hipEvent_t ev[2];
     MEK_TRY(hipEventCreate(&ev[0]));
     if (hipEventCreate(&ev[1]) != hipSuccess) {
@@ -1786,8 +1818,14 @@ int solve_multi_async_impl(int64_t nb, const mek_plan* plans, const double* cons
     int st = multi_setup(nb, plans, C, X0, Xref, o, X, Ps, Ls);
     if (st) return st;
     if ((st = check_dev(dev_reports, sizeof(DevReport) * (size_t)nb))) return st;
-    if (Ps[0]->update == MEK_UPDATE_SPARSE) return MEK_EUNSUPPORTED;
     const int prec = Ps[0]->precision;
+    if (Ps[0]->update == MEK_UPDATE_SPARSE) {
+        std::vector<DevReport> unused(nb);
+        DevReport* dr = (DevReport*)dev_reports;
+        return prec == MEK_FP64
+                   ? run_sparse_multi<double>(nb, Ps.data(), o, C, X0, Xref, X, s, unused, nullptr, dr)
+                   : run_sparse_multi<float>(nb, Ps.data(), o, C, X0, Xref, X, s, unused, nullptr, dr);
+    }
     const bool cap = capturing(s);
     for (int64_t b = 0; b < nb; ++b) {
         if (Ps[b]->ws.base) continue;

@@ -197,7 +197,7 @@ def test_sparse_refusals():
         mek.mek_solve(plan, cuda(inst.C), variant="twosided", max_iters=5)
     assert e.value.code == mek.MEK_EUNSUPPORTED
     with pytest.raises(mek.MekError) as e:
-        mek.mek_solve_multi_async([plan], [cuda(inst.C)], max_iters=5)
+        mek.mek_solve_multi_async([plan], [cuda(inst.C)], variant="twosided", max_iters=5)
     assert e.value.code == mek.MEK_EUNSUPPORTED
     dense_plan = mek.mek_plan_create(cuda(inst.A), cuda(inst.B))
     with pytest.raises(mek.MekError) as e:
@@ -417,3 +417,41 @@ def test_sparse_async_graph_capture_and_replay():
         torch.cuda.synchronize()
         assert mek.read_device_report(repg) == eager
         assert torch.equal(Xg, X_e)
+
+
+
+def test_sparse_ragged_async_equals_sync_and_replays():
+    bases = [workloads.blurred_image(48, 1, 0.7, seed=s)[0] for s in (1, 2)]
+    plans = [_sparse_plan(b, 0.0) for b in bases]
+    rng = np.random.default_rng(14)
+    order = [0, 1, 0, 1, 0]   # both plans shared
+    Xs = [rng.uniform(0, 1, (48, 48)) for _ in order]
+    Cs = [cuda(bases[i].A @ x @ bases[i].B) for i, x in zip(order, Xs)]
+    Xr = [cuda(x) for x in Xs]
+    kw = dict(variant="grbk", stop="rel_err", tol=1e-5, max_iters=400000, seed=21, instance=4)
+    st, sync = mek.mek_solve_multi([plans[i] for i in order], Cs, X_ref=Xr, **kw)
+    assert st == mek.MEK_OK
+    X, rep = mek.mek_solve_multi_async([plans[i] for i in order], Cs, X_ref=Xr, **kw)
+    torch.cuda.synchronize()
+    for b, r in enumerate(sync):
+        d = mek.read_device_report(rep[b])
+        assert d["status"] == r.status and d["iters"] == r.iters and d["rel_err"] == r.rel_err
+        assert torch.equal(X[b], r.X)
+    Xg = [torch.empty_like(x) for x in X]
+    repg = torch.zeros_like(rep)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        mek.mek_solve_multi_async([plans[i] for i in order], Cs, X_ref=Xr, X_out=Xg, reports=repg,
+                                  **kw)
+    for rep_i in range(3):
+        for x in Xg:
+            x.fill_(float(rep_i))
+        repg.zero_()
+        _, junk = mek.mek_solve_multi([plans[i] for i in order], Cs, variant="rbk", max_iters=30,
+                                      seed=rep_i)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for b, r in enumerate(sync):
+            assert mek.read_device_report(repg[b])["iters"] == r.iters
+            assert torch.equal(Xg[b], r.X)
