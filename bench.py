@@ -327,6 +327,7 @@ def paper_image_forms(mek, workloads, torch, names=("face", "bird", "mandril")):
                        "iters": r.iters, "rel_err": r.rel_err,
                        "rel_resid": float(np.sqrt(r.resid2) / torch.linalg.norm(C)),
                        "psnr": float(10 * np.log10(1.0 / mse))}
+            print(f"[bench] image {name} {v}: {te:.1f} s", file=sys.stderr, flush=True)
         mek.mek_plan_destroy(plan)
         out[name] = rows
     return out
