@@ -252,8 +252,8 @@ typedef struct mek_device_report {
  * norms, transposes, the persistent launch, X) is enqueued on `stream` and
  * the call returns without waiting; the report is written to dev_report
  * (device memory) when the stream reaches it. Nothing in the call reads
- * device data on the host, so once the plan's workspace exists (after one
- * call of any solve on the plan) it can be captured into a graph. FP64 and
+ * device data on the host or allocates (mek_plan_create makes the plan's
+ * workspace for one instance), so it can be captured into a graph. FP64 and
  * FP32 plans, DENSE or SPARSE; MIXED plans, the two-sided variant and
  * replay_idx return MEK_EUNSUPPORTED. No finite check of the inputs is made (non-finite data
  * ends in MEK_EDIVERGED or a non-finite report). X, the histories and the

@@ -86,7 +86,7 @@ def test_async_graph_capture_and_replay(team):
     plan = mek.mek_plan_create(cuda(inst.A), cuda(inst.B), alpha=alpha, team_wgs=team)
     C, Xref = cuda(inst.C), cuda(inst.X_star)
     kw = dict(variant="grbk", stop="rel_err", tol=1e-6, X_ref=Xref, max_iters=100000, seed=11)
-    X_e, rep_e = mek.mek_solve_async(plan, C, **kw)    # eager (the workspace exists after it)
+    X_e, rep_e = mek.mek_solve_async(plan, C, **kw)    # eager: the reference for every replay
     torch.cuda.synchronize()
     eager = mek.read_device_report(rep_e)
     assert eager["status"] == mek.MEK_OK
