@@ -171,9 +171,12 @@ __device__ __forceinline__ void visit_norms(const double* __restrict__ a, int b,
 // [b, b + cnt) where select_rows would hold them in registers, and every
 // decision, sum and scan follows select_rows in the same order, so the two
 // forms pick the same rows with the same arithmetic. rho_i >= 0 exactly for
-// the rows with ||A_i|| > 0.
+// the rows with ||A_i|| > 0. cmax = max of rho over the thread's rows: a
+// chunk whose maximum is below the threshold (or below M for MWRBK) holds
+// no member and is not read.
 __device__ SelectOut select_rows_mem(int variant, int b, int cnt, const double2* __restrict__ r2,
-                                     const double* __restrict__ a, double S, double M, double F_A,
+                                     const double* __restrict__ a, double cmax, double S, double M,
+                                     double F_A,
                                      double theta, double u, long long k,
                                      const int* __restrict__ active, int n_active,
                                      BlockScratch& sc) {
@@ -187,13 +190,14 @@ __device__ SelectOut select_rows_mem(int variant, int b, int cnt, const double2*
     }
     if (variant == kMWRBK) {
         int cand = INT_MAX;
-        visit_rows(r2, b, cnt, [&](int i, double, double rho) {
-            if (rho >= 0.0 && rho == M) {
-                cand = i;
-                return true;
-            }
-            return false;
-        });
+        if (cmax >= M)
+            visit_rows(r2, b, cnt, [&](int i, double, double rho) {
+                if (rho >= 0.0 && rho == M) {
+                    cand = i;
+                    return true;
+                }
+                return false;
+            });
         if (threadIdx.x == 0) sc.out_i[2] = INT_MAX;
         cand = wave_min_int(cand);
         __syncthreads();
@@ -217,15 +221,17 @@ __device__ SelectOut select_rows_mem(int variant, int b, int cnt, const double2*
     // a_i (Alg. 1).
     double ws = 0.0;
     int c = 0, lastm = -1;
-    if (greedy)
-        visit_rows(r2, b, cnt, [&](int i, double ri, double rho) {
-            if (rho >= 0.0 && rho >= t) {
-                ws += ri;
-                ++c;
-                lastm = i;
-            }
-            return false;
-        });
+    if (greedy) {
+        if (cmax >= t)
+            visit_rows(r2, b, cnt, [&](int i, double ri, double rho) {
+                if (rho >= 0.0 && rho >= t) {
+                    ws += ri;
+                    ++c;
+                    lastm = i;
+                }
+                return false;
+            });
+    }
     else
         visit_norms(a, b, cnt, [&](int i, double ai) {
             if (ai > 0.0) {
@@ -300,6 +306,10 @@ template <typename T, int SR>
 __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     __shared__ BlockScratch sc;
+    // Memory form: bit t set when a row of thread t's chunk of norms (of row
+    // errors of X) changed since the thread last summed the chunk.
+    __shared__ unsigned int dirty[kThreads / 32];
+    __shared__ unsigned int edirty[kThreads / 32];
     // Ragged batch: work-group b runs instance b with its own parameters
     // (own plan, sizes, state and slot).
     const bool ragged = P.multi != nullptr;
@@ -400,6 +410,10 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
         }
         if (lane == 0) e_l[x] = acc;
     }
+    if (tid < kThreads / 32) {
+        dirty[tid] = ~0u;
+        edirty[tid] = ~0u;
+    }
     __syncthreads();
 
     const int cs = (m + kThreads - 1) / kThreads;
@@ -409,6 +423,9 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
     const int eb = min(p, tid * ecs);
     const int ecnt = min(p, eb + ecs) - eb;
     double S0 = -1.0, S = 0.0, err = NAN;
+    // Memory form: this thread's chunk sums of r and of the row errors, and
+    // the chunk's maximum of rho.
+    double chunk_S = 0.0, chunk_M = -1.0, chunk_E = 0.0;
     long long k = 0;
     int status = kMaxIter, last_set = 0;
     const bool timing = P.phase != nullptr && blockIdx.x == 0 && tid == 0;
@@ -434,15 +451,37 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
             }
         } else {
             // The same sums and maximum; the register form's padding adds
-            // +0 and -1, which change neither.
-            visit_rows(r2g, sb, scnt, [&](int, double rj, double rho) {
-                Sp += rj;
-                Mp = fmax(Mp, rho);
-                return false;
-            });
+            // +0 and -1, which change neither. Only a chunk with a changed
+            // row is read again; the others keep their last sums.
+            const unsigned int bit = 1u << (tid & 31);
+            if (dirty[tid >> 5] & bit) {
+                visit_rows(r2g, sb, scnt, [&](int, double rj, double rho) {
+                    Sp += rj;
+                    Mp = fmax(Mp, rho);
+                    return false;
+                });
+                chunk_S = Sp;
+                chunk_M = Mp;
+                atomicAnd(&dirty[tid >> 5], ~bit);
+            } else {
+                Sp = chunk_S;
+                Mp = chunk_M;
+            }
         }
+        if constexpr (kNormsLds) {
 #pragma unroll 8
-        for (int j = 0; j < ecnt; ++j) Ep += e_l[eb + j];
+            for (int j = 0; j < ecnt; ++j) Ep += e_l[eb + j];
+        } else {
+            const unsigned int bit = 1u << (tid & 31);
+            if (edirty[tid >> 5] & bit) {
+#pragma unroll 8
+                for (int j = 0; j < ecnt; ++j) Ep += e_l[eb + j];
+                chunk_E = Ep;
+                atomicAnd(&edirty[tid >> 5], ~bit);
+            } else {
+                Ep = chunk_E;
+            }
+        }
         block_sum_max_sum(Sp, Mp, Ep, sc);
         S = Sp;
         const double M = Mp;
@@ -472,8 +511,8 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
                 so = select_rows<kSR>(P.variant, sb, scnt, rr, aa, rho, S, M, P.F_A, P.theta, u_k, k,
                                       P.active, P.n_active, sc, nullptr, nullptr);
             else
-                so = select_rows_mem(P.variant, sb, scnt, r2g, asrc, S, M, P.F_A, P.theta, u_k, k,
-                                     P.active, P.n_active, sc);
+                so = select_rows_mem(P.variant, sb, scnt, r2g, asrc, chunk_M, S, M, P.F_A, P.theta,
+                                     u_k, k, P.active, P.n_active, sc);
             ik = so.idx;
             last_set = so.setsize;
         }
@@ -543,7 +582,13 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
                 }
             }
             if (has_ref) acc = wave_sum(acc);
-            if (lane == 0) e_l[x] = acc;
+            if (lane == 0) {
+                e_l[x] = acc;
+                if constexpr (!kNormsLds) {
+                    const int owner = x / ecs;
+                    atomicOr(&edirty[owner >> 5], 1u << (owner & 31));
+                }
+            }
         };
         auto r_tail = [&](int i, T cg, int l0, double acc) {
             T* rp = R + (size_t)i * n;
@@ -554,8 +599,13 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
             }
             acc = wave_sum(acc);
             if (lane == 0) {
-                if constexpr (kNormsLds) r_l[i] = acc;
-                else r2g[i] = make_double2(acc, asrc[i] > 0.0 ? acc / asrc[i] : -1.0);
+                if constexpr (kNormsLds) {
+                    r_l[i] = acc;
+                } else {
+                    r2g[i] = make_double2(acc, asrc[i] > 0.0 ? acc / asrc[i] : -1.0);
+                    const int owner = i / cs;
+                    atomicOr(&dirty[owner >> 5], 1u << (owner & 31));
+                }
             }
         };
 #pragma unroll
