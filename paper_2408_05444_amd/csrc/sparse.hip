@@ -100,9 +100,13 @@ template hipError_t ell_fill<float>(const double*, int, int, long long, long lon
 // ---------------------------------------------------------------------------
 // The solver: one work-group per instance.
 // ---------------------------------------------------------------------------
-constexpr int kSpRows = 3;   // rows of R per wave held in registers for an update
-constexpr int kSpX = 2;      // rows of X per wave held in registers for an update
-constexpr int kSpE = 8;      // entries per lane of such a row (rows up to 512 long)
+// Rows of R and of X per wave held in registers for an update, and entries
+// per lane of such a row: rows up to 512 long, or (the narrow shape, for
+// n, q <= 64) one entry per lane and more rows, so that the whole update's
+// rows are loaded at once. Entries and rows past these go through device
+// memory in the same per-lane order, so both shapes give the same sums.
+constexpr int kSpRows = 3, kSpX = 2, kSpE = 8;
+constexpr int kSpRowsNarrow = 11, kSpXNarrow = 4, kSpENarrow = 1;
 
 // Sum over the ELL slots of line j (slot t at idx[t * stride + j]) of
 // val * x[idx], in slot order. Padded slots (index -1, value 0) add zero;
@@ -302,8 +306,11 @@ enum { kSpPhReduce, kSpPhSelect, kSpPhLoad, kSpPhV, kSpPhWX, kSpPhR, kSpPhCount 
         }                                                               \
     } while (0)
 
-template <typename T, int SR>
+template <typename T, int SR, bool NARROW>
 __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) {
+    constexpr int kRows = NARROW ? kSpRowsNarrow : kSpRows;
+    constexpr int kXr = NARROW ? kSpXNarrow : kSpX;
+    constexpr int kE = NARROW ? kSpENarrow : kSpE;
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     __shared__ BlockScratch sc;
     // Memory form: bit t set when a row of thread t's chunk of norms (of row
@@ -527,34 +534,34 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
         // while v and w are formed: R_{i_k} into LDS, and into registers
         // this wave's rows of R (column i_k of A A^T, slots wv + u kWaves)
         // and of X and X_ref (row i_k of A, likewise).
-        int ri[kSpRows], xi[kSpX];
-        double gv[kSpRows], av[kSpX];
-        T rreg[kSpRows][kSpE], xreg[kSpX][kSpE];
-        double xrf[kSpX][kSpE];
+        int ri[kRows], xi[kXr];
+        double gv[kRows], av[kXr];
+        T rreg[kRows][kE], xreg[kXr][kE];
+        double xrf[kXr][kE];
 #pragma unroll
-        for (int u = 0; u < kSpRows; ++u) {
+        for (int u = 0; u < kRows; ++u) {
             const int t = wv + u * kWaves;
             ri[u] = t < P.kg ? g_idx[(size_t)ik * P.kg + t] : -1;
             gv[u] = ri[u] >= 0 ? (double)g_val[(size_t)ik * P.kg + t] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kSpX; ++u) {
+        for (int u = 0; u < kXr; ++u) {
             const int t = wv + u * kWaves;
             xi[u] = t < P.ka ? a_idx[(size_t)ik * P.ka + t] : -1;
             av[u] = xi[u] >= 0 ? (double)a_val[(size_t)ik * P.ka + t] : 0.0;
         }
         for (int j = tid; j < n; j += kThreads) rowv[j] = R[(size_t)ik * n + j];
 #pragma unroll
-        for (int u = 0; u < kSpRows; ++u)
+        for (int u = 0; u < kRows; ++u)
 #pragma unroll
-            for (int e = 0; e < kSpE; ++e) {
+            for (int e = 0; e < kE; ++e) {
                 const int l = lane + e * kWave;
                 rreg[u][e] = (ri[u] >= 0 && l < n) ? R[(size_t)ri[u] * n + l] : (T)0;
             }
 #pragma unroll
-        for (int u = 0; u < kSpX; ++u)
+        for (int u = 0; u < kXr; ++u)
 #pragma unroll
-            for (int e = 0; e < kSpE; ++e) {
+            for (int e = 0; e < kE; ++e) {
                 const int j = lane + e * kWave;
                 const bool in = xi[u] >= 0 && j < q;
                 xreg[u][e] = in ? X[(size_t)xi[u] * q + j] : (T)0;
@@ -570,7 +577,7 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
         // where A_{i_k} is nonzero, with their errors.
         for (int l = tid; l < n; l += kThreads) ww[l] = (T)ell_dot(bt_idx, bt_val, P.kbt, n, l, vv);
         // A row of X or R updated from device memory (rows past the ones
-        // held in registers, entries past kSpE per lane).
+        // held in registers, entries past kE per lane).
         auto x_tail = [&](int x, T ca, int j0, double acc) {
             T* xr = X + (size_t)x * q;
             for (int j = j0; j < q; j += kWave) {
@@ -609,13 +616,13 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
             }
         };
 #pragma unroll
-        for (int u = 0; u < kSpX; ++u) {
+        for (int u = 0; u < kXr; ++u) {
             if (xi[u] < 0) continue;
             const T ca = (T)(c * av[u]);
             T* xr = X + (size_t)xi[u] * q;
             double acc = 0.0;
 #pragma unroll
-            for (int e = 0; e < kSpE; ++e) {
+            for (int e = 0; e < kE; ++e) {
                 const int j = lane + e * kWave;
                 if (j < q) {
                     const T nv = xreg[u][e] + ca * vv[j];
@@ -626,9 +633,9 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
                     }
                 }
             }
-            x_tail(xi[u], ca, lane + kSpE * kWave, acc);
+            x_tail(xi[u], ca, lane + kE * kWave, acc);
         }
-        for (int t = wv + kSpX * kWaves; t < P.ka; t += kWaves) {
+        for (int t = wv + kXr * kWaves; t < P.ka; t += kWaves) {
             const int x = a_idx[(size_t)ik * P.ka + t];
             if (x < 0) break;
             x_tail(x, (T)(c * (double)a_val[(size_t)ik * P.ka + t]), lane, 0.0);
@@ -638,13 +645,13 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
         // ---- The rows of R where column i_k of A A^T is nonzero, with their
         // new norms.
 #pragma unroll
-        for (int u = 0; u < kSpRows; ++u) {
+        for (int u = 0; u < kRows; ++u) {
             if (ri[u] < 0) continue;
             const T cg = (T)(c * gv[u]);
             T* rp = R + (size_t)ri[u] * n;
             double acc = 0.0;
 #pragma unroll
-            for (int e = 0; e < kSpE; ++e) {
+            for (int e = 0; e < kE; ++e) {
                 const int l = lane + e * kWave;
                 if (l < n) {
                     const T nv = rreg[u][e] - cg * ww[l];
@@ -652,9 +659,9 @@ __global__ void __launch_bounds__(kThreads, 1) sparse_kernel(SparseParams<T> P) 
                     acc += (double)nv * (double)nv;
                 }
             }
-            r_tail(ri[u], cg, lane + kSpE * kWave, acc);
+            r_tail(ri[u], cg, lane + kE * kWave, acc);
         }
-        for (int t = wv + kSpRows * kWaves; t < P.kg; t += kWaves) {
+        for (int t = wv + kRows * kWaves; t < P.kg; t += kWaves) {
             const int i = g_idx[(size_t)ik * P.kg + t];
             if (i < 0) break;
             r_tail(i, (T)(c * (double)g_val[(size_t)ik * P.kg + t]), lane, 0.0);
@@ -690,7 +697,11 @@ size_t sparse_lds_bytes(int m, int p, int q, int n, size_t elem, bool norms_in_l
 
 template <typename T, int SR>
 static hipError_t launch_sparse_sr(const SparseParams<T>& P, size_t lds_bytes, hipStream_t s) {
-    auto kern = sparse_kernel<T, SR>;
+    // The narrow shape for instances of at most 64 columns of R and X (the
+    // first instance's sizes decide for a ragged table; either shape is
+    // correct for any size).
+    auto kern = (P.n <= kWave && P.q <= kWave) ? sparse_kernel<T, SR, true>
+                                               : sparse_kernel<T, SR, false>;
     if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds_bytes) != hipSuccess)
         (void)hipGetLastError();
