@@ -134,7 +134,7 @@ __device__ __forceinline__ double ell_dot(const int* idx, const T* val, int slot
     return acc;
 }
 
-constexpr int kMemBatch = 16;   // rows loaded per batch in the device-memory selection
+constexpr int kMemBatch = 24;   // rows loaded per batch in the device-memory selection
 
 // Rows [b, b + cnt) of the {r_i, rho_i} pairs (rho_i = r_i / ||A_i||^2, -1
 // for rows with A_i = 0) in batches of kMemBatch 16-byte loads, visited in
