@@ -163,6 +163,8 @@ def blur_batch_forms(mek, workloads, torch):
             out[prec]["rel_diff_vs_fp64_same_indices"] = float(
                 torch.linalg.norm(Xm - X64r) / torch.linalg.norm(X64r))
             out[prec]["passes"] = res[0].passes
+            mek.mek_plan_destroy(plan64)
+            mek.mek_plan_destroy(plan)
     # The sparse-aware update on the same channels, variant, budget and draws:
     # one work-group per channel.
     plan = mek.mek_plan_create(A, B, update="sparse")

@@ -10,6 +10,7 @@ HIP kernels; if the library is missing or fails to load, every call raises.
 from __future__ import annotations
 
 import ctypes
+import sys
 import math
 import os
 from dataclasses import dataclass
@@ -178,12 +179,25 @@ class Plan:
     precision: int
 
     def __del__(self):
+        # A plan dropped during interpreter shutdown is left to the process
+        # exit: by then the HIP runtime (and any profiler attached to it) may
+        # already be tearing down, and a device synchronise or free issued
+        # from a finaliser at that point can crash the exit path.
+        if sys.is_finalizing():
+            return
         try:
             if self.handle:
                 lib().mek_plan_destroy(self.handle)
                 self.handle = None
         except Exception:
             pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        mek_plan_destroy(self)
+        return False
 
 
 def mek_plan_create(A: torch.Tensor, B: torch.Tensor, precision="fp64", alpha: float = 0.0,

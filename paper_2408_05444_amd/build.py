@@ -10,6 +10,7 @@ import shutil
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -21,27 +22,32 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # Packed FP32 instructions are kept out of the generated code.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    "-Wall", "-Werror", "-Wno-unused-function", "-Wno-unused-variable",
 ]
+
+
+def _compile(src: str, tmpdir: str, verbose: bool) -> str:
+    obj = os.path.join(tmpdir, src + ".o")
+    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
+                    if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{out}")
+    if out.strip() and verbose:
+        print(out)
+    return obj
 
 
 def build(verbose: bool = False) -> str:
     tmpdir = tempfile.mkdtemp(prefix="mek_build_")
     try:
-        objs = []
-        for src in SOURCES:
-            obj = os.path.join(tmpdir, src + ".o")
-            cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
-            if verbose:
-                print(" ".join(cmd), flush=True)
-            r = subprocess.run(cmd, capture_output=True, text=True)
-            out = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
-                            if "packed-fp32-ops" not in l)
-            if r.returncode != 0:
-                raise RuntimeError(f"hipcc failed for {src}:\n{out}")
-            if out.strip() and verbose:
-                print(out)
-            objs.append(obj)
+        # One hipcc per source, in parallel; link in the listed order.
+        jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            objs = list(ex.map(lambda src: _compile(src, tmpdir, verbose), SOURCES))
         tmp_lib = os.path.join(tmpdir, "libmek.so")
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp_lib] + objs
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -340,8 +340,8 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             last_set = 0;
         } else {
             const SelectOut so = select_rows<SR>(P.variant, sb, scnt, rr, aa, rho, S, M, P.F_A,
-                                                 P.theta, u_k, k, P.active, P.n_active, sc,
-                                                 nullptr, nullptr);
+                                                 P.theta, u_k, P.k_offset + k, P.active,
+                                                 P.n_active, sc, nullptr, nullptr);
             ik = so.idx;
             last_set = so.setsize;
         }

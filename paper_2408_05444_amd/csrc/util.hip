@@ -187,10 +187,15 @@ __global__ void copy_kernel(const double* __restrict__ x, long long len, double*
          e += (long long)gridDim.x * blockDim.x)
         y[e] = x[e];
 }
-__global__ void zero_kernel(unsigned int* __restrict__ x, long long words) {
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < words;
-         e += (long long)gridDim.x * blockDim.x)
-        x[e] = 0u;
+// Zeroes exactly `bytes` bytes: 4-byte stores over the aligned body when the
+// start is 4-byte aligned, single-byte stores for the rest (and for the whole
+// buffer when the start is not aligned), so nothing past the end is written.
+__global__ void zero_kernel(unsigned char* __restrict__ x, long long bytes, long long words) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned int* xw = reinterpret_cast<unsigned int*>(x);
+    for (long long e = t0; e < words; e += stride) xw[e] = 0u;
+    for (long long e = words * 4 + t0; e < bytes; e += stride) x[e] = 0;
 }
 __global__ void lincomb_kernel(double a, const double* x, double b, const double* y,
                                long long len, double* out) {
@@ -218,11 +223,14 @@ hipError_t copy_f64(const double* x, long long len, double* y, hipStream_t s) {
     hipLaunchKernelGGL(copy_kernel, ew_grid(len), dim3(256), 0, s, x, len, y);
     return hipGetLastError();
 }
-// Zero a buffer whose size is a multiple of 4 bytes with a kernel (not a
-// memset node, so the call is safe inside captured graphs).
+// Zero a buffer of any size and alignment with a kernel (not a memset node,
+// so the call is safe inside captured graphs).
 hipError_t fill_zero_bytes(void* x, long long bytes, hipStream_t s) {
-    const long long words = (bytes + 3) / 4;
-    hipLaunchKernelGGL(zero_kernel, ew_grid(words), dim3(256), 0, s, (unsigned int*)x, words);
+    if (bytes <= 0) return hipSuccess;
+    const long long words = ((uintptr_t)x & 3) ? 0 : bytes / 4;
+    const long long work = words + (bytes - words * 4);
+    hipLaunchKernelGGL(zero_kernel, ew_grid(work), dim3(256), 0, s, (unsigned char*)x, bytes,
+                       words);
     return hipGetLastError();
 }
 // Bytes carried in a launch's arguments and stored by the kernel: a host
