@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define MEK_ABI_VERSION 3
+#define MEK_ABI_VERSION 4
 
 /* Selection rules (Algs. 1-5), and the two-sided block projection. */
 #define MEK_BK 0
@@ -164,6 +164,17 @@ typedef struct {
     double tau;
     int32_t* rows_hist;
     int32_t* cols_hist;
+    /* MEK_FP32 and MEK_MIXED plans, DENSE update, mek_solve and
+     * mek_solve_batched: every refresh_period updates the FP32 residual is
+     * recomputed from the current iterate by the split-BF16 residual engine
+     * (see mek_residual_split), so that the incrementally updated residual
+     * does not drift: FP32 recomputes R = C - A X B with 3 bf16 terms per
+     * operand (FP32 accuracy); MIXED recomputes the inner residual
+     * R_true - A D B of its correction D with 2 terms (about 2^-17, far
+     * below the inner stop). 0: automatic (every max(2048, 4 m) updates);
+     * < 0: never. The stream-ordered and ragged calls run without refreshes
+     * and return MEK_EUNSUPPORTED for refresh_period > 0. */
+    int64_t refresh_period;
 } mek_solve_opts;
 
 typedef struct {
@@ -174,7 +185,8 @@ typedef struct {
     double alpha;        /* step used */
     int team_wgs;        /* work-groups per solve */
     int r_in_lds;        /* 1 if R stayed in LDS */
-    int passes;          /* MEK_MIXED refinement passes (1 otherwise) */
+    int passes;          /* launches of the persistent solver: MEK_MIXED refinement
+                            passes, MEK_FP32 residual refreshes + 1, else 1 */
     double kernel_ms;    /* time of the persistent solver launch(es), measured
                             with HIP events on `stream` around each launch */
 } mek_report;
@@ -356,6 +368,26 @@ int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, co
 int mek_residual_batched(int64_t nb, int64_t m, int64_t p, int64_t q, int64_t n, const double* A,
                          const double* X, const double* B, const double* C, double* R,
                          void* stream);
+
+/* The FP32 residual engine of the FP32 and mixed iterations (the residual
+ * R = C - A X B with which Alg. 3 starts, recomputed from the current
+ * iterate so that the incrementally updated FP32 residual does not drift):
+ * for b < nb, R_b = C_b - (A X_b) B with A (m x p), X_b = X + b p q
+ * (p x q) and B (q x n) device float, C_b = C + b m n device double and
+ * R_b = R + b m n device float (row-major, instances contiguous). Both
+ * products run on the BF16 matrix cores with FP32 accumulation, every FP32
+ * operand value split into `pieces` bf16 terms (1, 2 or 3) and the cross
+ * terms of combined order below `pieces` summed: 1 term gives about bf16
+ * accuracy (2^-9 relative per product), 2 about 2^-17, 3 about FP32
+ * accuracy (2^-24). T = A X_b is rounded to FP32 between the products;
+ * C_b - T B is formed in FP64 and rounded once. R must not overlap any
+ * input. Blocking; the temporaries T (nb x m x q floats) use a per-device
+ * buffer kept between calls. Errors: MEK_EINVAL for pieces outside 1..3,
+ * sizes <= 0, null or overlapping pointers; MEK_EHIP for host or short
+ * buffers. */
+int mek_residual_split(int pieces, int64_t nb, int64_t m, int64_t p, int64_t q, int64_t n,
+                       const float* A, const float* X, const float* B, const double* C, float* R,
+                       void* stream);
 
 /* Gram products by the FP64 MFMA GEMM: G = M M^T (transpose_first = 0,
  * G rows x rows) or G = M^T M (transpose_first = 1, G cols x cols) for M

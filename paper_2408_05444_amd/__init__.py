@@ -60,7 +60,7 @@ class mek_solve_opts(ctypes.Structure):
                 ("hist_cap", ctypes.c_int64), ("inner_iters", ctypes.c_int64),
                 ("block_rows", ctypes.c_int), ("block_cols", ctypes.c_int),
                 ("tau", ctypes.c_double), ("rows_hist", ctypes.c_void_p),
-                ("cols_hist", ctypes.c_void_p)]
+                ("cols_hist", ctypes.c_void_p), ("refresh_period", ctypes.c_int64)]
 
 
 class mek_report(ctypes.Structure):
@@ -131,6 +131,8 @@ def lib() -> ctypes.CDLL:
         L.mek_residual.restype = ci
         L.mek_residual_batched.argtypes = [i64, i64, i64, i64, i64, vp, vp, vp, vp, vp, vp]
         L.mek_residual_batched.restype = ci
+        L.mek_residual_split.argtypes = [ci, i64, i64, i64, i64, i64, vp, vp, vp, vp, vp, vp]
+        L.mek_residual_split.restype = ci
         L.mek_gram.argtypes = [i64, i64, vp, ci, vp, vp]
         L.mek_gram.restype = ci
         _lib_handle = L
@@ -263,7 +265,8 @@ class SolveResult:
 
 
 def _solve_opts(nb, dev, variant, theta, alpha, stop, tol, X_ref_ptr, max_iters, seed, instance,
-                replay_idx, diverge, hist_cap, inner_iters, block_rows=0, block_cols=0, tau=0.0):
+                replay_idx, diverge, hist_cap, inner_iters, block_rows=0, block_cols=0, tau=0.0,
+                refresh_period=0):
     hists = {}
     twosided = VARIANTS.get(variant, variant) == MEK_TWOSIDED
     if hist_cap > 0:
@@ -298,6 +301,7 @@ def _solve_opts(nb, dev, variant, theta, alpha, stop, tol, X_ref_ptr, max_iters,
         setattr(o, k, _dev(t, dtype=t.dtype, name=k))
     o.hist_cap = int(hist_cap)
     o.inner_iters = int(inner_iters)
+    o.refresh_period = int(refresh_period)
     return o, hists
 
 
@@ -326,7 +330,7 @@ def mek_solve(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = None, va
               instance: int = 0, replay_idx: Optional[torch.Tensor] = None, diverge: float = 0.0,
               hist_cap: int = 0, inner_iters: int = 0, X_out: Optional[torch.Tensor] = None,
               block_rows: int = 32, block_cols: int = 32, tau: float = 0.0,
-              raise_on_error: bool = True) -> SolveResult:
+              refresh_period: int = 0, raise_on_error: bool = True) -> SolveResult:
     """variant "twosided" takes block_rows / block_cols (1..32) and tau; its
     histories are rows_hist / cols_hist (lists of I and J per step)."""
     m, p, q, n = plan.m, plan.p, plan.q, plan.n
@@ -334,7 +338,8 @@ def mek_solve(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = None, va
     X = X_out if X_out is not None else torch.empty(p, q, dtype=torch.float64, device=dev)
     o, hists = _solve_opts(1, dev, variant, theta, alpha, stop, tol,
                            _dev(X_ref, shape=(p, q), name="X_ref"), max_iters, seed, instance,
-                           replay_idx, diverge, hist_cap, inner_iters, block_rows, block_cols, tau)
+                           replay_idx, diverge, hist_cap, inner_iters, block_rows, block_cols, tau,
+                           refresh_period)
     rep = mek_report()
     code = lib().mek_solve(plan.handle, _dev(C, shape=(m, n), name="C"),
                            _dev(X0, shape=(p, q), name="X0"), ctypes.byref(o),
@@ -350,7 +355,8 @@ def mek_solve_batched(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = 
                       max_iters: int = 100000, seed: int = 0, instance: int = 0,
                       replay_idx: Optional[torch.Tensor] = None, diverge: float = 0.0,
                       hist_cap: int = 0, inner_iters: int = 0, block_rows: int = 32,
-                      block_cols: int = 32, tau: float = 0.0, raise_on_error: bool = True):
+                      block_cols: int = 32, tau: float = 0.0, refresh_period: int = 0,
+                      raise_on_error: bool = True):
     """Uniform batch: C (nb, m, n) [, X0, X_ref (nb, p, q)] sharing the plan's A
     and B. Returns (status, [SolveResult per instance]); instance b draws
     under Philox key (seed, instance + b)."""
@@ -361,7 +367,7 @@ def mek_solve_batched(plan: Plan, C: torch.Tensor, X0: Optional[torch.Tensor] = 
     o, hists = _solve_opts(nb, dev, variant, theta, alpha, stop, tol,
                            _dev(X_ref, shape=(nb, p, q), name="X_ref"), max_iters, seed,
                            instance, replay_idx, diverge, hist_cap, inner_iters, block_rows,
-                           block_cols, tau)
+                           block_cols, tau, refresh_period)
     reps = (mek_report * nb)()
     code = lib().mek_solve_batched(plan.handle, nb, _dev(C, shape=(nb, m, n), name="C"),
                                    _dev(X0, shape=(nb, p, q), name="X0"), ctypes.byref(o),
@@ -547,6 +553,23 @@ def mek_residual_batched(A, X, B, C) -> torch.Tensor:
                                       _dev(X, shape=(nb, p, q), name="X"), _dev(B, name="B"),
                                       _dev(C, shape=(nb, m, n), name="C"), _dev(R), _stream()),
            "mek_residual_batched")
+    return R
+
+
+def mek_residual_split(A, X, B, C, pieces: int = 3) -> torch.Tensor:
+    """R_b = C_b - (A X_b) B on the BF16 matrix cores with FP32 operands
+    split into `pieces` bf16 terms: A (m, p), B (q, n) float32; X (nb, p, q)
+    float32; C (nb, m, n) float64; returns R (nb, m, n) float32."""
+    m, p = A.shape
+    q, n = B.shape
+    nb = X.shape[0]
+    R = torch.empty(nb, m, n, dtype=torch.float32, device=A.device)
+    _check(lib().mek_residual_split(int(pieces), nb, m, p, q, n,
+                                    _dev(A, torch.float32, name="A"),
+                                    _dev(X, torch.float32, shape=(nb, p, q), name="X"),
+                                    _dev(B, torch.float32, name="B"),
+                                    _dev(C, shape=(nb, m, n), name="C"),
+                                    _dev(R, torch.float32), _stream()), "mek_residual_split")
     return R
 
 

@@ -1141,6 +1141,30 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
         return sl;
     };
 
+    // FP32 residual refresh from the current FP32 iterate on the split-BF16
+    // residual engine: R32_b = base_b - A32 (Xt32_b)^T B32 for the listed
+    // instances (one batched launch per product when the list is the whole
+    // batch). base is C (FP32 plans) or the FP64 true residual (MIXED).
+    auto refresh_r32 = [&](const double* base, const std::vector<int64_t>& ids,
+                           int pieces) -> int {
+        float* T = reinterpret_cast<float*>(w.T64);
+        const bool all = nb > 1 && (int64_t)ids.size() == nb;
+        for (size_t j = 0; j < (all ? 1 : ids.size()); ++j) {
+            const int64_t b = all ? 0 : ids[j];
+            const int cnt = all ? (int)nb : 1;
+            MEK_TRY(gemm_bf16s_batched(pieces, cnt, (int)m, (int)q, (int)p, 1.0, P->A32, p, 1, 0,
+                                       w.Xt32 + b * pq, 1, p, pq, 0.0, nullptr, 0, 0, T, q,
+                                       m * q, s));
+            MEK_TRY(gemm_bf16s_batched(pieces, cnt, (int)m, (int)n, (int)q, -1.0, T, q, 1, m * q,
+                                       P->B32, n, 1, 0, 1.0, base + b * mn, n, mn,
+                                       w.R32 + b * mn, n, mn, s));
+        }
+        return MEK_OK;
+    };
+    const long long refresh = o->refresh_period > 0 ? o->refresh_period
+                              : o->refresh_period == 0 ? std::max<long long>(2048, 4 * m)
+                                                       : 0;
+
     std::vector<DevReport> rep(nb);
     std::vector<int> passes(nb, 1);
     memset(rep.data(), 0, sizeof(DevReport) * nb);
@@ -1182,9 +1206,39 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
                 if (X0) MEK_TRY(transpose_to<float>(X0 + b * pq, (int)p, (int)q, w.Xt32 + b * pq, s));
                 else MEK_TRY(fill_zero_bytes(w.Xt32 + b * pq, (long long)pq * 4, s));
             }
-            st = run_kernel<float>(P, o, L, alpha, slots[0], sp, (int)nb, xr, w.R32, w.Xt32, s,
-                                   rep.data(), &kms);
-            if (st) return st;
+            // Passes of `refresh` updates, the residual recomputed (3 bf16
+            // terms, FP32 accuracy) between them; the Philox counter, replay
+            // position and histories continue across passes.
+            std::vector<long long> done(nb, 0);
+            std::vector<int64_t> ids;
+            for (int64_t b = 0; b < nb; ++b) ids.push_back(b);
+            std::vector<DevReport> ir(nb);
+            for (;;) {
+                std::vector<InstSlot> ps;
+                for (int64_t b : ids) {
+                    InstSlot sl = slots[b];
+                    const long long left = o->max_iters - done[b];
+                    sl.max_iters = refresh > 0 ? std::min<long long>(refresh, left) : left;
+                    sl.k_offset = done[b];
+                    sl.hist_offset = done[b];
+                    ps.push_back(sl);
+                }
+                st = run_kernel<float>(P, o, L, alpha, ps[0], nb > 1 ? ps.data() : nullptr,
+                                       (int)ps.size(), xr, w.R32, w.Xt32, s, ir.data(), &kms);
+                if (st) return st;
+                std::vector<int64_t> again;
+                for (const InstSlot& sl : ps) {
+                    const int64_t b = sl.id;
+                    done[b] += ir[b].iters;
+                    rep[b] = ir[b];
+                    rep[b].iters = done[b];
+                    if (ir[b].status == MEK_MAXITER && done[b] < o->max_iters) again.push_back(b);
+                }
+                if (again.empty()) break;
+                for (int64_t b : again) ++passes[b];
+                if ((st = refresh_r32(C, again, 3))) return st;
+                ids = again;
+            }
             for (int64_t b = 0; b < nb; ++b)
                 MEK_TRY(transpose_from<float>(w.Xt32 + b * pq, (int)p, (int)q, X + b * pq, s));
         }
@@ -1270,10 +1324,37 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
             }
             if (slots.empty()) break;
             const bool batched = nb > 1;
-            st = run_kernel<float>(P, &io, L, alpha, slots[0], batched ? slots.data() : nullptr,
-                                   (int)slots.size(), o->X_ref ? w.Xref_t : nullptr, w.R32, w.Xt32,
-                                   s, ir.data(), &kms);
-            if (st) return st;
+            // The inner pass in sub-passes of `refresh` updates; between them
+            // the inner residual R_true - A D B is recomputed from D (2 bf16
+            // terms: about 2^-17 relative, far below the inner stop).
+            std::vector<long long> idone(nb, 0), icap(nb, 0);
+            for (const InstSlot& sl : slots) icap[sl.id] = sl.max_iters;
+            std::vector<InstSlot> cur = slots;
+            for (;;) {
+                for (InstSlot& sl : cur) {
+                    const long long left = icap[sl.id] - idone[sl.id];
+                    sl.max_iters = refresh > 0 ? std::min<long long>(refresh, left) : left;
+                    sl.k_offset = done[sl.id] + idone[sl.id];
+                    sl.hist_offset = sl.k_offset;
+                }
+                st = run_kernel<float>(P, &io, L, alpha, cur[0], batched ? cur.data() : nullptr,
+                                       (int)cur.size(), o->X_ref ? w.Xref_t : nullptr, w.R32,
+                                       w.Xt32, s, ir.data(), &kms);
+                if (st) return st;
+                std::vector<InstSlot> next;
+                std::vector<int64_t> again;
+                for (const InstSlot& sl : cur) {
+                    idone[sl.id] += ir[sl.id].iters;
+                    if (ir[sl.id].status == MEK_MAXITER && idone[sl.id] < icap[sl.id]) {
+                        next.push_back(sl);
+                        again.push_back(sl.id);
+                    }
+                }
+                if (again.empty()) break;
+                if ((st = refresh_r32(w.R64, again, 2))) return st;
+                cur = next;
+            }
+            for (const InstSlot& sl : slots) ir[sl.id].iters = idone[sl.id];
             for (const InstSlot& sl : slots) {
                 const int64_t b = sl.id;
                 // X_acc += D, accumulated in FP64.
@@ -1732,6 +1813,7 @@ int solve_multi_impl(int64_t nb, const mek_plan* plans, const double* const* C,
                      const double* const* X0, const double* const* Xref,
                      const mek_solve_opts* o, double* const* X, mek_report* reports,
                      hipStream_t s) {
+    if (o && o->refresh_period > 0) return MEK_EUNSUPPORTED;
     std::vector<mek_plan_s*> Ps;
     std::vector<Layout> Ls;
     int st = multi_setup(nb, plans, C, X0, Xref, o, X, Ps, Ls);
@@ -1813,6 +1895,7 @@ int solve_multi_async_impl(int64_t nb, const mek_plan* plans, const double* cons
                            const mek_solve_opts* o, double* const* X, void* dev_reports,
                            hipStream_t s) {
     if (!dev_reports) return MEK_EINVAL;
+    if (o && o->refresh_period > 0) return MEK_EUNSUPPORTED;
     std::vector<mek_plan_s*> Ps;
     std::vector<Layout> Ls;
     int st = multi_setup(nb, plans, C, X0, Xref, o, X, Ps, Ls);
@@ -2002,7 +2085,8 @@ int enqueue_sparse(mek_plan_s* P, const mek_solve_opts* o, const double* C, cons
 int solve_async_impl(mek_plan P, const double* C, const double* X0, const mek_solve_opts* o,
                      double* X, void* dev_report, hipStream_t s) {
     if (!P || !C || !X || !dev_report || !o) return MEK_EINVAL;
-    if (P->precision == MEK_MIXED || o->variant == MEK_TWOSIDED || o->replay_len > 0)
+    if (P->precision == MEK_MIXED || o->variant == MEK_TWOSIDED || o->replay_len > 0 ||
+        o->refresh_period > 0)
         return MEK_EUNSUPPORTED;
     int st = validate_opts(P, o);
     if (st) return st;
@@ -2168,6 +2252,61 @@ int mek_residual_batched(int64_t nb, int64_t m, int64_t p, int64_t q, int64_t n,
 int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, const double* X,
                  const double* B, const double* C, double* R, void* stream) {
     return mek_residual_batched(1, m, p, q, n, A, X, B, C, R, stream);
+}
+
+int mek_residual_split(int pieces, int64_t nb, int64_t m, int64_t p, int64_t q, int64_t n,
+                       const float* A, const float* X, const float* B, const double* C, float* R,
+                       void* stream) {
+    if (pieces < 1 || pieces > 3) return MEK_EINVAL;
+    if (nb <= 0 || m <= 0 || p <= 0 || q <= 0 || n <= 0) return MEK_EINVAL;
+    if (m > INT32_MAX / 2 || p > INT32_MAX / 2 || q > INT32_MAX / 2 || n > INT32_MAX / 2 ||
+        nb > INT32_MAX / 2)
+        return MEK_EINVAL;
+    if (!A || !X || !B || !C || !R) return MEK_EINVAL;
+    const size_t rb = (size_t)(nb * m * n) * 4;
+    auto overlaps = [&](const void* x, size_t bytes) {
+        const char *r0 = (const char*)R, *x0 = (const char*)x;
+        return r0 < x0 + bytes && x0 < r0 + rb;
+    };
+    if (overlaps(A, (size_t)(m * p) * 4) || overlaps(X, (size_t)(nb * p * q) * 4) ||
+        overlaps(B, (size_t)(q * n) * 4) || overlaps(C, (size_t)(nb * m * n) * 8))
+        return MEK_EINVAL;
+    int st;
+    if ((st = check_dev(A, (size_t)(m * p) * 4)) || (st = check_dev(X, (size_t)(nb * p * q) * 4)) ||
+        (st = check_dev(B, (size_t)(q * n) * 4)) || (st = check_dev(C, (size_t)(nb * m * n) * 8)) ||
+        (st = check_dev(R, rb)))
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    // The temporaries A X_b (nb x m x q floats) live in a per-device buffer
+    // kept between calls (grown when a call needs more); calls are
+    // serialised on it.
+    static std::mutex mtx;
+    static float* tbuf[64] = {nullptr};
+    static size_t tbytes[64] = {0};
+    std::lock_guard<std::mutex> lock(mtx);
+    int dev = 0;
+    MEK_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return MEK_EUNSUPPORTED;
+    const size_t need = (size_t)(nb * m * q) * 4;
+    if (tbytes[dev] < need) {
+        if (tbuf[dev]) {
+            MEK_TRY(hipDeviceSynchronize());
+            (void)hipFree(tbuf[dev]);
+            tbuf[dev] = nullptr;
+            tbytes[dev] = 0;
+        }
+        MEK_TRY(hipMalloc((void**)&tbuf[dev], need));
+        tbytes[dev] = need;
+    }
+    float* T = tbuf[dev];
+    const int b = (int)nb;
+    hipError_t e = gemm_bf16s_batched(pieces, b, (int)m, (int)q, (int)p, 1.0, A, p, 1, 0, X, q, 1,
+                                      p * q, 0.0, nullptr, 0, 0, T, q, m * q, s);
+    if (e == hipSuccess)
+        e = gemm_bf16s_batched(pieces, b, (int)m, (int)n, (int)q, -1.0, T, q, 1, m * q, B, n, 1, 0,
+                               1.0, C, n, m * n, R, n, m * n, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e);
 }
 
 }  // extern "C"

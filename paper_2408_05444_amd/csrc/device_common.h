@@ -8,6 +8,22 @@
 
 namespace mek {
 
+// Blocks of a tiled product are dealt to the 8 XCDs round-robin by linear
+// id. Give each XCD a contiguous range of a grouped tile order (G tile rows,
+// column by column) so that the tiles sharing one L2 touch few distinct
+// panels of the two operands. Block b of a tm x tn tile grid -> (ti, tj).
+__device__ __forceinline__ void tile_coords(int b, int tm, int tn, int& ti, int& tj) {
+    constexpr int G = 4;
+    const int nt = tm * tn;
+    const int xcd = b & 7, local = b >> 3, base = nt >> 3, rem = nt & 7;
+    const int lin = xcd < rem ? xcd * (base + 1) + local
+                              : rem * (base + 1) + (xcd - rem) * base + local;
+    const int group = lin / (G * tn), first = group * G;
+    const int rows = min(G, tm - first), within = lin - group * G * tn;
+    ti = first + within % rows;
+    tj = within / rows;
+}
+
 constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kThreads = 512;     // threads per work-group of the solver
 constexpr int kWaves = kThreads / kWave;

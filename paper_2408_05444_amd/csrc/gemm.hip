@@ -37,21 +37,6 @@ constexpr int kTK = 32;
 
 __device__ __forceinline__ int swz(int k) { return ((k & 1) << 4) | ((k & 15) ^ ((k >> 4) & 1)); }
 
-// Blocks are dealt to the 8 XCDs round-robin by linear id. Give each XCD a
-// contiguous range of a grouped tile order (G tile rows, column by column)
-// so that the tiles sharing one L2 touch few distinct panels of A and B.
-__device__ __forceinline__ void tile_coords(int b, int tm, int tn, int& ti, int& tj) {
-    constexpr int G = 4;
-    const int nt = tm * tn;
-    const int xcd = b & 7, local = b >> 3, base = nt >> 3, rem = nt & 7;
-    const int lin = xcd < rem ? xcd * (base + 1) + local
-                              : rem * (base + 1) + (xcd - rem) * base + local;
-    const int group = lin / (G * tn), first = group * G;
-    const int rows = min(G, tm - first), within = lin - group * G * tn;
-    ti = first + within % rows;
-    tj = within / rows;
-}
-
 // AK: A has unit stride along k (else along i); BJ: B has unit stride along
 // j (else along k). The loads put the unit-stride dimension fastest across
 // threads; the other strides are general.

@@ -270,6 +270,13 @@ hipError_t launch_philox(uint64_t seed, uint64_t inst, long long k0, long long c
 // Dense kernels (gemm.hip).
 // D = beta * C + alpha * A B, A(i,k) = A[i*a_i + k*a_k], B(k,j) = B[k*b_k + j*b_j],
 // C, D row-major with leading dimensions ldc, ldd (C may be null when beta == 0).
+// D_b = beta C_b + alpha A_b B_b (FP32 operands split into `pieces` bf16
+// terms on the BF16 matrix cores, FP32 accumulation; C FP64, D FP32).
+hipError_t gemm_bf16s_batched(int pieces, int nb, int M, int N, int K, double alpha,
+                              const float* A, long long a_i, long long a_k, long long sA,
+                              const float* B, long long b_k, long long b_j, long long sB,
+                              double beta, const double* C, long long ldc, long long sC, float* D,
+                              long long ldd, long long sD, hipStream_t s);
 hipError_t gemm_f64(int M, int N, int K, double alpha, const double* A, long long a_i,
                     long long a_k, const double* B, long long b_k, long long b_j, double beta,
                     const double* C, long long ldc, double* D, long long ldd, hipStream_t s);

@@ -163,6 +163,40 @@ def test_blur_channels_mixed_vs_fp64_under_replay():
         assert rel(host(rmx[b].X), host(r64[b].X)) <= 1e-5
 
 
+def test_blur_full_size_mixed_vs_fp64_under_replay():
+    """The image form at full size: 3 channels of a 512 x 512 image, blur
+    sigma 2 on both sides, noise std 1e-3, ME-RGRBK theta 0.8, a budget of
+    100 m = 51200 updates per channel. The FP64 trajectory of channel 0 is
+    the oracle's over its first 2000 updates; replaying channel 0's indices
+    on every channel, the mixed form (FP64 refinement around FP32 inner
+    solves with split-BF16 inner residual refreshes) stays within 1e-5 of
+    the FP64 iterate."""
+    chans = workloads.blurred_image(512, 3, 2.0, seed=4, noise_std=1e-3)
+    A, B = chans[0].A, chans[0].B
+    alpha = oracle.spectral_alpha(B)
+    K, W = 100 * 512, 2000
+    C = stack(chans, "C")
+    p64 = mek.mek_plan_create(cuda(A), cuda(B), alpha=alpha)
+    _, f64 = mek.mek_solve_batched(p64, C, variant="rgrbk", theta=0.8, alpha=alpha,
+                                   max_iters=K, seed=9, hist_cap=K + 1)
+    seq = host(f64[0].idx_hist)
+    ref = oracle.solve(A, B, chans[0].C, variant="rgrbk", theta=0.8, alpha=alpha, max_iters=W,
+                       seed=9)
+    assert seq[:W].tolist() == ref.idx.tolist()
+    rp = cuda(seq, torch.int32)
+    _, r64 = mek.mek_solve_batched(p64, C, variant="rgrbk", theta=0.8, alpha=alpha, max_iters=K,
+                                   replay_idx=rp)
+    pmx = mek.mek_plan_create(cuda(A), cuda(B), alpha=alpha, precision="mixed")
+    _, rmx = mek.mek_solve_batched(pmx, C, variant="rgrbk", theta=0.8, alpha=alpha, max_iters=K,
+                                   replay_idx=rp, inner_iters=K // 8)
+    assert rel(host(r64[0].X), host(f64[0].X)) == 0.0
+    for b in range(3):
+        assert rmx[b].iters == K and rmx[b].passes >= 8
+        assert rel(host(rmx[b].X), host(r64[b].X)) <= 1e-5
+    for P in (p64, pmx):
+        mek.mek_plan_destroy(P)
+
+
 def test_batched_edge_cases():
     base = workloads.small()
     alpha = oracle.spectral_alpha(base.B)
