@@ -32,25 +32,34 @@ STOP_NONE, STOP_REL_ERR, STOP_REL_RESID = 0, 1, 2
 OK, MAXITER, EXACT, EINVAL, ENOMEM, EDIVERGED = 0, 1, 2, -1, -2, -5
 
 
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, _SRC, _SRC_BLOCK, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA
+    contraction), once single-threaded and once with OpenMP (the same source:
+    its row loops split over threads, every sum in the same order, so both
+    builds give identical results)."""
+    for lib_path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib_path):
+            tmp = lib_path + ".tmp"
+            subprocess.check_call(["gcc"] + _CFLAGS + extra + ["-o", tmp, _SRC, _SRC_BLOCK, "-lm"])
+            os.replace(tmp, lib_path)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = ctypes.CDLL(_LIB)
+def lib(omp: bool = False):
+    """The single-threaded build, or with omp=True the OpenMP build (threads
+    from OMP_NUM_THREADS, else every core)."""
+    if omp not in _libs:
+        path = _LIB_OMP if omp else _LIB
+        if not os.path.exists(path):
+            build(force=False)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         d, i64, u64 = ctypes.c_double, ctypes.c_int64, ctypes.c_uint64
         dp, lp, bp = P(d), P(i64), P(ctypes.c_ubyte)
@@ -77,8 +86,8 @@ def lib():
                                   ctypes.c_int, d, dp, i64, d, dp, lp, P(ctypes.c_int), dp, dp,
                                   lp, lp, lp, lp, i64]
         L.mo_solve_2s.restype = ctypes.c_int
-        _lib = L
-    return _lib
+        _libs[omp] = L
+    return _libs[omp]
 
 
 def _dp(x: Optional[np.ndarray]):
@@ -163,8 +172,9 @@ class Result:
 
 def solve(A, B, C, X0=None, variant="grbk", theta=0.5, alpha=None, stop=STOP_NONE, tol=0.0,
           Xref=None, max_iters=1000, seed=0, inst=0, forced=None, literal=False,
-          diverge=0.0, hist_cap=None) -> Result:
-    """Run the oracle iteration. See mo_solve in mek_oracle.c for semantics."""
+          diverge=0.0, hist_cap=None, omp=False) -> Result:
+    """Run the oracle iteration. See mo_solve in mek_oracle.c for semantics.
+    omp=True runs the OpenMP build (same results, row loops over threads)."""
     variant = VARIANTS.get(variant, variant)
     A, B, C, X0, Xref = map(_f64, (A, B, C, X0, Xref))
     m, p = A.shape
@@ -188,7 +198,7 @@ def solve(A, B, C, X0=None, variant="grbk", theta=0.5, alpha=None, stop=STOP_NON
     else:
         fp, nf = None, 0
     LP = ctypes.POINTER(ctypes.c_int64)
-    rc = lib().mo_solve(m, p, q, n, _dp(A), _dp(B), _dp(C), _dp(X0), int(variant), float(theta),
+    rc = lib(omp).mo_solve(m, p, q, n, _dp(A), _dp(B), _dp(C), _dp(X0), int(variant), float(theta),
                         float(alpha), int(stop), float(tol), _dp(Xref), int(max_iters), int(seed),
                         int(inst), fp, nf, 1 if literal else 0, float(diverge), _dp(X),
                         ctypes.byref(it), ctypes.byref(st), _dp(s_hist), _dp(e_hist),

@@ -226,6 +226,7 @@ void mo_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, co
 
 /* G = M M^T for M rows x cols (row-major). */
 void mo_gram_rows(int64_t rows, int64_t cols, const double* M, double* G) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < rows; ++i)
         for (int64_t l = 0; l < rows; ++l) {
             double s = 0.0;
@@ -236,6 +237,7 @@ void mo_gram_rows(int64_t rows, int64_t cols, const double* M, double* G) {
 
 /* G = M^T M for M rows x cols (row-major). */
 void mo_gram_cols(int64_t rows, int64_t cols, const double* M, double* G) {
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < cols; ++j)
         for (int64_t l = 0; l < cols; ++l) {
             double s = 0.0;
@@ -332,12 +334,16 @@ int mo_solve(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, const 
     for (;;) {
         if (literal) mo_residual(m, p, q, n, A, X, B, C, R);
         double S = 0.0;
+        /* Row-parallel in the OpenMP build (each row's sum in the same
+         * order; the total below in ascending row order, as in the plain
+         * build). */
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < m; ++i) {
             double s = 0.0;
             for (int64_t j = 0; j < n; ++j) s += R[i * n + j] * R[i * n + j];
             r[i] = s;
-            S += s;
         }
+        for (int64_t i = 0; i < m; ++i) S += r[i];
         if (S0 < 0.0) S0 = S;
         double err = Xref ? sqrt(frob_diff2((int64_t)pq, X, Xref) / (ref2 > 0.0 ? ref2 : 1.0)) : NAN;
         if (k < hist_cap) {
@@ -370,24 +376,28 @@ int mo_solve(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, const 
         /* The selected residual row (from the pre-update iterate). */
         memcpy(Ri, R + ik * n, sizeof(double) * (size_t)n);
         /* v = R_i B^T (q-vector). */
+#pragma omp parallel for schedule(static)
         for (int64_t l = 0; l < q; ++l) {
             double s = 0.0;
             for (int64_t j = 0; j < n; ++j) s += Ri[j] * B[l * n + j];
             v[l] = s;
         }
         /* X^{k+1} = X^k + alpha/||A_i||^2 A_i^T (R_i B^T). */
+#pragma omp parallel for schedule(static)
         for (int64_t s_ = 0; s_ < p; ++s_) {
             double cas = c * A[ik * p + s_];
             for (int64_t l = 0; l < q; ++l) X[s_ * q + l] += cas * v[l];
         }
         if (!literal) {
             /* w = R_i (B^T B) (n-vector). */
+#pragma omp parallel for schedule(static)
             for (int64_t j = 0; j < n; ++j) {
                 double s = 0.0;
                 for (int64_t l = 0; l < n; ++l) s += Ri[l] * GB[l * n + j];
                 w[j] = s;
             }
             /* R^{k+1} = R^k - alpha/||A_i||^2 (A A^T)_{:,i} (R_i B^T B). */
+#pragma omp parallel for schedule(static)
             for (int64_t h = 0; h < m; ++h) {
                 double cg = c * GA[h * m + ik];
                 for (int64_t j = 0; j < n; ++j) R[h * n + j] -= cg * w[j];

@@ -2,6 +2,8 @@
 iteration and result as mek_solve, calls queued without host waits, and
 capture into a graph replayed several times with the program's own eager
 work between the replays (every replay checked against the eager result)."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -58,7 +60,9 @@ def test_async_fp32():
     inst = workloads.small(seed=5)
     plan = mek.mek_plan_create(cuda(inst.A), cuda(inst.B), precision="fp32")
     kw = dict(variant="grbk", stop="rel_resid", tol=1e-4, max_iters=500000, seed=8)
-    one = mek.mek_solve(plan, cuda(inst.C), **kw)
+    # The stream-ordered call runs without residual refreshes: compare with
+    # the blocking call with refreshes switched off.
+    one = mek.mek_solve(plan, cuda(inst.C), refresh_period=-1, **kw)
     X, rep = mek.mek_solve_async(plan, cuda(inst.C), **kw)
     torch.cuda.synchronize()
     r = mek.read_device_report(rep)
@@ -76,6 +80,17 @@ def test_async_rejects_unsupported_forms():
     with pytest.raises(mek.MekError) as e:
         mek.mek_solve_async(p64, cuda(inst.C), variant="twosided", max_iters=10)
     assert e.value.code == mek.MEK_EUNSUPPORTED
+    # Residual refreshes need host decisions between passes.
+    o = mek.mek_solve_opts()
+    o.max_iters = 10
+    o.refresh_period = 5
+    C = cuda(inst.C)
+    X = torch.empty(40, 40, dtype=torch.float64, device="cuda")
+    rep = torch.zeros(mek.DEVICE_REPORT_BYTES, dtype=torch.uint8, device="cuda")
+    st = mek.lib().mek_solve_async(p64.handle, ctypes.c_void_p(C.data_ptr()), None, ctypes.byref(o),
+                                   ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(rep.data_ptr()),
+                                   None)
+    assert st == mek.MEK_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("team", [1, 6])

@@ -161,3 +161,79 @@ def test_forward_store_and_add():
     assert np.allclose(b[-1] - add, a[-1], rtol=0.05, atol=0.05)
     for li in (1, 2, 3):
         assert np.array_equal(conv.bf16(b[li]), b[li])
+
+
+def _one_pixel_net(W1c, W2c, pad_tap=7.0):
+    """Two 1 -> 1 channel layers on a 1 x 1 image: only the centre tap meets
+    the pixel, every other tap reads the zero padding (set to pad_tap to
+    show it is never used)."""
+    W1 = np.full((1, 1, 3, 3), pad_tap)
+    W2 = np.full((1, 1, 3, 3), -pad_tap)
+    W1[0, 0, 1, 1] = W1c
+    W2[0, 0, 1, 1] = W2c
+    return [(W1, np.zeros(1)), (W2, np.zeros(1))]
+
+
+def test_backward_store_worked_example():
+    """Hand-worked BF16 storage points of backward(store=bf16) (spacing 2^-7
+    on [1, 2), ties to even): the loss gradient and each propagated input
+    gradient of layers above the first are rounded; the weight and bias
+    gradients and the input gradient of the first layer are not."""
+    e = 2.0 ** -10
+    params = _one_pixel_net(1 + e, 1 + e)
+    x = np.full((1, 1, 1, 1), 1 + 2.0 ** -11)
+    acts = conv.forward(params, x, store=conv.bf16)
+    # z1 = (1 + 2^-10)(1 + 2^-11) rounds to 1; y = (1 + 2^-10) * 1.
+    assert acts[1][0, 0, 0, 0] == 1.0 and acts[2][0, 0, 0, 0] == 1 + e
+    d = 0.5 * (1 + 3 * 2.0 ** -9)
+    label = acts[2] - d
+    loss, grads, dx = conv.backward(params, acts, label, store=conv.bf16)
+    assert loss == pytest.approx(d * d, rel=1e-15)
+    g2 = 1 + 2.0 ** -7          # bf16(2 d) = bf16(1 + 3 2^-9): rounds up
+    g1 = 1 + 2.0 ** -7          # bf16(W2 g2) = bf16(1 + 2^-7 + 2^-10 + 2^-17): rounds down
+    (dW1, db1), (dW2, db2) = grads
+    assert dW2[0, 0, 1, 1] == g2 * 1.0 and db2[0] == g2
+    # Weight gradient of layer 1: stored g1 times the (unrounded) input.
+    assert dW1[0, 0, 1, 1] == g1 * (1 + 2.0 ** -11) and db1[0] == g1
+    assert dW1[0, 0, 1, 1] != conv.bf16(np.array([dW1[0, 0, 1, 1]]))[0]
+    # Taps that only meet the padding get zero gradient.
+    off = np.ones((3, 3), bool)
+    off[1, 1] = False
+    assert np.all(dW1[0, 0][off] == 0.0) and np.all(dW2[0, 0][off] == 0.0)
+    # The first layer's input gradient is not rounded.
+    assert dx[0, 0, 0, 0] == (1 + e) * g1
+
+
+def test_backward_store_points_and_gate_order():
+    """The values handed to `store` are, in order, the loss gradient and the
+    ungated input gradients of layers 3, 2, 1 (each then gated by the layer
+    below's ReLU output); rounding commutes with that 0/1 gate. Checked
+    against the unrounded backward with the same rounding applied by hand."""
+    rng = np.random.default_rng(8)
+    params = [(rng.standard_normal((o, c, 3, 3)) * 0.3, rng.standard_normal(o) * 0.1)
+              for c, o in zip(conv.CHANNELS[:-1], conv.CHANNELS[1:])]
+    x, label = rng.uniform(0, 1, (1, 3, 5, 5)), rng.uniform(0, 1, (1, 3, 5, 5))
+    acts = conv.forward(params, x, store=conv.bf16)
+    seen = []
+
+    def rec(v):
+        seen.append(np.array(v))
+        return conv.bf16(v)
+
+    _, grads, dx = conv.backward(params, acts, label, store=rec)
+    assert len(seen) == 4
+    # By hand: the same chain with conv.bf16 at the documented points.
+    g = conv.bf16(2.0 * (acts[-1] - label) / acts[-1].size)
+    assert np.array_equal(seen[0], 2.0 * (acts[-1] - label) / acts[-1].size)
+    for li, k in zip((3, 2, 1), (1, 2, 3)):
+        if li < 3:
+            g = g * (acts[li + 1] > 0)
+        dW, db = conv.conv3x3_grad_weight(g, acts[li])
+        assert np.array_equal(grads[li][0], dW) and np.array_equal(grads[li][1], db)
+        raw = conv.conv3x3_grad_input(g, params[li][0])
+        assert np.array_equal(seen[k], raw)
+        g = conv.bf16(raw)
+    g = g * (acts[1] > 0)
+    dW, db = conv.conv3x3_grad_weight(g, acts[0])
+    assert np.array_equal(grads[0][0], dW) and np.array_equal(grads[0][1], db)
+    assert np.array_equal(dx, conv.conv3x3_grad_input(g, params[0][0]))
