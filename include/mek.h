@@ -369,6 +369,22 @@ int mek_residual_batched(int64_t nb, int64_t m, int64_t p, int64_t q, int64_t n,
                          const double* X, const double* B, const double* C, double* R,
                          void* stream);
 
+/* For callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residual engine of mek_residual, R = C - (A X) B (same arguments, same
+ * kernels, same results), with the temporary T = A X (m x q doubles) in a
+ * fixed per-device array of 2^21 doubles (16 MiB) that the library holds
+ * until the process ends, so the call never allocates or frees. Stream
+ * ordered: returns once both products are enqueued on `stream`, without
+ * waiting. Every call on one device shares that device's array: calls that
+ * overlap on one device (other streams, other threads) race and give
+ * undefined results; order them on one stream. Errors: MEK_EINVAL for
+ * m q > 2^21, sizes <= 0, null, host, short or overlapping pointers;
+ * MEK_EHIP if a launch fails. */
+int mek_residual_noalloc(int64_t m, int64_t p, int64_t q, int64_t n, const double* A,
+                         const double* X, const double* B, const double* C, double* R,
+                         void* stream);
+
 /* The FP32 residual engine of the FP32 and mixed iterations (the residual
  * R = C - A X B with which Alg. 3 starts, recomputed from the current
  * iterate so that the incrementally updated FP32 residual does not drift):

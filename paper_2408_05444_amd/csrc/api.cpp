@@ -2254,6 +2254,71 @@ int mek_residual(int64_t m, int64_t p, int64_t q, int64_t n, const double* A, co
     return mek_residual_batched(1, m, p, q, n, A, X, B, C, R, stream);
 }
 
+}  // extern "C"
+
+// ---- Residual engine without allocation: the temporary T = A X lives in a
+// fixed device array of kNoAllocScratch doubles (16 MiB), one per device,
+// held until the process ends. Host code never passes the array's name to
+// a kernel (on the host it only stands in for the symbol): its device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+namespace {
+constexpr size_t kNoAllocScratch = (size_t)1 << 21;
+__device__ __align__(256) double scratch[kNoAllocScratch];
+std::mutex g_scratch_mtx;
+double* g_scratch_ptr[64] = {nullptr};
+
+int noalloc_scratch(double** out) {
+    int dev = 0;
+    MEK_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return MEK_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mtx);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return MEK_EHIP;
+        }
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MEK_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mek_residual_noalloc(int64_t m, int64_t p, int64_t q, int64_t n, const double* A,
+                         const double* X, const double* B, const double* C, double* R,
+                         void* stream) {
+    if (m <= 0 || p <= 0 || q <= 0 || n <= 0) return MEK_EINVAL;
+    if (m > INT32_MAX / 2 || p > INT32_MAX / 2 || q > INT32_MAX / 2 || n > INT32_MAX / 2)
+        return MEK_EINVAL;
+    if ((uint64_t)m * (uint64_t)q > kNoAllocScratch) return MEK_EINVAL;   // T does not fit
+    if (!A || !X || !B || !C || !R) return MEK_EINVAL;
+    const size_t rb = (size_t)(m * n) * 8;
+    auto overlaps = [&](const double* x, size_t bytes) {
+        const char *r0 = (const char*)R, *x0 = (const char*)x;
+        return r0 < x0 + bytes && x0 < r0 + rb;
+    };
+    if (overlaps(A, (size_t)(m * p) * 8) || overlaps(X, (size_t)(p * q) * 8) ||
+        overlaps(B, (size_t)(q * n) * 8) || overlaps(C, rb))
+        return MEK_EINVAL;
+    int st;
+    if ((st = check_dev(A, (size_t)(m * p) * 8)) || (st = check_dev(X, (size_t)(p * q) * 8)) ||
+        (st = check_dev(B, (size_t)(q * n) * 8)) || (st = check_dev(C, rb)) ||
+        (st = check_dev(R, rb)))
+        return st;
+    double* T = nullptr;
+    if ((st = noalloc_scratch(&T))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // T = A X fills the first m q doubles completely (beta = 0), so nothing
+    // has to be cleared between calls.
+    MEK_TRY(gemm_f64((int)m, (int)q, (int)p, 1.0, A, p, 1, X, q, 1, 0.0, nullptr, 0, T, q, s));
+    MEK_TRY(gemm_f64((int)m, (int)n, (int)q, -1.0, T, q, 1, B, n, 1, 1.0, C, n, R, n, s));
+    return MEK_OK;
+}
+
 int mek_residual_split(int pieces, int64_t nb, int64_t m, int64_t p, int64_t q, int64_t n,
                        const float* A, const float* X, const float* B, const double* C, float* R,
                        void* stream) {
