@@ -15,6 +15,7 @@ import argparse
 import json
 import os
 import sys
+import subprocess
 import time
 
 import numpy as np
@@ -74,6 +75,7 @@ def measured_traffic(team_wgs, iters):
 
 TS_BLOCK = 32   # block rows / columns of the two-sided form
 MFMA_F64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 
 
 def gemm_forms(mek, torch, A, B, Xs, C, blur=None, reps=10):
@@ -95,7 +97,24 @@ def gemm_forms(mek, torch, A, B, Xs, C, blur=None, reps=10):
         m3, n3 = A3.shape[0], B3.shape[1]
         cases["residual_blur3_batched"] = (lambda: mek.mek_residual_batched(A3, X3, B3, C3),
                                            2.0 * nb * (m3 * p3 * q3 + m3 * q3 * n3))
-    for name, (fn, flops) in cases.items():
+    # The split-BF16 residual engine of the FP32 and mixed iterations (BF16
+    # matrix cores, FP32 accumulation): FP32 operands, 3 and 2 bf16 terms per
+    # value (6 and 3 bf16 products per multiply-add). Its flop count is the
+    # algorithmic 2 M N K per product; the bf16 work is 6x (3x) that.
+    A32, B32 = A.float().contiguous(), B.float().contiguous()
+    X32, C1 = Xs.float().contiguous()[None], C[None].contiguous()
+    for P, mult in ((3, 6), (2, 3)):
+        cases[f"split{P}_residual_C-AXB"] = (
+            lambda P=P: mek.mek_residual_split(A32, X32, B32, C1, pieces=P),
+            2.0 * (m * p * q + m * q * n), mult)
+    if blur is not None:
+        A3f, B3f, X3f = A3.float().contiguous(), B3.float().contiguous(), X3.float().contiguous()
+        cases["split3_residual_blur3_batched"] = (
+            lambda: mek.mek_residual_split(A3f, X3f, B3f, C3, pieces=3),
+            2.0 * nb * (m3 * p3 * q3 + m3 * q3 * n3), 6)
+    for name, case in cases.items():
+        fn, flops = case[0], case[1]
+        bf16 = len(case) > 2
         fn()
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -109,8 +128,15 @@ def gemm_forms(mek, torch, A, B, Xs, C, blur=None, reps=10):
         # Each call validates its pointers and synchronises, so this time
         # includes the call's own overhead: a lower bound on the kernels'
         # rate (the kernel trace in profiles/ gives the kernels alone).
-        out[name] = {"ms_per_call": sec * 1e3, "tflops_incl_call": tf,
-                     "peak_tflops": MFMA_F64_PEAK_TFLOPS, "frac_incl_call": tf / MFMA_F64_PEAK_TFLOPS}
+        if bf16:
+            tfb = tf * case[2]
+            out[name] = {"ms_per_call": sec * 1e3, "tflops_incl_call": tf,
+                         "bf16_tflops_incl_call": tfb, "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+                         "frac_incl_call": tfb / MFMA_BF16_PEAK_TFLOPS}
+        else:
+            out[name] = {"ms_per_call": sec * 1e3, "tflops_incl_call": tf,
+                         "peak_tflops": MFMA_F64_PEAK_TFLOPS,
+                         "frac_incl_call": tf / MFMA_F64_PEAK_TFLOPS}
     return out
 
 
@@ -187,13 +213,56 @@ def blur_batch_forms(mek, workloads, torch):
         "rel_diff_vs_dense_fp64": float(torch.linalg.norm(Xsp - X64) / torch.linalg.norm(X64)),
         "same_indices_as_dense_channel0": same / K}
     mek.mek_plan_destroy(plan)
+    out["discrepancy_stop"] = blur_discrepancy_forms(mek, workloads, torch, A, B, C, Xs)
+    return out
+
+
+def _psnr(X, Xs):
+    """Peak signal-to-noise ratio of X against X* for images in [0, 1]."""
+    mse = float(((X - Xs) ** 2).mean())
+    return 10.0 * np.log10(1.0 / mse) if mse > 0 else float("inf")
+
+
+def blur_discrepancy_forms(mek, workloads, torch, A, B, C, Xs):
+    """The image form stopped by the discrepancy principle: each channel
+    solved (ME-RGRBK theta 0.8) until ||C - A X B||_F <= 1.05 ||E||_F, with E
+    the channel's added noise (rel. error 1e-6 against the image is out of
+    reach, the blur being ill conditioned and C noisy), one solve per
+    channel; the FP64 dense form, the mixed form and the FP64 sparse-aware
+    form. Time to the stop and PSNR of the result against the image."""
+    chans = workloads.blurred_image(512, 3, 2.0, seed=4, noise_std=1e-3)
+    out = {}
+    for name, prec, upd in [("fp64", "fp64", "dense"), ("mixed", "mixed", "dense"),
+                            ("fp64_sparse", "fp64", "sparse")]:
+        plan = mek.mek_plan_create(A, B, precision=prec, update=upd)
+        per = []
+        for c, ch in enumerate(chans):
+            E = float(np.linalg.norm(ch.C - ch.A @ ch.X_star @ ch.B))
+            tol = 1.05 * E / float(np.linalg.norm(ch.C))
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            r = mek.mek_solve(plan, C[c].contiguous(), variant="rgrbk", theta=0.8,
+                              stop="rel_resid", tol=tol, max_iters=3_000_000,
+                              seed=2408054440, instance=c)
+            torch.cuda.synchronize()
+            te = time.perf_counter() - ts
+            per.append({"iters": r.iters, "time_s": te, "status": r.status,
+                        "psnr_db": _psnr(r.X, Xs[c]),
+                        "rel_err_vs_image": float(torch.linalg.norm(r.X - Xs[c]) /
+                                                  torch.linalg.norm(Xs[c]))})
+        mek.mek_plan_destroy(plan)
+        out[name] = {"channels": per, "time_s": sum(x["time_s"] for x in per),
+                     "mean_psnr_db": float(np.mean([x["psnr_db"] for x in per])),
+                     "all_stopped": all(x["status"] == 0 for x in per)}
+    blurred = [_psnr(torch.from_numpy(ch.C).to(A.device), Xs[c]) for c, ch in enumerate(chans)]
+    out["psnr_blurred_db"] = float(np.mean(blurred))
     return out
 
 
 def variant_sweep_forms(mek, workloads, torch, A, B, C, Xs, seed):
     """The variant sweep on the large workload: ME-GRBK, ME-RGRBK (theta 0.5
-    and 1) and ME-MWRBK in FP64 (to relative error 1e-6) and FP32 (to 1e-4,
-    its reach); then ME-GRBK in FP64 on the rank-deficient case A = U V
+    and 1) and ME-MWRBK in FP64 (to relative error 1e-6) and FP32 (to 1e-5,
+    residual refreshed from the iterate every 4 m updates); then ME-GRBK in FP64 on the rank-deficient case A = U V
     (rank 250, data seed 3) to 1e-6 against the least-norm solution
     A^+ C B^+ = V^T (V V^T)^-1 V X* (B has full row rank and U full column
     rank, so A^+ A is the projector onto the rows of V). Wall time of plan
@@ -213,7 +282,7 @@ def variant_sweep_forms(mek, workloads, torch, A, B, C, Xs, seed):
                     "iters_per_s": r.iters / te, "rel_err": r.rel_err, "status": r.status,
                     "kernel_us_per_update": r.kernel_ms * 1e3 / max(r.iters, 1)}
 
-    for prec, tol in [("fp64", 1e-6), ("fp32", 1e-4)]:
+    for prec, tol in [("fp64", 1e-6), ("fp32", 1e-5)]:
         for v, th in [("grbk", 0.5), ("rgrbk", 0.5), ("rgrbk", 1.0), ("mwrbk", 0.5)]:
             run(f"{prec}_{v}_theta{th}", A, B, C, Xs, prec, v, th, tol)
     rd = workloads.large_rankdef()
@@ -476,18 +545,107 @@ def warm_start_forms(mek, workloads, torch, n_train=1024, n_test=512, epochs=20,
             "mean_start_rel_resid_warm": float(np.mean(r["start_rel_resid_warm"]))}
 
 
-def cpu_baseline(inst, seed, updates=600):
+def _host_cpu():
+    """Model name (lscpu) and logical CPU count of the host."""
+    model = "unknown"
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return model, os.cpu_count()
+
+
+def _oracle_rate(oracle, inst, seed, updates, runs, omp, alpha):
+    """Updates/s of the oracle's iteration loop: median over `runs` solves of
+    `updates` ME-GRBK updates, each minus the median time of the set-up alone
+    (row norms, Gram matrices, initial residual: a solve with 0 updates)."""
+    kw = dict(variant="grbk", alpha=alpha, seed=seed, omp=omp, hist_cap=1)
+    setup, total = [], []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.solve(inst.A, inst.B, inst.C, max_iters=0, **kw)
+        t1 = time.perf_counter()
+        oracle.solve(inst.A, inst.B, inst.C, max_iters=updates, **kw)
+        t2 = time.perf_counter()
+        setup.append(t1 - t0)
+        total.append(t2 - t1)
+    loop = max(float(np.median(total)) - float(np.median(setup)), 1e-9)
+    return updates / loop, float(np.median(setup))
+
+
+def cpu_baseline(inst, seed, workloads):
+    """The CPU oracle on this host, as it stands: the plain single-threaded
+    build and the OpenMP build of the same source (row loops over all
+    threads, identical results). Headline: the 2000 x 500 / 500 x 2000 FP64
+    ME-GRBK instance, median of 5 windows of 200 updates (all threads) and of
+    3 windows of 100 updates (one thread), set-up excluded. Also the
+    100 x 40 / 40 x 100 instance's full time to rel. error 1e-6 (median of 5,
+    one thread) and a 200-update window of one 512 x 512 blur channel."""
     import oracle
     alpha = oracle.spectral_alpha(inst.B)
-    t0 = time.perf_counter()
-    oracle.solve(inst.A, inst.B, inst.C, variant="grbk", alpha=alpha, max_iters=0, seed=seed)
-    t1 = time.perf_counter()
-    oracle.solve(inst.A, inst.B, inst.C, variant="grbk", alpha=alpha, max_iters=updates, seed=seed)
-    t2 = time.perf_counter()
-    iter_time = max((t2 - t1) - (t1 - t0), 1e-9)
-    return {"value": updates / iter_time, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{updates} ME-GRBK updates of the same 2000x500/500x2000 FP64 instance "
-                      f"on one host core (set-up of {t1 - t0:.1f} s excluded)"}
+    model, ncpu = _host_cpu()
+    thr = oracle.threads(omp=True)
+    rate_all, set_all = _oracle_rate(oracle, inst, seed, 200, 5, True, alpha)
+    rate_one, set_one = _oracle_rate(oracle, inst, seed, 100, 3, False, alpha)
+    c1 = workloads.small()
+    a1 = oracle.spectral_alpha(c1.B)
+    t1s, it1 = [], 0
+    for _ in range(5):
+        t0 = time.perf_counter()
+        r = oracle.solve(c1.A, c1.B, c1.C, variant="grbk", alpha=a1, stop=oracle.STOP_REL_ERR,
+                         tol=1e-6, Xref=c1.X_star, max_iters=10 ** 7, seed=seed, hist_cap=1)
+        t1s.append(time.perf_counter() - t0)
+        it1 = r.iters
+    blur = workloads.blurred_image(512, 1, 2.0, seed=4, noise_std=1e-3)[0]
+    rate_blur, _ = _oracle_rate(oracle, blur, seed, 200, 3, True, oracle.spectral_alpha(blur.B))
+    return {"value": rate_all, "unit": "iters/s", "cores": thr, "kind": "oracle",
+            "sample": f"ME-GRBK on the same 2000x500/500x2000 FP64 instance, OpenMP build on "
+                      f"{thr} threads: median of 5 windows of 200 updates, set-up "
+                      f"({set_all:.2f} s) excluded",
+            "host": {"cpu_model": model, "logical_cpus": ncpu},
+            "single_thread": {"value": rate_one, "unit": "iters/s", "cores": 1,
+                              "sample": "median of 3 windows of 100 updates, set-up "
+                                        f"({set_one:.2f} s) excluded"},
+            "small_100x40_time_to_1e-6": {"time_s": float(np.median(t1s)), "iters": it1,
+                                          "iters_per_s": it1 / float(np.median(t1s)),
+                                          "cores": 1, "runs": 5},
+            "blur512_one_channel": {"value": rate_blur, "unit": "iters/s", "cores": thr,
+                                    "sample": "median of 3 windows of 200 ME-GRBK updates, "
+                                              "set-up excluded"}}
+
+
+def small_forms(mek, workloads, torch, reps=7):
+    """Plain ME-GRBK on A 100 x 40, B 40 x 100, X* 40 x 40 iid N(0, 1) (data
+    seed 1), C = A X* B, X0 = 0, FP64, alpha = 1/||B||_2^2 from the oracle's
+    SVD passed explicitly, stopped at ||X - X*||_F <= 1e-6 ||X*||_F (checked
+    before every update). Time to tolerance (plan made once; median over
+    `reps` solves, host wait and report copy included) and kernel time."""
+    import oracle
+    inst = workloads.small()
+    alpha = oracle.spectral_alpha(inst.B)
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    A, B, C, Xs = t(inst.A), t(inst.B), t(inst.C), t(inst.X_star)
+    plan = mek.mek_plan_create(A, B, alpha=alpha)
+    kw = dict(variant="grbk", alpha=alpha, stop="rel_err", tol=1e-6, X_ref=Xs,
+              max_iters=10 ** 7, seed=2408054440)
+    mek.mek_solve(plan, C, **kw)
+    walls, res = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        res = mek.mek_solve(plan, C, **kw)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - ts)
+    mek.mek_plan_destroy(plan)
+    w = float(np.median(walls))
+    return {"tol": 1e-6, "iters": res.iters, "status": res.status, "rel_err": res.rel_err,
+            "time_to_tol_s": w, "iters_per_s": res.iters / w, "team_wgs": res.team_wgs,
+            "kernel_us_per_update": res.kernel_ms * 1e3 / max(res.iters, 1)}
 
 
 def main():
@@ -635,9 +793,9 @@ def main():
     }
     if not args.no_forms:
         forms = {}
-        # FP32 alone stalls near 1e-4 (its incremental residual drifts by
-        # O(1e-7) per sweep), so it is timed to 1e-4; mixed reaches 1e-6.
-        for prec, tol, cap in [("fp32", 1e-4, 1_000_000), ("mixed", 1e-6, 5_000_000)]:
+        # FP32 (residual refreshed from the iterate every 4 m updates on the
+        # split-BF16 engine) is timed to its target 1e-5; mixed to 1e-6.
+        for prec, tol, cap in [("fp32", 1e-5, 1_000_000), ("mixed", 1e-6, 5_000_000)]:
             torch.cuda.synchronize()
             ts = time.perf_counter()
             r = step(prec, tol, cap)
@@ -666,6 +824,7 @@ def main():
                              "kernel_us_per_step": r.kernel_ms * 1e3 / max(r.iters, 1)}
         # Each form reports to stderr when it ends (the run takes minutes).
         for name, fn in [
+                ("small_100x40", lambda: small_forms(mek, workloads, torch)),
                 ("variant_sweep", lambda: variant_sweep_forms(mek, workloads, torch, A, B, C, Xs, seed)),
                 ("blur3_batched", lambda: blur_batch_forms(mek, workloads, torch)),
                 ("blur_sparse_many", lambda: sparse_many_forms(mek, workloads, torch)),
@@ -681,7 +840,7 @@ def main():
         line["gemm_mfma_f64"] = gemm_forms(mek, torch, A, B, Xs, C,
                                            blur=blur_tensors(workloads, torch))
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(inst, seed)
+        line["cpu_baseline"] = cpu_baseline(inst, seed, workloads)
     print(json.dumps(line), flush=True)
 
 

@@ -65,6 +65,8 @@ def lib(omp: bool = False):
         dp, lp, bp = P(d), P(i64), P(ctypes.c_ubyte)
         L.mo_philox4x64_10.argtypes = [P(u64), P(u64), P(u64)]
         L.mo_philox4x64_10.restype = None
+        L.mo_threads.argtypes = []
+        L.mo_threads.restype = ctypes.c_int
         L.mo_uniform.argtypes = [u64, u64, i64]
         L.mo_uniform.restype = d
         L.mo_select.argtypes = [ctypes.c_int, i64, dp, dp, d, d, u64, u64, i64, bp, dp, dp]
@@ -168,6 +170,11 @@ class Result:
         self.e_hist = e_hist
         self.idx = idx_hist
         self.set_sizes = set_hist
+
+
+def threads(omp: bool = False) -> int:
+    """Threads the oracle's row loops run on (1 for the plain build)."""
+    return int(lib(omp).mo_threads())
 
 
 def solve(A, B, C, X0=None, variant="grbk", theta=0.5, alpha=None, stop=STOP_NONE, tol=0.0,

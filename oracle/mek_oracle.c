@@ -46,6 +46,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MO_BK 0
 #define MO_RBK 1
@@ -98,6 +101,15 @@ void mo_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64
         x0 = y0; x1 = y1; x2 = y2; x3 = y3;
     }
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Threads the row loops use: 1 in the plain build. */
+int mo_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Uniform draw in [0, 1) for iteration k of instance `inst`. */

@@ -180,12 +180,13 @@ class Plan:
     n: int
     precision: int
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # A plan dropped during interpreter shutdown is left to the process
         # exit: by then the HIP runtime (and any profiler attached to it) may
         # already be tearing down, and a device synchronise or free issued
-        # from a finaliser at that point can crash the exit path.
-        if sys.is_finalizing():
+        # from a finaliser at that point can crash the exit path. (The check
+        # is bound as a default: module globals may already be cleared.)
+        if _finalizing():
             return
         try:
             if self.handle:

@@ -1316,7 +1316,11 @@ int solve_impl(mek_plan P, int64_t nb, const double* C, const double* X0,
                 }
                 InstSlot sl = slot_for(b);
                 sl.C2 = S;
-                sl.S_target = 1e-6 * S;
+                // The inner residual tracks the true residual of X_acc + D,
+                // so under REL_RESID the inner pass also ends where the
+                // outer rule would (the next pass checks it in FP64).
+                sl.S_target = std::max(1e-6 * S, o->stop == MEK_STOP_REL_RESID
+                                                     ? o->tol * o->tol * C2[b] : 0.0);
                 sl.max_iters = std::min<long long>(inner_cap, o->max_iters - done[b]);
                 sl.k_offset = done[b];
                 sl.hist_offset = done[b];
@@ -1794,7 +1798,17 @@ int multi_setup(int64_t nb, const mek_plan* plans, const double* const* C,
         cost[b] = (double)P->m * P->n + 2.0 * P->q * P->n + 2.0 * P->p * P->q;
         wmax[b] = (int)std::max<int64_t>(1, (P->m + kRowsPerWG - 1) / kRowsPerWG);
     }
-    for (int spare = cus - (int)nb; spare > 0; --spare) {
+    // Team sizes given on every plan (an autotuned allocation) and fitting the
+    // device are taken as they are.
+    int64_t given = 0;
+    bool all_given = true;
+    for (int64_t b = 0; b < nb; ++b) {
+        all_given = all_given && Ps[b]->team_wgs > 0;
+        given += std::max(0, Ps[b]->team_wgs);
+    }
+    if (all_given && given <= cus)
+        for (int64_t b = 0; b < nb; ++b) cap[b] = wmax[b] = Ps[b]->team_wgs;
+    for (int spare = cus - (int)nb; !(all_given && given <= cus) && spare > 0; --spare) {
         int64_t best = -1;
         for (int64_t b = 0; b < nb; ++b)
             if (cap[b] < wmax[b] && (best < 0 || cost[b] / cap[b] > cost[best] / cap[best]))

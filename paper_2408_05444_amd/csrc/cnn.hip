@@ -27,6 +27,13 @@ constexpr int kMaxC = 32;                // channels of the network
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) {
+    return (uint32_t)lo | ((uint32_t)hi << 16);
+}
+
 // FP32 -> BF16, round to nearest, ties to even (NaN stays a quiet NaN).
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -189,6 +196,130 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
     }
 }
 
+// Weight and bias gradient partial sums of one 16 x 16 pixel tile on the
+// BF16 matrix cores, for 32 input channels: per tap t, D_t[o][c] =
+// sum over the tile's pixels of g'[o][p] x[c][p + shift_t], the 256 pixels
+// as 8 k steps of 32 (two 16-pixel rows each). The gradient tile sits in LDS
+// as [o][pixel] (a k chunk is 8 consecutive pixels of a row); the input as
+// three column-shifted copies x_j[c][halo row][16 columns] = x[c][h0 - 1 +
+// row][w0 + col + j - 1], so that the chunk of tap (i, j) is one aligned
+// 16-byte read. The 9 taps x output-channel tiles x input-channel tiles of
+// the block's result are shared out over its 4 waves; the bias gradient is
+// a plain sum. Partials are written in the layout of the VALU kernel, so the
+// same fixed-order summation follows.
+constexpr int kGStride = 33;   // 16-byte slots per output channel of the gradient tile (odd)
+constexpr int kXStride = 37;   // slots per input channel of a shifted copy (18 rows x 2, + 1)
+
+template <int CO>
+__global__ void __launch_bounds__(256)
+conv3x3_wgrad_mfma_kernel(const uint16_t* __restrict__ x, int H, int W,
+                          const uint16_t* __restrict__ g, const uint16_t* __restrict__ gmask,
+                          float* __restrict__ partial) {
+    constexpr int CI = 32;
+    constexpr int COP = (CO + 15) & ~15;
+    constexpr int OT = COP / 16, CT = CI / 16;
+    constexpr int TILES = 9 * OT * CT;            // 16 x 16 result tiles of the block
+    constexpr int PER = (TILES + 3) / 4;          // per wave
+    __shared__ uint4 gs[COP * kGStride];
+    __shared__ uint16_t xsh[3 * CI * kXStride * 8];
+    __shared__ float bsum[4][COP];
+    const int tiles_w = (W + kCT - 1) / kCT;
+    const int th = blockIdx.x / tiles_w, tw = blockIdx.x - th * tiles_w;
+    const int n = blockIdx.y;
+    const int h0 = th * kCT, w0 = tw * kCT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t plane = (size_t)H * W;
+
+    // Gradient tile (gated), zero outside the image and in padded channels;
+    // the bias gradient from the same values.
+    for (int e = tid; e < COP * 32; e += 256) {
+        const int o = e >> 5, chk = e & 31;          // 32 chunks of 8 pixels
+        const int hh = h0 + (chk >> 1), ww0 = w0 + 8 * (chk & 1);
+        uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (o < CO && hh < H) {
+            const size_t base = ((size_t)n * CO + o) * plane + (size_t)hh * W;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int ww = ww0 + u;
+                if (ww < W) {
+                    uint16_t b = g[base + ww];
+                    if (gmask && !(bf2f(gmask[base + ww]) > 0.0f)) b = 0;
+                    v[u] = b;
+                }
+            }
+        }
+        gs[o * kGStride + chk] = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]),
+                                            pack2(v[6], v[7]));
+    }
+    // Input: each halo element to the shifted copies that hold it.
+    for (int e = tid; e < CI * kHaloPix; e += 256) {
+        const int c = e / kHaloPix, r = e - c * kHaloPix;
+        const int hr = r / kHalo, hc = r % kHalo;
+        const int hh = h0 - 1 + hr, ww = w0 - 1 + hc;
+        uint16_t b = 0;
+        if (hh >= 0 && hh < H && ww >= 0 && ww < W) b = x[((size_t)n * CI + c) * plane + (size_t)hh * W + ww];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int col = hc - j;
+            if (col >= 0 && col < 16)
+                xsh[((j * CI + c) * kXStride + 2 * hr + (col >> 3)) * 8 + (col & 7)] = b;
+        }
+    }
+    __syncthreads();
+    // Bias gradient: thread (o, part) sums a quarter of the tile's pixels.
+    if (tid < 4 * COP) {
+        const int o = tid % COP, part = tid / COP;
+        float sacc = 0.0f;
+        for (int chk = 8 * part; chk < 8 * part + 8; ++chk) {
+            const uint4 w4 = gs[o * kGStride + chk];
+            const uint32_t ww[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sacc += bf2f(ww[u] & 0xffff) + bf2f(ww[u] >> 16);
+        }
+        bsum[part][o] = sacc;
+    }
+
+    const int l16 = lane & 15, lq = lane >> 4;
+    const uint4* xs4 = reinterpret_cast<const uint4*>(xsh);
+    float4_t acc[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) acc[u] = (float4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        // k chunk of this lane: pixel row 2 ks + lq / 2, columns 8 (lq & 1) ..
+        const int prow = 2 * ks + (lq >> 1), half = lq & 1;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int tile = wave * PER + u;
+            if (tile >= TILES) break;
+            const int t = tile / (OT * CT), rem = tile % (OT * CT);
+            const int ot = rem / CT, ct = rem % CT;
+            const int i = t / 3, j = t % 3;
+            const bf16x8_t fa =
+                __builtin_bit_cast(bf16x8_t, gs[(16 * ot + l16) * kGStride + 2 * prow + half]);
+            const bf16x8_t fb = __builtin_bit_cast(
+                bf16x8_t, xs4[(j * CI + 16 * ct + l16) * kXStride + 2 * (prow + i) + half]);
+            acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[u], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    const size_t E = (size_t)CO * CI * 9 + CO;
+    float* out = partial + ((size_t)n * gridDim.x + blockIdx.x) * E;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int tile = wave * PER + u;
+        if (tile >= TILES) break;
+        const int t = tile / (OT * CT), rem = tile % (OT * CT);
+        const int ot = rem / CT, ct = rem % CT;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int o = 16 * ot + 4 * lq + jj, c = 16 * ct + l16;
+            if (o < CO) out[((size_t)o * CI + c) * 9 + t] = acc[u][jj];
+        }
+    }
+    if (tid < CO) out[(size_t)CO * CI * 9 + tid] = bsum[0][tid] + bsum[1][tid] + bsum[2][tid] + bsum[3][tid];
+}
+
 // Two-level fixed-order sum of the T tile partials of each entry e: block
 // (x, k) sums tiles [k T / S, (k + 1) T / S) in tile order into mid[k][e],
 // then mid is summed over k in order.
@@ -262,10 +393,149 @@ __global__ void round_bf16_kernel(long long n, const float* __restrict__ x, floa
     if (k < n) y[k] = bf2f(f2bf(x[k]));
 }
 
+// ---------------------------------------------------------------------------
+// The same convolution on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation) for 32 input channels: per 3 x 3 tap, a product of the
+// tap's weights (output channels x 32 input channels) with the input tile
+// (32 input channels x 16 pixels of a row), summed over the 9 taps. The 32
+// input channels of a tap are one k step of the instruction, so an output
+// value is the FP32 sum of 9 k steps of 32 exact bf16 x bf16 products.
+//
+// Operand layout (checked on gfx950): lane l supplies row l % 16 of the
+// first operand and column l % 16 of the second, each as the 8 consecutive
+// k values 8 (l / 16) .. 8 (l / 16) + 7; accumulator value j of lane l is
+// D[4 (l / 16) + j][l % 16]. Here rows are output channels, columns pixels.
+//
+// LDS: the (kMT + 2) x 18 input tile, pixel-major with the 32 channels of a
+// pixel in four 16-byte chunks and a pixel stride of five chunks (so any 8
+// or 16 consecutive pixels of one chunk fall on distinct 16-byte bank
+// groups); the weights as [tap][output channel][32 channels], the same
+// padded stride.
+constexpr int kMT = 16;                      // output rows per block (4 per wave)
+constexpr int kMW = 16;                      // output columns per block
+constexpr int kMHr = kMT + 2, kMHc = kMW + 2;
+constexpr int kMPix = kMHr * kMHc;           // 324 halo pixels
+constexpr int kSlot = 5;                     // 16-byte slots per pixel / per weight row
+
+template <int CO, bool TRANS>
+__global__ void __launch_bounds__(256)
+conv3x3_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ mask, int H,
+                    int W, const float* __restrict__ w, const float* __restrict__ bias, int relu,
+                    uint16_t* __restrict__ yb, double* __restrict__ yd,
+                    const double* __restrict__ add) {
+    constexpr int CI = 32;
+    constexpr int COP = (CO + 15) & ~15;     // output channels padded to MFMA rows
+    constexpr int OT = COP / 16;
+    __shared__ uint4 xs[kMPix * kSlot];
+    __shared__ uint4 ws[9 * COP * kSlot];
+    const int tiles_w = (W + kMW - 1) / kMW;
+    const int th = blockIdx.x / tiles_w, tw = blockIdx.x - th * tiles_w;
+    const int n = blockIdx.y;
+    const int h0 = th * kMT, w0 = tw * kMW;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t plane = (size_t)H * W;
+
+    // Input tile: task e = (chunk, halo pixel); 8 channels gathered per task
+    // (lanes take consecutive pixels, so each load is coalesced).
+    for (int e = tid; e < 4 * kMPix; e += 256) {
+        const int ch = e / kMPix, px = e - ch * kMPix;
+        const int hh = h0 - 1 + px / kMHc, ww = w0 - 1 + px % kMHc;
+        uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
+            const size_t base = ((size_t)n * CI + 8 * ch) * plane + (size_t)hh * W + ww;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                uint16_t b = x[base + u * plane];
+                if (mask && !(bf2f(mask[base + u * plane]) > 0.0f)) b = 0;
+                v[u] = b;
+            }
+        }
+        xs[px * kSlot + ch] = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]),
+                                         pack2(v[6], v[7]));
+    }
+    // Weights: task e = (tap, output channel, chunk); forward W[o][c][i][j],
+    // input gradient W[c][o][2 - i][2 - j] (the layer's weights transposed and
+    // flipped). Values are BF16-representable floats.
+    for (int e = tid; e < 9 * COP * 4; e += 256) {
+        const int ch = e & 3, o = (e >> 2) % COP, t = (e >> 2) / COP;
+        const int i = t / 3, j = t % 3;
+        uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (o < CO) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = 8 * ch + u;
+                const float f = TRANS ? w[((c * CO + o) * 3 + (2 - i)) * 3 + (2 - j)]
+                                      : w[((o * CI + c) * 3 + i) * 3 + j];
+                v[u] = f2bf(f);
+            }
+        }
+        ws[(t * COP + o) * kSlot + ch] = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]),
+                                                    pack2(v[4], v[5]), pack2(v[6], v[7]));
+    }
+    __syncthreads();
+
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int r0 = wave * 4;   // this wave's first output row in the tile
+    float4_t acc[4][OT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int a = 0; a < OT; ++a) acc[r][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int i = t / 3, j = t % 3;
+        bf16x8_t fa[OT];
+#pragma unroll
+        for (int a = 0; a < OT; ++a)
+            fa[a] = __builtin_bit_cast(bf16x8_t, ws[(t * COP + 16 * a + l16) * kSlot + lq]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bf16x8_t fb =
+                __builtin_bit_cast(bf16x8_t, xs[((r0 + r + i) * kMHc + l16 + j) * kSlot + lq]);
+#pragma unroll
+            for (int a = 0; a < OT; ++a)
+                acc[r][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb, acc[r][a], 0, 0, 0);
+        }
+    }
+
+    const int wq = w0 + l16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int h = h0 + r0 + r;
+        if (h >= H || wq >= W) continue;
+#pragma unroll
+        for (int a = 0; a < OT; ++a)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int o = 16 * a + 4 * lq + jj;
+                if (o >= CO) continue;
+                float v = acc[r][a][jj] + (bias ? bias[o] : 0.0f);
+                if (relu) v = fmaxf(v, 0.0f);
+                const size_t idx = ((size_t)n * CO + o) * plane + (size_t)h * W + wq;
+                if (yb) yb[idx] = f2bf(v);
+                else yd[idx] = (add ? add[idx] : 0.0) + (double)v;
+            }
+    }
+}
+
 template <bool TRANS>
 hipError_t conv_dispatch(int N, int Cin, int H, int W, int Cout, const uint16_t* x,
                          const uint16_t* mask, const float* w, const float* b, int relu,
                          uint16_t* yb, double* yd, const double* add, hipStream_t s) {
+    if (Cin == 32) {
+        // 32 input channels: the matrix-core form.
+        const int tiles = ((H + kMT - 1) / kMT) * ((W + kMW - 1) / kMW);
+        dim3 grid(tiles, N);
+        if (Cout == 32)
+            hipLaunchKernelGGL((conv3x3_mfma_kernel<32, TRANS>), grid, dim3(256), 0, s, x, mask,
+                               H, W, w, b, relu, yb, yd, add);
+        else if (Cout == 3)
+            hipLaunchKernelGGL((conv3x3_mfma_kernel<3, TRANS>), grid, dim3(256), 0, s, x, mask,
+                               H, W, w, b, relu, yb, yd, add);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     const int tiles = ((H + kCT - 1) / kCT) * ((W + kCT - 1) / kCT);
     dim3 grid(tiles, N);
     switch (Cout) {
@@ -312,7 +582,13 @@ hipError_t cnn_conv3x3_grad_weight(int N, int Cin, int H, int W, int Cout, const
                                    float* dw, float* db, hipStream_t s) {
     const int tiles = ((H + kCT - 1) / kCT) * ((W + kCT - 1) / kCT);
     dim3 grid(tiles, N);
-    switch (Cout) {
+    if (Cin == 32 && Cout == 32)
+        hipLaunchKernelGGL(conv3x3_wgrad_mfma_kernel<32>, grid, dim3(256), 0, s, x, H, W, g, gmask,
+                           partial);
+    else if (Cin == 32 && Cout == 3)
+        hipLaunchKernelGGL(conv3x3_wgrad_mfma_kernel<3>, grid, dim3(256), 0, s, x, H, W, g, gmask,
+                           partial);
+    else switch (Cout) {
         case 32:
             hipLaunchKernelGGL(conv3x3_wgrad_kernel<32>, grid, dim3(kCThreads), 0, s, x, Cin, H, W,
                                g, gmask, partial);
