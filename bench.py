@@ -493,6 +493,121 @@ def ragged_batch_forms(mek, workloads, torch, nb=64, budget=10_000):
     return out
 
 
+def ragged_tol_forms(mek, workloads, torch, nb=64, tol=1e-4, cap=100_000):
+    """The uneven-instance form by its time-to-tolerance protocol: the same 64
+    instances (data seed 5), FP32 iterations (FP64 norms, step, stop test),
+    ME-GRBK to ||X - X_ref|| <= tol ||X_ref|| with X_ref = A^+ C B^+ (the
+    oracle's pseudoinverses; != X* where m < p or n < q), per-instance cap
+    `cap` updates. The measured set is the instances that reach the
+    tolerance within the cap in a first ragged launch of all 64 (the plain
+    form follows the same Philox trajectories). On that set: (1) plain, each
+    instance alone (mek_solve, no residual refreshes: the arithmetic of a
+    ragged launch); (2) one ragged launch with the library's default team
+    sizes; (3) the same with team sizes from the autotuner (per-shape
+    measured update times, the slowest instance's predicted time
+    minimised), the stream-ordered call captured in a graph and replayed.
+    Per instance: sizes, kappa(A) kappa(B), updates."""
+    import oracle
+    from paper_2408_05444_amd import autotune
+    insts = workloads.ragged_batch(nb, seed=5)
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    per, Xr = [], []
+    for i in insts:
+        xr = oracle.least_norm(i.A, i.C, i.B)
+        Xr.append(t(xr))
+        sa = np.linalg.svd(i.A, compute_uv=False)
+        sb = np.linalg.svd(i.B, compute_uv=False)
+        per.append({"m": i.A.shape[0], "p": i.A.shape[1], "q": i.B.shape[0], "n": i.B.shape[1],
+                    "kappa": float(sa[0] / sa[-1] * sb[0] / sb[-1])})
+    dv = [(t(i.A), t(i.B), t(i.C)) for i in insts]
+    kw = dict(variant="grbk", stop="rel_err", tol=tol, max_iters=cap, seed=2408054440)
+    plans = [mek.mek_plan_create(A, B, precision="fp32") for A, B, _ in dv]
+    _, first = mek.mek_solve_multi(plans, [c for _, _, c in dv], X_ref=Xr, **kw)
+    for P in plans:
+        mek.mek_plan_destroy(P)
+    S = [b for b in range(nb) if first[b].status == 0]
+    for b in range(nb):
+        per[b]["iters_first_launch"] = first[b].iters
+    # On the set, instance j (= S[j]) draws under Philox key (seed, j) in
+    # every form, so the forms follow the same trajectories; the cap is
+    # doubled so that a changed key does not drop an instance from the set.
+    kw = dict(kw, max_iters=2 * cap)
+    plain_t = []
+    for j, b in enumerate(S):
+        A, B, C = dv[b]
+        plan = mek.mek_plan_create(A, B, precision="fp32")
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        r = mek.mek_solve(plan, C, X_ref=Xr[b], instance=j, refresh_period=-1, **kw)
+        torch.cuda.synchronize()
+        plain_t.append(time.perf_counter() - ts)
+        mek.mek_plan_destroy(plan)
+        per[b].update({"iters_plain": r.iters, "status_plain": r.status})
+    out = {"instances": nb, "tol": tol, "cap": cap, "precision": "fp32",
+           "measured_set": len(S), "per_instance": per,
+           "plain": {"time_s": float(sum(plain_t)),
+                     "updates": int(sum(per[b]["iters_plain"] for b in S)),
+                     "all_reached_tol": all(per[b]["status_plain"] == 0 for b in S)}}
+    out["plain"]["iters_per_s"] = out["plain"]["updates"] / out["plain"]["time_s"]
+
+    def ragged(plans, label):
+        Cs, Xs_ = [dv[b][2] for b in S], [Xr[b] for b in S]
+        kwm = dict(kw)
+        kwm["X_ref"] = Xs_
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, res = mek.mek_solve_multi(plans, Cs, **kwm)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - ts
+        upd = int(sum(r.iters for r in res))
+        out[label] = {"time_s": te, "updates": upd, "iters_per_s": upd / te,
+                      "all_reached_tol": all(r.status == 0 for r in res),
+                      "teams": [r.team_wgs for r in res], "kernel_ms": res[0].kernel_ms}
+        return res
+
+    plans = [mek.mek_plan_create(dv[b][0], dv[b][1], precision="fp32") for b in S]
+    ragged(plans, "batched_default_teams")
+    for P in plans:
+        mek.mek_plan_destroy(P)
+    ts = time.perf_counter()
+    table = autotune.Table()
+    times = autotune.tune([dv[b] for b in S], "fp32", table, cus)
+    teams = autotune.allocate(times, [per[b]["iters_plain"] for b in S], cus)
+    out["autotuned_teams"] = teams
+    out["autotune"] = {"time_s": time.perf_counter() - ts, "table": table.path,
+                       "shapes_in_table": len(table.data)}
+    plans = autotune.plans_for([dv[b] for b in S], "fp32", teams)
+    ragged(plans, "batched_autotuned")
+    # The autotuned launch captured in a graph and replayed.
+    Cs, Xs_ = [dv[b][2] for b in S], [Xr[b] for b in S]
+    kwa = dict(kw)
+    kwa["X_ref"] = Xs_
+    Xg, repg = mek.mek_solve_multi_async(plans, Cs, **kwa)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        mek.mek_solve_multi_async(plans, Cs, X_out=Xg, reports=repg, **kwa)
+    reps = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - ts)
+    rd = [mek.read_device_report(repg[j]) for j in range(len(S))]
+    upd = int(sum(d["iters"] for d in rd))
+    tg = float(np.median(reps))
+    out["batched_autotuned_graph"] = {"time_s": tg, "updates": upd, "iters_per_s": upd / tg,
+                                      "all_reached_tol": all(d["status"] == 0 for d in rd),
+                                      "replays": 3}
+    for P in plans:
+        mek.mek_plan_destroy(P)
+    out["speedup_graph_vs_plain"] = out["plain"]["time_s"] / tg
+    return out
+
+
 def warm_start_forms(mek, workloads, torch, n_train=1024, n_test=512, epochs=20, lr=2e-3,
                      size=256, tau=1e-3):
     """The learned warm start: 3-channel 256 x 256 blurred images (sigma
@@ -735,7 +850,9 @@ def main():
               flush=True)
         return
     if args.ragged_only:
-        print(json.dumps({"ragged64_fp32": ragged_batch_forms(mek, workloads, torch)}), flush=True)
+        print(json.dumps({"ragged64_fp32": ragged_batch_forms(mek, workloads, torch),
+                          "ragged64_fp32_to_tol": ragged_tol_forms(mek, workloads, torch)}),
+              flush=True)
         return
     if args.gemm_only:
         print(json.dumps({"gemm_mfma_f64": gemm_forms(mek, torch, A, B, Xs, C,
@@ -831,6 +948,7 @@ def main():
                 ("paper_tables", lambda: paper_table_forms(mek, workloads, torch)),
                 ("paper_images", lambda: paper_image_forms(mek, workloads, torch)),
                 ("ragged64_fp32", lambda: ragged_batch_forms(mek, workloads, torch)),
+                ("ragged64_fp32_to_tol", lambda: ragged_tol_forms(mek, workloads, torch)),
                 ("warm_start", lambda: warm_start_forms(mek, workloads, torch))]:
             t0 = time.perf_counter()
             forms[name] = fn()

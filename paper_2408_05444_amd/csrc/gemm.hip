@@ -88,38 +88,43 @@ gemm_f64_tile_kernel(int M, int N, int K, double alpha, const double* __restrict
         const long long c = min(tile_j + bj0 + s * BCS, N - 1);
         return B + (long long)k * b_k + c * b_j;
     };
-    double ra[LA], rb[LB];
-    auto load = [&](int k0) {
+    // Small tiles (short K steps) keep two register sets, so that the tile
+    // two steps ahead is in flight while the next one is stored to LDS; the
+    // large tiles have the registers for one set only.
+    constexpr bool DEEP = BM * BN <= 64 * 64;
+    constexpr int NS = DEEP ? 2 : 1;
+    double ra[NS][LA], rb[NS][LB];
+    auto load = [&](int k0, double (&xa)[LA], double (&xb)[LB]) {
         if (k0 + kTK <= K) {
 #pragma unroll
-            for (int s = 0; s < LA; ++s) ra[s] = *a_at(s, k0 + ak0 + s * AKS);
+            for (int s = 0; s < LA; ++s) xa[s] = *a_at(s, k0 + ak0 + s * AKS);
 #pragma unroll
-            for (int s = 0; s < LB; ++s) rb[s] = *b_at(s, k0 + bk0 + s * BKS);
+            for (int s = 0; s < LB; ++s) xb[s] = *b_at(s, k0 + bk0 + s * BKS);
         } else {
 #pragma unroll
             for (int s = 0; s < LA; ++s) {
                 const int k = k0 + ak0 + s * AKS;
                 const double v = *a_at(s, min(k, K - 1));
-                ra[s] = k < K ? v : 0.0;
+                xa[s] = k < K ? v : 0.0;
             }
 #pragma unroll
             for (int s = 0; s < LB; ++s) {
                 const int k = k0 + bk0 + s * BKS;
                 const double v = *b_at(s, min(k, K - 1));
-                rb[s] = k < K ? v : 0.0;
+                xb[s] = k < K ? v : 0.0;
             }
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, const double (&xa)[LA], const double (&xb)[LB]) {
 #pragma unroll
         for (int s = 0; s < LA; ++s) {
             const int k = ak0 + s * AKS, i = ai0 + s * ARS;
-            As[buf][k * BM + (i ^ swz(k))] = ra[s];
+            As[buf][k * BM + (i ^ swz(k))] = xa[s];
         }
 #pragma unroll
         for (int s = 0; s < LB; ++s) {
             const int k = bk0 + s * BKS, j = bj0 + s * BCS;
-            Bs[buf][k * BN + (j ^ swz(k))] = rb[s];
+            Bs[buf][k * BN + (j ^ swz(k))] = xb[s];
         }
     };
 
@@ -143,22 +148,24 @@ gemm_f64_tile_kernel(int M, int N, int K, double alpha, const double* __restrict
 
     const int nk = (K + kTK - 1) / kTK;   // K = 0 leaves acc at zero
     if (nk > 0) {
-        load(0);
-        store(0);
+        load(0, ra[0], rb[0]);
+        store(0, ra[0], rb[0]);
     }
-    if (nk > 1) load(kTK);
-    for (int t = 0; t < nk; ++t) {
+    if (nk > 1) load(kTK, ra[NS - 1], rb[NS - 1]);
+    if (DEEP && nk > 2) load(2 * kTK, ra[0], rb[0]);
+    // Step t: tile t multiplies from buffer t & 1; after its first MFMA
+    // steps tile t + 1 (register set (t + 1) % NS) goes to the other buffer
+    // and that set fetches tile t + 1 + NS.
+    auto step = [&](int t, double (&xa)[LA], double (&xb)[LB]) {
         const int cur = t & 1;
         __syncthreads();   // tile t is in buffer cur; nobody reads cur ^ 1 any more
         frag(cur, 0, 0);
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
             if (q + 1 < KS) frag(cur, 4 * (q + 1), (q + 1) & 1);
-            // Hand the next tile to LDS and fetch the one after while the
-            // MFMAs of the first steps run.
             if (q == 1 && t + 1 < nk) {
-                store(cur ^ 1);
-                if (t + 2 < nk) load((t + 2) * kTK);
+                store(cur ^ 1, xa, xb);
+                if (t + 1 + NS < nk) load((t + 1 + NS) * kTK, xa, xb);
             }
 #pragma unroll
             for (int x = 0; x < TM; ++x)
@@ -167,6 +174,14 @@ gemm_f64_tile_kernel(int M, int N, int K, double alpha, const double* __restrict
                     acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[q & 1][x], fb[q & 1][y],
                                                                      acc[x][y], 0, 0, 0);
         }
+    };
+    if constexpr (DEEP) {
+        for (int t = 0; t < nk; t += 2) {
+            step(t, ra[NS - 1], rb[NS - 1]);
+            if (t + 1 < nk) step(t + 1, ra[0], rb[0]);
+        }
+    } else {
+        for (int t = 0; t < nk; ++t) step(t, ra[0], rb[0]);
     }
 
     // Epilogue: all loads of C first (clamped into the matrix, so always in

@@ -140,14 +140,16 @@ gemm_bf16s_kernel(int M, int N, int K, double alpha, const float* __restrict__ A
     const float* a_row = A + (long long)min(tile_i + ar, M - 1) * a_i;
     const float* b_col = B + (long long)min(tile_j + br, N - 1) * b_j;
     const int a_slot = chunk_slot(ar, ac), b_slot = chunk_slot(br, bc);
-    float va[8], vb[8];
-    auto load = [&](int k0) {
-        load_chunk<AK>(a_row, 0, a_k, 0, k0 + 8 * ac, K, vec_a != 0, va);
-        load_chunk<!BJ>(b_col, 0, b_k, 0, k0 + 8 * bc, K, vec_b != 0, vb);
+    // Two register sets: the tile two steps ahead is in flight while the
+    // next one is split into LDS.
+    float va[2][8], vb[2][8];
+    auto load = [&](int k0, float (&ra)[8], float (&rb)[8]) {
+        load_chunk<AK>(a_row, 0, a_k, 0, k0 + 8 * ac, K, vec_a != 0, ra);
+        load_chunk<!BJ>(b_col, 0, b_k, 0, k0 + 8 * bc, K, vec_b != 0, rb);
     };
-    auto store = [&](int buf) {
-        store_split<P>(&lds[buf][0], BM, a_slot, va);
-        store_split<P>(&lds[buf][SA], BN, b_slot, vb);
+    auto store = [&](int buf, const float (&ra)[8], const float (&rb)[8]) {
+        store_split<P>(&lds[buf][0], BM, a_slot, ra);
+        store_split<P>(&lds[buf][SA], BN, b_slot, rb);
     };
 
     float4_t acc[TM][TN];
@@ -160,11 +162,15 @@ gemm_bf16s_kernel(int M, int N, int K, double alpha, const float* __restrict__ A
     const int ia = wm * WM, jb = wn * WN;
     const int nk = (K + kKT - 1) / kKT;   // K = 0 leaves acc at zero
     if (nk > 0) {
-        load(0);
-        store(0);
+        load(0, va[0], vb[0]);
+        store(0, va[0], vb[0]);
     }
-    if (nk > 1) load(kKT);
-    for (int t = 0; t < nk; ++t) {
+    if (nk > 1) load(kKT, va[1], vb[1]);
+    if (nk > 2) load(2 * kKT, va[0], vb[0]);
+    // Step t: tile t multiplies from LDS buffer t & 1; tile t + 1 (register
+    // set (t + 1) & 1) is split into the other buffer, and that set then
+    // fetches tile t + 3.
+    auto step = [&](int t, float (&ra)[8], float (&rb)[8]) {
         const int cur = t & 1;
         __syncthreads();   // tile t is in buffer cur; nobody reads cur ^ 1 any more
         bf16x8_t fa[P][TM], fb[P][TN];
@@ -182,8 +188,8 @@ gemm_bf16s_kernel(int M, int N, int K, double alpha, const float* __restrict__ A
             }
         }
         if (t + 1 < nk) {
-            store(cur ^ 1);
-            if (t + 2 < nk) load((t + 2) * kKT);
+            store(cur ^ 1, ra, rb);
+            if (t + 3 < nk) load((t + 3) * kKT, ra, rb);
         }
         // Cross products with u + v < P, highest order (smallest) first.
 #pragma unroll
@@ -196,6 +202,10 @@ gemm_bf16s_kernel(int M, int N, int K, double alpha, const float* __restrict__ A
                     for (int y = 0; y < TN; ++y)
                         acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                             fa[u][x], fb[ord - u][y], acc[x][y], 0, 0, 0);
+    };
+    for (int t = 0; t < nk; t += 2) {
+        step(t, va[1], vb[1]);
+        if (t + 1 < nk) step(t + 1, va[0], vb[0]);
     }
 
     // Epilogue: C loads first (clamped, always in bounds), then guarded

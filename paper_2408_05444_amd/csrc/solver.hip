@@ -206,6 +206,10 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     const size_t v_bytes = ((size_t)max(n, q) * sizeof(T) + 15) & ~(size_t)15;
     T* Rl = reinterpret_cast<T*>(dyn_smem);
     T* vec = reinterpret_cast<T*>(dyn_smem + r_bytes);
+    // The row norms of a team pass through the n-vector staging buffer when
+    // they fit there (it is free between the end of one update and the
+    // selection of the next).
+    const bool stage_norms = (size_t)m * sizeof(double) <= v_bytes;
     double* vl = reinterpret_cast<double*>(dyn_smem + r_bytes + v_bytes);
     double* part = vl + P.xpw;
     const int wslot = dot_parts(P.xpw, n, P.wpw, q, false);
@@ -295,7 +299,27 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         for (int j = 0; j < SR; ++j) aa[j] = (j < scnt) ? asrc[sb + j] : 0.0;
         double Ep = 0.0;
         if (team) {
-            if (!poll_words<double, SR>(r_x + sb, scnt, tag, rr, P.sync, P.poll_sleep)) s_fail = 1;
+            if (stage_norms) {
+                // Word j is polled by thread j mod kThreads (each load of a
+                // wave reads 64 consecutive words), staged in LDS, then
+                // every thread takes its contiguous chunk.
+                double* stage = reinterpret_cast<double*>(vec);
+                for (int j0 = 0; j0 < m; j0 += kThreads * kVecRegs) {
+                    double tv[kVecRegs];
+                    const int cnt = max(0, min(kVecRegs, (m - j0 - tid + kThreads - 1) / kThreads));
+                    if (!poll_strided<double, kVecRegs>(r_x + j0 + tid, kThreads, cnt, tag, tv,
+                                                        P.sync, P.poll_sleep))
+                        s_fail = 1;
+#pragma unroll
+                    for (int u = 0; u < kVecRegs; ++u)
+                        if (u < cnt) stage[j0 + tid + u * kThreads] = tv[u];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < SR; ++j) rr[j] = (j < scnt) ? stage[sb + j] : 0.0;
+            } else if (!poll_words<double, SR>(r_x + sb, scnt, tag, rr, P.sync, P.poll_sleep)) {
+                s_fail = 1;
+            }
             double e1[1];
             if (tid < W && !poll_words<double, 1>(e_x + tid, 1, tag, e1, P.sync, P.poll_sleep)) s_fail = 1;
             if (tid < W) Ep = e1[0];
@@ -491,12 +515,12 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         {
             const unsigned int ntag = seq_tag(k + 1);
             const T* garow = P.GA + (size_t)ik * m + row0;
+            // The norms go to LDS first; after the update's closing barrier
+            // one wave stores all of them (one coalesced store instead of
+            // one single-lane store per row).
             auto publish = [&](int ii, double acc) {
                 acc = wave_sum(acc);
-                if (lane == 0) {
-                    if (team) xstore(&r_x[row0 + ii], pack_word(acc, ntag));
-                    else r_local[ii] = acc;
-                }
+                if (lane == 0) r_local[ii] = acc;
             };
             if (LDS) {
                 for (int ii = wv; ii < nrow; ii += kWaves) {
@@ -553,11 +577,15 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             if (tid == 0) {
                 double e = 0.0;
                 for (int w2 = 0; w2 < kWaves; ++w2) e += s_err[w2];
-                if (team) xstore(&e_x[g], pack_word(e, ntag));
-                else s_err[0] = e;
+                s_err[0] = e;
             }
         }
         __syncthreads();
+        if (team) {
+            const unsigned int ntag = seq_tag(k + 1);
+            if (tid < nrow) xstore(&r_x[row0 + tid], pack_word(r_local[tid], ntag));
+            if (tid == kWave) xstore(&e_x[g], pack_word(s_err[0], ntag));
+        }
         MEK_PHASE(kPhUpdate);
         ++k;
     }
