@@ -413,13 +413,21 @@ int mek_gram(int64_t rows, int64_t cols, const double* M, int transpose_first, d
 
 /* ---- Learned warm start X0 = C + f(C) (not in the paper: an extension of
  * its initial guess X^0). f is a network of 3 x 3 convolutions; these calls
- * are its layers, gradients and optimiser step. Tensors are device arrays in
- * NCHW order; BF16 tensors are uint16_t (the upper half of an IEEE single,
- * rounded to nearest even); weights are float arrays (O, C, 3, 3) holding
- * BF16-rounded values; sums are FP32 (the loss FP64). Channel counts must be
- * 3 or 32, N <= 65535, H, W <= 32768. All calls synchronise `stream`.
- * Errors: MEK_EINVAL for bad sizes or pointers, MEK_EHIP for host or
- * short buffers and launch failures. */
+ * are its layers, gradients and optimiser step. Tensors are device arrays:
+ * with 3 channels in NCHW order (the image-shaped input C, the output, the
+ * loss gradient), with 32 channels in NHWC order (channels innermost: the
+ * hidden activations and their gradients, so that a pixel's 32 channels are
+ * 64 contiguous bytes for the matrix cores); indices below are written
+ * [n,c,h,w] in either case. BF16 tensors are uint16_t (the upper half of an
+ * IEEE single, rounded to nearest even); weights are float arrays
+ * (O, C, 3, 3) holding BF16-rounded values; sums are FP32 (the loss FP64).
+ * Channel counts must be 3 or 32, N <= 65535, H, W <= 32768. The calls are
+ * stream ordered (they return once their kernels are enqueued on `stream`)
+ * except mek_cnn_mse_grad, which returns the loss and so synchronises.
+ * grad_weight and mse_grad share a per-device scratch buffer, and the
+ * convolutions a per-device buffer for their weights: order those calls on
+ * one stream. Errors: MEK_EINVAL for bad sizes or pointers, MEK_EHIP for
+ * host or short buffers and launch failures. */
 
 /* y[n,o,h,w] = b[o] + sum_{c,i,j} w[o,c,i,j] x[n,c,h+i-1,w+j-1] (zero
  * padding 1), then max(., 0) when relu; written to exactly one of y_bf16

@@ -227,6 +227,7 @@ struct Layout {
     bool lds;
     bool a_lds;
     bool x_lds;
+    bool b_lds;
     size_t lds_bytes;
 };
 
@@ -290,6 +291,11 @@ int choose_layout_cap(const mek_plan_s* P, size_t elem, int cap, bool allow_lds,
     if (L->lds_bytes > budget || W > kMaxTeam) return MEK_EUNSUPPORTED;
     // With room left: this work-group's rows of X^T (updated every step),
     // then ||A_i||^2 of all rows.
+    // One work-group with R in LDS: B and B^T first (the dot products then
+    // read no device memory).
+    const size_t bb = 2 * (size_t)q * n * elem;
+    L->b_lds = L->W == 1 && L->lds && L->lds_bytes + bb <= budget;
+    if (L->b_lds) L->lds_bytes += bb;
     const size_t xb = (size_t)L->xpw * P->p * elem;
     L->x_lds = L->lds_bytes + xb <= budget;
     if (L->x_lds) L->lds_bytes += xb;
@@ -332,6 +338,7 @@ int validate_opts(const mek_plan_s* P, const mek_solve_opts* o) {
 template <typename T>
 void fill_common(SolveParams<T>& K, const mek_plan_s* P, const mek_solve_opts* o,
                  const Layout& L, double alpha) {
+    memset(&K, 0, sizeof(K));
     K.m = (int)P->m;
     K.p = (int)P->p;
     K.q = (int)P->q;
@@ -434,6 +441,7 @@ int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double a
     K.phase = phases ? w.phase : nullptr;
     K.a_in_lds = L.a_lds ? 1 : 0;
     K.x_in_lds = L.x_lds ? 1 : 0;
+    K.b_in_lds = L.b_lds ? 1 : 0;
     // Pause between polls of exchange words (tuning knob MEK_POLL_SLEEP).
     static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
     K.poll_sleep = poll_sleep;
@@ -1481,6 +1489,7 @@ int run_multi(int64_t nb, mek_plan_s* const* plans, const std::vector<Layout>& L
         k.phase = nullptr;
         k.a_in_lds = L.a_lds ? 1 : 0;
         k.x_in_lds = L.x_lds ? 1 : 0;
+        k.b_in_lds = L.b_lds ? 1 : 0;
         k.poll_sleep = poll_sleep;
         start[b + 1] = start[b] + L.W;
         lds = std::max(lds, L.lds_bytes);
@@ -2037,6 +2046,7 @@ int enqueue_solve(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, const
     K.phase = nullptr;
     K.a_in_lds = L.a_lds ? 1 : 0;
     K.x_in_lds = L.x_lds ? 1 : 0;
+    K.b_in_lds = L.b_lds ? 1 : 0;
     static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
     K.poll_sleep = poll_sleep;
     MEK_TRY(fill_zero_bytes(w.sync, (long long)sizeof(TeamSync), s));
@@ -2416,6 +2426,20 @@ int cnn_scratch(size_t need, void** out) {
     return MEK_OK;
 }
 
+// The weights of a matrix-core convolution in MFMA order: a per-device
+// buffer made on first use (calls are ordered on their stream, so one
+// buffer serves every call).
+uint16_t* g_cnn_wb[64] = {nullptr};
+
+int cnn_weight_buf(uint16_t** out) {
+    int dev = 0;
+    MEK_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return MEK_EUNSUPPORTED;
+    if (!g_cnn_wb[dev]) MEK_TRY(hipMalloc((void**)&g_cnn_wb[dev], kCnnWeightScratch * 2));
+    *out = g_cnn_wb[dev];
+    return MEK_OK;
+}
+
 bool cnn_dims_ok(int64_t N, int64_t H, int64_t W) {
     return N > 0 && H > 0 && W > 0 && N <= 65535 && H <= (1 << 15) && W <= (1 << 15);
 }
@@ -2436,10 +2460,11 @@ int mek_cnn_conv3x3(int64_t N, int64_t Cin, int64_t H, int64_t W, int64_t Cout, 
         (add_f64 && (st = check_dev(add_f64, outn * 8))))
         return st;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = cnn_conv3x3((int)N, (int)Cin, (int)H, (int)W, (int)Cout, x, nullptr, w, b,
-                               relu ? 1 : 0, y_bf16, y_f64, add_f64, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    return hip_status(e);
+    std::lock_guard<std::mutex> lock(g_cnn_mtx);
+    uint16_t* wb = nullptr;
+    if ((st = cnn_weight_buf(&wb))) return st;
+    return hip_status(cnn_conv3x3((int)N, (int)Cin, (int)H, (int)W, (int)Cout, x, nullptr, w, b,
+                                  relu ? 1 : 0, y_bf16, y_f64, add_f64, wb, s));
 }
 
 int mek_cnn_conv3x3_grad_input(int64_t N, int64_t Cout, int64_t H, int64_t W, int64_t Cin,
@@ -2453,10 +2478,11 @@ int mek_cnn_conv3x3_grad_input(int64_t N, int64_t Cout, int64_t H, int64_t W, in
         (st = check_dev(w, (size_t)(Cout * Cin * 9) * 4)) || (st = check_dev(gx, xn * 2)))
         return st;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = cnn_conv3x3_grad_input((int)N, (int)Cout, (int)H, (int)W, (int)Cin, g, g_gate, w,
-                                          gx, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    return hip_status(e);
+    std::lock_guard<std::mutex> lock(g_cnn_mtx);
+    uint16_t* wb = nullptr;
+    if ((st = cnn_weight_buf(&wb))) return st;
+    return hip_status(cnn_conv3x3_grad_input((int)N, (int)Cout, (int)H, (int)W, (int)Cin, g, g_gate,
+                                             w, gx, wb, s));
 }
 
 int mek_cnn_conv3x3_grad_weight(int64_t N, int64_t Cin, int64_t H, int64_t W, int64_t Cout,
@@ -2476,10 +2502,8 @@ int mek_cnn_conv3x3_grad_weight(int64_t N, int64_t Cin, int64_t H, int64_t W, in
     if ((st = cnn_scratch(cnn_wgrad_partial_floats((int)N, (int)Cin, (int)H, (int)W, (int)Cout) * 4,
                           &part)))
         return st;
-    hipError_t e = cnn_conv3x3_grad_weight((int)N, (int)Cin, (int)H, (int)W, (int)Cout, x, g,
-                                           g_gate, (float*)part, dw, db, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    return hip_status(e);
+    return hip_status(cnn_conv3x3_grad_weight((int)N, (int)Cin, (int)H, (int)W, (int)Cout, x, g,
+                                              g_gate, (float*)part, dw, db, s));
 }
 
 int mek_cnn_mse_grad(int64_t len, const double* y, const double* label, uint16_t* g, double* loss,
@@ -2519,7 +2543,6 @@ int mek_cnn_adam(int64_t n, float* w, float* wq, const float* g, float* m, float
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = cnn_adam(n, w, wq, g, m, v, (float)lr, (float)beta1, (float)beta2, (float)eps,
                             (int)std::min<int64_t>(t, INT32_MAX), s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     return hip_status(e);
 }
 
@@ -2529,7 +2552,6 @@ int mek_cnn_to_bf16(int64_t n, const double* x, double scale, uint16_t* y, void*
     if ((st = check_dev(x, (size_t)n * 8)) || (st = check_dev(y, (size_t)n * 2))) return st;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = cnn_to_bf16(n, x, scale, y, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     return hip_status(e);
 }
 
@@ -2539,7 +2561,6 @@ int mek_cnn_round_bf16(int64_t n, const float* x, float* y, void* stream) {
     if ((st = check_dev(x, (size_t)n * 4)) || (st = check_dev(y, (size_t)n * 4))) return st;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = cnn_round_bf16(n, x, y, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     return hip_status(e);
 }
 

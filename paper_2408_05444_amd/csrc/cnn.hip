@@ -9,7 +9,11 @@
 //
 // Storage: activations and their gradients in BF16 (round to nearest even),
 // weights as FP32 holding BF16-rounded values (the optimiser keeps FP32
-// master copies), every sum in FP32 (the loss in FP64). Layout NCHW.
+// master copies), every sum in FP32 (the loss in FP64). Layout: tensors with
+// 3 channels (the image-shaped input, output and loss gradient) NCHW;
+// tensors with 32 channels (hidden activations and their gradients) NHWC,
+// so that the 32 channels of a pixel are 64 contiguous bytes (four 16-byte
+// chunks of 8 channels, one MFMA k chunk each).
 #include "internal.h"
 
 #include <math.h>
@@ -24,6 +28,7 @@ constexpr int kHaloPix = kHalo * kHalo;  // 324
 constexpr int kChanStride = kHaloPix + 1;   // odd: 32 channels hit 32 LDS banks
 constexpr int kCThreads = kCT * kCT;     // one thread per output pixel
 constexpr int kMaxC = 32;                // channels of the network
+constexpr int kGsStride = kCThreads + 1;  // odd: a wave's 32 channels of one pixel on 32 banks
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
@@ -32,6 +37,13 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) {
     return (uint32_t)lo | ((uint32_t)hi << 16);
+}
+
+// Element (n, c, h, w) of a tensor with C channels: NHWC for 32 channels,
+// NCHW otherwise.
+__device__ __forceinline__ size_t tidx(int n, int c, int h, int w, int C, int H, int W) {
+    return C == 32 ? (((size_t)n * H + h) * W + w) * 32 + c
+                   : (((size_t)n * C + c) * H + h) * W + w;
 }
 
 // FP32 -> BF16, round to nearest, ties to even (NaN stays a quiet NaN).
@@ -54,7 +66,7 @@ __device__ __forceinline__ void stage_halo(float* xs, const uint16_t* __restrict
         const int hh = h0 - 1 + r / kHalo, ww = w0 - 1 + r % kHalo;
         float v = 0.0f;
         if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
-            const size_t idx = (((size_t)n * C + c) * H + hh) * W + ww;
+            const size_t idx = tidx(n, c, hh, ww, C, H, W);
             v = bf2f(x[idx]);
             if (mask && !(bf2f(mask[idx]) > 0.0f)) v = 0.0f;
         }
@@ -116,11 +128,30 @@ conv3x3_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ mask
     }
     const int h = h0 + ty, wq = w0 + tx;
     if (h >= H || wq >= W) return;
+    if (CO == 32 && yb) {
+        // NHWC: the pixel's 32 outputs as four 16-byte stores.
+        uint32_t pk[16];
+#pragma unroll
+        for (int o = 0; o < 32; o += 2) {
+            float v0 = acc[o] + (bias ? bias[o] : 0.0f);
+            float v1 = acc[o + 1] + (bias ? bias[o + 1] : 0.0f);
+            if (relu) {
+                v0 = fmaxf(v0, 0.0f);
+                v1 = fmaxf(v1, 0.0f);
+            }
+            pk[o / 2] = pack2(f2bf(v0), f2bf(v1));
+        }
+        uint4* dst = reinterpret_cast<uint4*>(yb + (((size_t)n * H + h) * W + wq) * 32);
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4)
+            dst[c4] = make_uint4(pk[4 * c4], pk[4 * c4 + 1], pk[4 * c4 + 2], pk[4 * c4 + 3]);
+        return;
+    }
 #pragma unroll
     for (int o = 0; o < CO; ++o) {
         float v = acc[o] + (bias ? bias[o] : 0.0f);
         if (relu) v = fmaxf(v, 0.0f);
-        const size_t idx = (((size_t)n * CO + o) * H + h) * W + wq;
+        const size_t idx = tidx(n, o, h, wq, CO, H, W);
         if (yb) yb[idx] = f2bf(v);
         else yd[idx] = (add ? add[idx] : 0.0) + (double)v;
     }
@@ -136,22 +167,25 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
                      float* __restrict__ partial) {
     constexpr int OPER = (CO + 7) / 8;
     __shared__ float xs[kMaxC * kChanStride];
-    __shared__ float gs[CO * kCThreads];
+    __shared__ float gs[CO * kGsStride];
     const int tiles_w = (W + kCT - 1) / kCT;
     const int th = blockIdx.x / tiles_w, tw = blockIdx.x - th * tiles_w;
     const int n = blockIdx.y;
     const int h0 = th * kCT, w0 = tw * kCT;
     stage_halo(xs, x, nullptr, n, Cin, H, W, h0, w0);
     for (int e = threadIdx.x; e < CO * kCThreads; e += kCThreads) {
-        const int o = e / kCThreads, p = e - o * kCThreads;
+        // Channel fastest across lanes for NHWC gradients (coalesced reads),
+        // pixel fastest for NCHW.
+        const int o = CO == 32 ? e % CO : e / kCThreads;
+        const int p = CO == 32 ? e / CO : e - o * kCThreads;
         const int hh = h0 + p / kCT, ww = w0 + p % kCT;
         float v = 0.0f;
         if (hh < H && ww < W) {
-            const size_t idx = (((size_t)n * CO + o) * H + hh) * W + ww;
+            const size_t idx = tidx(n, o, hh, ww, CO, H, W);
             v = bf2f(g[idx]);
             if (gmask && !(bf2f(gmask[idx]) > 0.0f)) v = 0.0f;
         }
-        gs[e] = v;
+        gs[o * kGsStride + p] = v;
     }
     __syncthreads();
     const int c = threadIdx.x % kMaxC, grp = threadIdx.x / kMaxC;
@@ -175,7 +209,7 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
 #pragma unroll
             for (int k = 0; k < OPER; ++k) {
                 const int o = o0 + k;
-                const float gv = o < CO ? gs[o * kCThreads + p] : 0.0f;
+                const float gv = o < CO ? gs[o * kGsStride + p] : 0.0f;
                 bacc[k] += gv;
 #pragma unroll
                 for (int t = 0; t < 9; ++t) acc[k][t] = fmaf(gv, xv[t], acc[k][t]);
@@ -228,7 +262,6 @@ conv3x3_wgrad_mfma_kernel(const uint16_t* __restrict__ x, int H, int W,
     const int n = blockIdx.y;
     const int h0 = th * kCT, w0 = tw * kCT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const size_t plane = (size_t)H * W;
 
     // Gradient tile (gated), zero outside the image and in padded channels;
     // the bias gradient from the same values.
@@ -237,13 +270,13 @@ conv3x3_wgrad_mfma_kernel(const uint16_t* __restrict__ x, int H, int W,
         const int hh = h0 + (chk >> 1), ww0 = w0 + 8 * (chk & 1);
         uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (o < CO && hh < H) {
-            const size_t base = ((size_t)n * CO + o) * plane + (size_t)hh * W;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int ww = ww0 + u;
                 if (ww < W) {
-                    uint16_t b = g[base + ww];
-                    if (gmask && !(bf2f(gmask[base + ww]) > 0.0f)) b = 0;
+                    const size_t idx = tidx(n, o, hh, ww, CO, H, W);
+                    uint16_t b = g[idx];
+                    if (gmask && !(bf2f(gmask[idx]) > 0.0f)) b = 0;
                     v[u] = b;
                 }
             }
@@ -251,18 +284,27 @@ conv3x3_wgrad_mfma_kernel(const uint16_t* __restrict__ x, int H, int W,
         gs[o * kGStride + chk] = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]),
                                             pack2(v[6], v[7]));
     }
-    // Input: each halo element to the shifted copies that hold it.
-    for (int e = tid; e < CI * kHaloPix; e += 256) {
-        const int c = e / kHaloPix, r = e - c * kHaloPix;
+    // Input (NHWC): task e = (halo pixel, 8-channel chunk), one 16-byte load;
+    // each of its 8 values goes to the shifted copies that hold it.
+    for (int e = tid; e < 4 * kHaloPix; e += 256) {
+        const int r = e >> 2, ch = e & 3;
         const int hr = r / kHalo, hc = r % kHalo;
         const int hh = h0 - 1 + hr, ww = w0 - 1 + hc;
-        uint16_t b = 0;
-        if (hh >= 0 && hh < H && ww >= 0 && ww < W) b = x[((size_t)n * CI + c) * plane + (size_t)hh * W + ww];
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (hh >= 0 && hh < H && ww >= 0 && ww < W)
+            v = *reinterpret_cast<const uint4*>(x + (((size_t)n * H + hh) * W + ww) * CI + 8 * ch);
+        const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int col = hc - j;
-            if (col >= 0 && col < 16)
-                xsh[((j * CI + c) * kXStride + 2 * hr + (col >> 3)) * 8 + (col & 7)] = b;
+            if (col >= 0 && col < 16) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = 8 * ch + u;
+                    xsh[((j * CI + c) * kXStride + 2 * hr + (col >> 3)) * 8 + (col & 7)] =
+                        (uint16_t)((u & 1) ? (vv[u >> 1] >> 16) : (vv[u >> 1] & 0xffff));
+                }
+            }
         }
     }
     __syncthreads();
@@ -417,11 +459,31 @@ constexpr int kMHr = kMT + 2, kMHc = kMW + 2;
 constexpr int kMPix = kMHr * kMHc;           // 324 halo pixels
 constexpr int kSlot = 5;                     // 16-byte slots per pixel / per weight row
 
+// The weights of a matrix-core convolution in MFMA order, BF16:
+// wb[(t * COP + o) * 32 + c] = W[o][c][i][j] (forward) or W[c][o][2-i][2-j]
+// (input gradient), t = 3 i + j, zero for padded output channels o >= CO.
+template <int CO, bool TRANS>
+__global__ void prep_weights_kernel(const float* __restrict__ w, uint16_t* __restrict__ wb) {
+    constexpr int CI = 32;
+    constexpr int COP = (CO + 15) & ~15;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 9 * COP * CI) return;
+    const int c = e % CI, o = (e / CI) % COP, t = e / (CI * COP);
+    const int i = t / 3, j = t % 3;
+    float f = 0.0f;
+    if (o < CO)
+        f = TRANS ? w[((c * CO + o) * 3 + (2 - i)) * 3 + (2 - j)] : w[((o * CI + c) * 3 + i) * 3 + j];
+    wb[e] = f2bf(f);
+}
+
+// Input x: 32 channels, NHWC. mask (input gradient): the ReLU output of the
+// layer whose gradient x is, same layout; entries whose mask is not > 0 read
+// as zero. Output: NHWC BF16 for 32 channels, NCHW (BF16 or FP64 + add) for 3.
 template <int CO, bool TRANS>
 __global__ void __launch_bounds__(256)
 conv3x3_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ mask, int H,
-                    int W, const float* __restrict__ w, const float* __restrict__ bias, int relu,
-                    uint16_t* __restrict__ yb, double* __restrict__ yd,
+                    int W, const uint16_t* __restrict__ wb, const float* __restrict__ bias,
+                    int relu, uint16_t* __restrict__ yb, double* __restrict__ yd,
                     const double* __restrict__ add) {
     constexpr int CI = 32;
     constexpr int COP = (CO + 15) & ~15;     // output channels padded to MFMA rows
@@ -433,45 +495,34 @@ conv3x3_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__
     const int n = blockIdx.y;
     const int h0 = th * kMT, w0 = tw * kMW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const size_t plane = (size_t)H * W;
 
-    // Input tile: task e = (chunk, halo pixel); 8 channels gathered per task
-    // (lanes take consecutive pixels, so each load is coalesced).
+    // Input tile: task e = (halo pixel, chunk of 8 channels), one 16-byte
+    // load each (four lanes cover a pixel's 64 bytes).
     for (int e = tid; e < 4 * kMPix; e += 256) {
-        const int ch = e / kMPix, px = e - ch * kMPix;
+        const int px = e >> 2, ch = e & 3;
         const int hh = h0 - 1 + px / kMHc, ww = w0 - 1 + px % kMHc;
-        uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
-            const size_t base = ((size_t)n * CI + 8 * ch) * plane + (size_t)hh * W + ww;
+            const size_t off = (((size_t)n * H + hh) * W + ww) * CI + 8 * ch;
+            v = *reinterpret_cast<const uint4*>(x + off);
+            if (mask) {
+                const uint4 mk = *reinterpret_cast<const uint4*>(mask + off);
+                uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+                const uint32_t mm[4] = {mk.x, mk.y, mk.z, mk.w};
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                uint16_t b = x[base + u * plane];
-                if (mask && !(bf2f(mask[base + u * plane]) > 0.0f)) b = 0;
-                v[u] = b;
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t lo = (bf2f(mm[u] & 0xffff) > 0.0f) ? 0x0000ffffu : 0u;
+                    const uint32_t hi = (bf2f(mm[u] >> 16) > 0.0f) ? 0xffff0000u : 0u;
+                    vv[u] &= (lo | hi);
+                }
+                v = make_uint4(vv[0], vv[1], vv[2], vv[3]);
             }
         }
-        xs[px * kSlot + ch] = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]),
-                                         pack2(v[6], v[7]));
+        xs[px * kSlot + ch] = v;
     }
-    // Weights: task e = (tap, output channel, chunk); forward W[o][c][i][j],
-    // input gradient W[c][o][2 - i][2 - j] (the layer's weights transposed and
-    // flipped). Values are BF16-representable floats.
-    for (int e = tid; e < 9 * COP * 4; e += 256) {
-        const int ch = e & 3, o = (e >> 2) % COP, t = (e >> 2) / COP;
-        const int i = t / 3, j = t % 3;
-        uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (o < CO) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int c = 8 * ch + u;
-                const float f = TRANS ? w[((c * CO + o) * 3 + (2 - i)) * 3 + (2 - j)]
-                                      : w[((o * CI + c) * 3 + i) * 3 + j];
-                v[u] = f2bf(f);
-            }
-        }
-        ws[(t * COP + o) * kSlot + ch] = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]),
-                                                    pack2(v[4], v[5]), pack2(v[6], v[7]));
-    }
+    // Weights, already in MFMA order: one 16-byte load per slot.
+    for (int e = tid; e < 9 * COP * 4; e += 256)
+        ws[(e >> 2) * kSlot + (e & 3)] = *reinterpret_cast<const uint4*>(wb + 8 * e);
     __syncthreads();
 
     const int l16 = lane & 15, lq = lane >> 4;
@@ -498,42 +549,63 @@ conv3x3_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__
         }
     }
 
+    // Lane (l16, lq) holds output channels 16 a + 4 lq + jj of pixel l16.
     const int wq = w0 + l16;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int h = h0 + r0 + r;
         if (h >= H || wq >= W) continue;
 #pragma unroll
-        for (int a = 0; a < OT; ++a)
+        for (int a = 0; a < OT; ++a) {
+            float v[4];
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 const int o = 16 * a + 4 * lq + jj;
-                if (o >= CO) continue;
-                float v = acc[r][a][jj] + (bias ? bias[o] : 0.0f);
-                if (relu) v = fmaxf(v, 0.0f);
-                const size_t idx = ((size_t)n * CO + o) * plane + (size_t)h * W + wq;
-                if (yb) yb[idx] = f2bf(v);
-                else yd[idx] = (add ? add[idx] : 0.0) + (double)v;
+                v[jj] = acc[r][a][jj] + ((bias && o < CO) ? bias[o] : 0.0f);
+                if (relu) v[jj] = fmaxf(v[jj], 0.0f);
             }
+            if (CO == 32) {
+                // Four consecutive channels of one pixel: one 8-byte store.
+                const size_t off = (((size_t)n * H + h) * W + wq) * 32 + 16 * a + 4 * lq;
+                *reinterpret_cast<uint2*>(yb + off) =
+                    make_uint2(pack2(f2bf(v[0]), f2bf(v[1])), pack2(f2bf(v[2]), f2bf(v[3])));
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int o = 16 * a + 4 * lq + jj;
+                    if (o >= CO) continue;
+                    const size_t idx = (((size_t)n * CO + o) * H + h) * W + wq;
+                    if (yb) yb[idx] = f2bf(v[jj]);
+                    else yd[idx] = (add ? add[idx] : 0.0) + (double)v[jj];
+                }
+            }
+        }
     }
 }
 
 template <bool TRANS>
 hipError_t conv_dispatch(int N, int Cin, int H, int W, int Cout, const uint16_t* x,
                          const uint16_t* mask, const float* w, const float* b, int relu,
-                         uint16_t* yb, double* yd, const double* add, hipStream_t s) {
+                         uint16_t* yb, double* yd, const double* add, uint16_t* wb,
+                         hipStream_t s) {
     if (Cin == 32) {
-        // 32 input channels: the matrix-core form.
+        // 32 input channels: the matrix-core form, weights put in MFMA order
+        // first.
         const int tiles = ((H + kMT - 1) / kMT) * ((W + kMW - 1) / kMW);
         dim3 grid(tiles, N);
-        if (Cout == 32)
+        if (Cout == 32) {
+            hipLaunchKernelGGL((prep_weights_kernel<32, TRANS>), dim3((9 * 32 * 32 + 255) / 256),
+                               dim3(256), 0, s, w, wb);
             hipLaunchKernelGGL((conv3x3_mfma_kernel<32, TRANS>), grid, dim3(256), 0, s, x, mask,
-                               H, W, w, b, relu, yb, yd, add);
-        else if (Cout == 3)
+                               H, W, wb, b, relu, yb, yd, add);
+        } else if (Cout == 3) {
+            hipLaunchKernelGGL((prep_weights_kernel<3, TRANS>), dim3((9 * 16 * 32 + 255) / 256),
+                               dim3(256), 0, s, w, wb);
             hipLaunchKernelGGL((conv3x3_mfma_kernel<3, TRANS>), grid, dim3(256), 0, s, x, mask,
-                               H, W, w, b, relu, yb, yd, add);
-        else
+                               H, W, wb, b, relu, yb, yd, add);
+        } else {
             return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     }
     const int tiles = ((H + kCT - 1) / kCT) * ((W + kCT - 1) / kCT);
@@ -565,16 +637,16 @@ size_t cnn_wgrad_partial_floats(int N, int Cin, int H, int W, int Cout) {
 
 hipError_t cnn_conv3x3(int N, int Cin, int H, int W, int Cout, const uint16_t* x,
                        const uint16_t* mask, const float* w, const float* b, int relu,
-                       uint16_t* yb, double* yd, const double* add, hipStream_t s) {
-    return conv_dispatch<false>(N, Cin, H, W, Cout, x, mask, w, b, relu, yb, yd, add, s);
+                       uint16_t* yb, double* yd, const double* add, uint16_t* wb, hipStream_t s) {
+    return conv_dispatch<false>(N, Cin, H, W, Cout, x, mask, w, b, relu, yb, yd, add, wb, s);
 }
 
 hipError_t cnn_conv3x3_grad_input(int N, int Cout, int H, int W, int Cin, const uint16_t* g,
                                   const uint16_t* gmask, const float* w, uint16_t* gx,
-                                  hipStream_t s) {
+                                  uint16_t* wb, hipStream_t s) {
     // A convolution over g (Cout channels) producing Cin channels.
     return conv_dispatch<true>(N, Cout, H, W, Cin, g, gmask, w, nullptr, 0, gx, nullptr, nullptr,
-                               s);
+                               wb, s);
 }
 
 hipError_t cnn_conv3x3_grad_weight(int N, int Cin, int H, int W, int Cout, const uint16_t* x,

@@ -99,6 +99,7 @@ struct SolveParams {
     unsigned long long* phase;   // optional: per-phase wall-clock ticks (3 timed work-groups)
     int a_in_lds;                // keep ||A_i||^2 for all rows in LDS
     int x_in_lds;                // keep this work-group's rows of X^T in LDS
+    int b_in_lds;                // keep B and B^T in LDS (one-work-group teams)
     int poll_sleep;              // s_sleep length between polls of exchange words
     // Batch: with slots set, nb teams of W work-groups, team b on instance
     // slots[b].id, whose R, X^T, X_ref^T, r, rowbuf, vbuf, wbuf, errpart,
@@ -292,12 +293,15 @@ hipError_t gemm_f64_batched(int nb, int M, int N, int K, double alpha, const dou
 // channel counts 3 or 32.
 bool cnn_channels_ok(int64_t c);
 size_t cnn_wgrad_partial_floats(int N, int Cin, int H, int W, int Cout);
+// wb: device scratch of kCnnWeightScratch uint16 for the weights in MFMA
+// order (used when the convolution's input has 32 channels).
+constexpr int kCnnWeightScratch = 9 * 32 * 32;
 hipError_t cnn_conv3x3(int N, int Cin, int H, int W, int Cout, const uint16_t* x,
                        const uint16_t* mask, const float* w, const float* b, int relu,
-                       uint16_t* yb, double* yd, const double* add, hipStream_t s);
+                       uint16_t* yb, double* yd, const double* add, uint16_t* wb, hipStream_t s);
 hipError_t cnn_conv3x3_grad_input(int N, int Cout, int H, int W, int Cin, const uint16_t* g,
                                   const uint16_t* gmask, const float* w, uint16_t* gx,
-                                  hipStream_t s);
+                                  uint16_t* wb, hipStream_t s);
 hipError_t cnn_conv3x3_grad_weight(int N, int Cin, int H, int W, int Cout, const uint16_t* x,
                                    const uint16_t* g, const uint16_t* gmask, float* partial,
                                    float* dw, float* db, hipStream_t s);

@@ -206,10 +206,6 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     const size_t v_bytes = ((size_t)max(n, q) * sizeof(T) + 15) & ~(size_t)15;
     T* Rl = reinterpret_cast<T*>(dyn_smem);
     T* vec = reinterpret_cast<T*>(dyn_smem + r_bytes);
-    // The row norms of a team pass through the n-vector staging buffer when
-    // they fit there (it is free between the end of one update and the
-    // selection of the next).
-    const bool stage_norms = (size_t)m * sizeof(double) <= v_bytes;
     double* vl = reinterpret_cast<double*>(dyn_smem + r_bytes + v_bytes);
     double* part = vl + P.xpw;
     const int wslot = dot_parts(P.xpw, n, P.wpw, q, false);
@@ -217,6 +213,13 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     double* u_tab = r_local + P.rpw;
     double* a_lds = u_tab + kUTable;
     T* Xl = P.x_in_lds ? reinterpret_cast<T*>(a_lds + (P.a_in_lds ? m : 0)) : nullptr;
+    // B and B^T (the rows of the two dot-product phases) in LDS, after X^T.
+    T* Bl = P.b_in_lds ? reinterpret_cast<T*>(a_lds + (P.a_in_lds ? m : 0)) +
+                             (P.x_in_lds ? (size_t)P.xpw * p : 0)
+                       : nullptr;
+    T* BTl = Bl ? Bl + (size_t)q * n : nullptr;
+    const T* Bsrc = Bl ? Bl : P.B;
+    const T* BTsrc = BTl ? BTl : P.BT;
     T* Rown = LDS ? Rl : P.R + (size_t)row0 * n;
     if (P.a_in_lds)
         for (int i = tid; i < m; i += kThreads) a_lds[i] = P.a[i];
@@ -232,6 +235,13 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         const T* src = P.Xt + (size_t)xc0 * p;
         const size_t tot = (size_t)nx * p;
         for (size_t e = tid; e < tot; e += kThreads) Xl[e] = src[e];
+    }
+    if (Bl) {
+        const size_t tot = (size_t)q * n;
+        for (size_t e = tid; e < tot; e += kThreads) {
+            Bl[e] = P.B[e];
+            BTl[e] = P.BT[e];
+        }
     }
     __syncthreads();
     for (int ii = wv; ii < nrow; ii += kWaves) {
@@ -299,27 +309,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         for (int j = 0; j < SR; ++j) aa[j] = (j < scnt) ? asrc[sb + j] : 0.0;
         double Ep = 0.0;
         if (team) {
-            if (stage_norms) {
-                // Word j is polled by thread j mod kThreads (each load of a
-                // wave reads 64 consecutive words), staged in LDS, then
-                // every thread takes its contiguous chunk.
-                double* stage = reinterpret_cast<double*>(vec);
-                for (int j0 = 0; j0 < m; j0 += kThreads * kVecRegs) {
-                    double tv[kVecRegs];
-                    const int cnt = max(0, min(kVecRegs, (m - j0 - tid + kThreads - 1) / kThreads));
-                    if (!poll_strided<double, kVecRegs>(r_x + j0 + tid, kThreads, cnt, tag, tv,
-                                                        P.sync, P.poll_sleep))
-                        s_fail = 1;
-#pragma unroll
-                    for (int u = 0; u < kVecRegs; ++u)
-                        if (u < cnt) stage[j0 + tid + u * kThreads] = tv[u];
-                }
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < SR; ++j) rr[j] = (j < scnt) ? stage[sb + j] : 0.0;
-            } else if (!poll_words<double, SR>(r_x + sb, scnt, tag, rr, P.sync, P.poll_sleep)) {
-                s_fail = 1;
-            }
+            if (!poll_words<double, SR>(r_x + sb, scnt, tag, rr, P.sync, P.poll_sleep)) s_fail = 1;
             double e1[1];
             if (tid < W && !poll_words<double, 1>(e_x + tid, 1, tag, e1, P.sync, P.poll_sleep)) s_fail = 1;
             if (tid < W) Ep = e1[0];
@@ -392,7 +382,10 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             xref_r[u] = (ref_regs && wv < nx && s2 < p) ? P.Xref_t[(size_t)(xc0 + wv) * p + s2] : 0.0;
         }
         // (A A^T)_{i_k, i} of the first row i each wave updates, likewise.
-        const T ga_pre = (wv < nrow) ? P.GA[(size_t)ik * m + row0 + wv] : (T)0;
+        // (A A^T)_{i_k, i} of the rows this wave updates (row wv + 8 u in
+        // lane u), likewise.
+        const int ga_row = wv + kWaves * lane;
+        const T ga_lane = (ga_row < nrow) ? P.GA[(size_t)ik * m + row0 + ga_row] : (T)0;
         MEK_PHASE(kPhSelect);
 
         // ---- 2. The selected row: its owner publishes it, the others poll
@@ -424,7 +417,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         // v = R_{i_k} B^T: this work-group's entries (rows xc0.. of B), into
         // LDS and, in a team, published for the others.
         xword* const v_x = reinterpret_cast<xword*>(P.vbuf);
-        block_dots<T>(rowsrc, n, nx, [&](int d) { return P.B + (size_t)(xc0 + d) * n; },
+        block_dots<T>(rowsrc, n, nx, [&](int d) { return Bsrc + (size_t)(xc0 + d) * n; },
                       [&](int d, double val) {
                           vl[d] = val;
                           if (team) xstore(&v_x[xc0 + d], pack_word((T)val, tag));
@@ -487,7 +480,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             vfull = vec;
         }
         // w = v B for this work-group's entries (rows wc0.. of B^T).
-        block_dots<T>(vfull, q, nw, [&](int d) { return P.BT + (size_t)(wc0 + d) * q; },
+        block_dots<T>(vfull, q, nw, [&](int d) { return BTsrc + (size_t)(wc0 + d) * q; },
                       [&](int d, double val) {
                           if (team) xstore(&w_x[wc0 + d], pack_word((T)val, tag));
                           else part[wslot + d] = val;
@@ -515,16 +508,22 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         {
             const unsigned int ntag = seq_tag(k + 1);
             const T* garow = P.GA + (size_t)ik * m + row0;
-            // The norms go to LDS first; after the update's closing barrier
-            // one wave stores all of them (one coalesced store instead of
-            // one single-lane store per row).
+            // (A A^T)_{i_k, i} of row ii = wv + 8 u: from lane u's register
+            // (ii is the same in the whole wave), past 64 rows from memory.
+            auto ga_of = [&](int ii) -> T {
+                const int u = (ii - wv) / kWaves;
+                return u < kWave ? __shfl(ga_lane, u) : garow[ii];
+            };
             auto publish = [&](int ii, double acc) {
                 acc = wave_sum(acc);
-                if (lane == 0) r_local[ii] = acc;
+                if (lane == 0) {
+                    if (team) xstore(&r_x[row0 + ii], pack_word(acc, ntag));
+                    else r_local[ii] = acc;
+                }
             };
             if (LDS) {
                 for (int ii = wv; ii < nrow; ii += kWaves) {
-                    const T sc_i = (T)(c * (double)(ii == wv ? ga_pre : garow[ii]));
+                    const T sc_i = (T)(c * (double)ga_of(ii));
                     T* rp = Rown + (size_t)ii * n;
                     double acc = 0.0;
                     for (int j = lane; j < n; j += kWave) {
@@ -541,8 +540,9 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
                 for (int ii = wv; ii < nrow; ii += 2 * kWaves) {
                     const int i2 = ii + kWaves;
                     const bool two = i2 < nrow;
-                    const T sa = (T)(c * (double)(ii == wv ? ga_pre : garow[ii]));
-                    const T sb = two ? (T)(c * (double)garow[i2]) : T(0);
+                    const T sa = (T)(c * (double)ga_of(ii));
+                    const T gb = ga_of(two ? i2 : ii);
+                    const T sb = two ? (T)(c * (double)gb) : T(0);
                     T* ra = Rown + (size_t)ii * n;
                     T* rb = Rown + (size_t)(two ? i2 : ii) * n;
                     double acc_a = 0.0, acc_b = 0.0;
@@ -577,15 +577,11 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             if (tid == 0) {
                 double e = 0.0;
                 for (int w2 = 0; w2 < kWaves; ++w2) e += s_err[w2];
-                s_err[0] = e;
+                if (team) xstore(&e_x[g], pack_word(e, ntag));
+                else s_err[0] = e;
             }
         }
         __syncthreads();
-        if (team) {
-            const unsigned int ntag = seq_tag(k + 1);
-            if (tid < nrow) xstore(&r_x[row0 + tid], pack_word(r_local[tid], ntag));
-            if (tid == kWave) xstore(&e_x[g], pack_word(s_err[0], ntag));
-        }
         MEK_PHASE(kPhUpdate);
         ++k;
     }

@@ -79,7 +79,8 @@ class WarmStartNet:
         for li in range(nl):
             ci, co = CHANNELS[li], CHANNELS[li + 1]
             if li < nl - 1:
-                y = torch.empty((N, co, H, W), dtype=torch.int16, device=self.device)
+                # 32-channel activations are channels-last (NHWC).
+                y = torch.empty((N, H, W, co), dtype=torch.int16, device=self.device)
                 _check(lib().mek_cnn_conv3x3(N, ci, H, W, co, _p(acts[-1]), _p(self.wq[li]),
                                              _p(self.bq[li]), 1, _p(y), None, None, _stream()),
                        "mek_cnn_conv3x3")
@@ -111,7 +112,7 @@ class WarmStartNet:
                                                      _p(self.g[li]), _p(self.g[nl + li]),
                                                      _stream()), "mek_cnn_conv3x3_grad_weight")
             if li > 0:
-                gx = torch.empty((N, ci, H, W), dtype=torch.int16, device=self.device)
+                gx = torch.empty((N, H, W, ci), dtype=torch.int16, device=self.device)
                 _check(lib().mek_cnn_conv3x3_grad_input(N, co, H, W, ci, _p(g), _p(gate),
                                                         _p(self.wq[li]), _p(gx), _stream()),
                        "mek_cnn_conv3x3_grad_input")

@@ -32,11 +32,24 @@ def dev(x, dtype=torch.float64):
 
 
 def bits_dev(vals):
+    """BF16 bits of an (N, C, H, W) array on the GPU: NCHW for 3 channels,
+    NHWC for 32 (the library's layout of 32-channel tensors)."""
+    if vals.ndim == 4 and vals.shape[1] == 32:
+        vals = np.ascontiguousarray(vals.transpose(0, 2, 3, 1))
     return torch.from_numpy(workloads.bf16_bits(vals).view(np.int16)).to("cuda")
 
 
-def from_bits(t):
-    return workloads.bf16_values(t.cpu().numpy().view(np.uint16))
+def from_bits(t, channels=None):
+    """Values of a BF16 device tensor, back in (N, C, H, W) order."""
+    v = workloads.bf16_values(t.cpu().numpy().view(np.uint16))
+    if v.ndim == 4 and channels == 32:
+        v = np.ascontiguousarray(v.transpose(0, 3, 1, 2))
+    return v
+
+
+def empty_bf16(N, C, H, W):
+    shape = (N, H, W, C) if C == 32 else (N, C, H, W)
+    return torch.empty(shape, dtype=torch.int16, device="cuda")
 
 
 def p(t):
@@ -68,10 +81,10 @@ def test_conv_forward(cin, cout, relu, bias, out):
     L = mek.lib()
     xd, wd, bd = bits_dev(x), dev(w, torch.float32), dev(b, torch.float32) if bias else None
     if out == "bf16":
-        y = torch.empty((N, cout, H, W), dtype=torch.int16, device="cuda")
+        y = empty_bf16(N, cout, H, W)
         assert L.mek_cnn_conv3x3(N, cin, H, W, cout, p(xd), p(wd), p(bd), relu, p(y), None, None,
                                  None) == 0
-        got = from_bits(y)
+        got = from_bits(y, cout)
         tol = tol + 2.0 ** -8 * np.abs(ref)
     else:
         y = torch.empty((N, cout, H, W), dtype=torch.float64, device="cuda")
@@ -94,10 +107,10 @@ def test_conv_grad_input(cout, cin, gated):
     tol = 288 * U32 * conv.conv3x3_grad_input(np.abs(gg), np.abs(w)) + 2.0 ** -8 * np.abs(ref)
     # Every device tensor stays referenced until the call returns.
     gd, gated_d, wd = bits_dev(g), bits_dev(gate) if gated else None, dev(w, torch.float32)
-    gx = torch.empty((N, cin, H, W), dtype=torch.int16, device="cuda")
+    gx = empty_bf16(N, cin, H, W)
     assert mek.lib().mek_cnn_conv3x3_grad_input(N, cout, H, W, cin, p(gd), p(gated_d), p(wd),
                                                 p(gx), None) == 0
-    assert np.all(np.abs(from_bits(gx) - ref) <= tol + 1e-30)
+    assert np.all(np.abs(from_bits(gx, cin) - ref) <= tol + 1e-30)
 
 
 @pytest.mark.parametrize("cin,cout,gated", [(3, 32, True), (32, 32, True), (32, 3, False)])

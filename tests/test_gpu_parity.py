@@ -222,6 +222,31 @@ def test_multi_workgroup_trajectory(team, lds, variant, theta):
     assert rel(host(res.X), ref.X) <= 1e-9
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant,theta", [("grbk", 0.5), ("rgrbk", 0.8), ("mwrbk", 0.5),
+                                           ("rbk", 0.5), ("bk", 0.5)])
+def test_one_work_group_with_b_in_lds(variant, theta, precision):
+    """A one-work-group team holding R, B and B^T in LDS (the dot products
+    read no device memory) follows the oracle's trajectory."""
+    inst = workloads.small(seed=7)
+    K = 1500
+    alpha = oracle.spectral_alpha(inst.B)
+    ref = oracle.solve(inst.A, inst.B, inst.C, variant=variant, theta=theta, alpha=alpha,
+                       max_iters=K, seed=19, Xref=inst.X_star)
+    plan = mek.mek_plan_create(cuda(inst.A), cuda(inst.B), alpha=alpha, team_wgs=1, r_in_lds=1,
+                               precision=precision)
+    res = mek.mek_solve(plan, cuda(inst.C), variant=variant, theta=theta, alpha=alpha,
+                        max_iters=K, seed=19, hist_cap=K + 1, X_ref=cuda(inst.X_star),
+                        refresh_period=-1)
+    assert res.team_wgs == 1 and res.r_in_lds
+    if precision == "fp64":
+        assert host(res.idx_hist).tolist() == ref.idx.tolist()
+        assert rel(host(res.X), ref.X) <= 1e-9
+    else:
+        assert (host(res.idx_hist)[:100] == ref.idx[:100]).all()
+        assert rel(host(res.X), ref.X) <= 1e-2
+
+
 def test_replay_of_oracle_indices():
     inst = workloads.ragged(seed=12)
     alpha = oracle.spectral_alpha(inst.B)
