@@ -625,6 +625,8 @@ def warm_start_forms(mek, workloads, torch, n_train=1024, n_test=512, epochs=20,
     for i in range(n_train):
         A, B, C, _, _ = workloads.warmstart_image(100000 + i, size=size)
         train.append((t(A), t(B), t(C)))
+        if (i + 1) % 2000 == 0:
+            print(f"[bench] warm start: {i + 1} training images made", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ts = time.perf_counter()
     labels = warmstart.solver_labels(mek, train, tau=tau, seed=2408054440)

@@ -385,6 +385,20 @@ int mek_residual_noalloc(int64_t m, int64_t p, int64_t q, int64_t n, const doubl
                          const double* X, const double* B, const double* C, double* R,
                          void* stream);
 
+/* Communication floor of the team solver (measurement): a cooperative
+ * launch of W work-groups that repeats, `rounds` times, the exchanges and
+ * block collectives of one update of Alg. 3 as the team kernel does them
+ * (all-gather of m row-norm words and W error words, block reductions and
+ * scan, broadcast of one row of n words, all-gather of the q words of
+ * v = R_i B^T and of the n words of w = v B) with no arithmetic and no
+ * operand traffic. *us_per_round (host) = kernel time per round, measured
+ * with HIP events on `stream`: the floor those exchanges put under one
+ * update at that team shape. Blocking. Errors: MEK_EINVAL for W < 1, m < W,
+ * m > 8192, sizes < 1 or rounds < 1; MEK_EUNSUPPORTED for W above the
+ * compute units; MEK_ETIMEOUT if a wait gave up. */
+int mek_exchange_floor(int64_t W, int64_t m, int64_t n, int64_t q, int64_t rounds,
+                       double* us_per_round, void* stream);
+
 /* The FP32 residual engine of the FP32 and mixed iterations (the residual
  * R = C - A X B with which Alg. 3 starts, recomputed from the current
  * iterate so that the incrementally updated FP32 residual does not drift):

@@ -131,6 +131,10 @@ def lib() -> ctypes.CDLL:
         L.mek_residual.restype = ci
         L.mek_residual_batched.argtypes = [i64, i64, i64, i64, i64, vp, vp, vp, vp, vp, vp]
         L.mek_residual_batched.restype = ci
+        L.mek_residual_noalloc.argtypes = [i64, i64, i64, i64, vp, vp, vp, vp, vp, vp]
+        L.mek_residual_noalloc.restype = ci
+        L.mek_exchange_floor.argtypes = [i64, i64, i64, i64, i64, vp, vp]
+        L.mek_exchange_floor.restype = ci
         L.mek_residual_split.argtypes = [ci, i64, i64, i64, i64, i64, vp, vp, vp, vp, vp, vp]
         L.mek_residual_split.restype = ci
         L.mek_gram.argtypes = [i64, i64, vp, ci, vp, vp]
@@ -572,6 +576,15 @@ def mek_residual_split(A, X, B, C, pieces: int = 3) -> torch.Tensor:
                                     _dev(C, shape=(nb, m, n), name="C"),
                                     _dev(R, torch.float32), _stream()), "mek_residual_split")
     return R
+
+
+def mek_exchange_floor(W: int, m: int, n: int, q: int, rounds: int = 20000) -> float:
+    """Microseconds per round of the team solver's exchanges alone (W
+    work-groups, m rows, n columns of R, q columns of X)."""
+    us = ctypes.c_double(0.0)
+    _check(lib().mek_exchange_floor(int(W), int(m), int(n), int(q), int(rounds),
+                                    ctypes.byref(us), _stream()), "mek_exchange_floor")
+    return us.value
 
 
 def mek_gram(M: torch.Tensor, transpose_first: bool) -> torch.Tensor:

@@ -15,7 +15,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmek.so")
-SOURCES = ["solver.hip", "sparse.hip", "block2.hip", "gemm.hip", "gemm_bf16.hip", "util.hip", "cnn.hip", "api.cpp"]
+SOURCES = ["solver.hip", "sparse.hip", "block2.hip", "gemm.hip", "gemm_bf16.hip", "probe.hip", "util.hip", "cnn.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

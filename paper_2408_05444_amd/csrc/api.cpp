@@ -2343,6 +2343,44 @@ int mek_residual_noalloc(int64_t m, int64_t p, int64_t q, int64_t n, const doubl
     return MEK_OK;
 }
 
+int mek_exchange_floor(int64_t W, int64_t m, int64_t n, int64_t q, int64_t rounds,
+                       double* us_per_round, void* stream) {
+    if (!us_per_round || W < 1 || m < W || n < 1 || q < 1 || rounds < 1) return MEK_EINVAL;
+    if (m > (int64_t)kSelRows * kThreads || n > INT32_MAX / 2 || q > INT32_MAX / 2)
+        return MEK_EINVAL;
+    int dev = 0, cus = 0;
+    MEK_TRY(hipGetDevice(&dev));
+    MEK_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (W > cus) return MEK_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t words = (size_t)(2 * n + m + q + W) * 8;
+    const size_t need = ((words + 255) & ~(size_t)255) + sizeof(TeamSync) + 256;
+    char* buf = nullptr;
+    MEK_TRY(hipMalloc((void**)&buf, need));
+    TeamSync* ts = reinterpret_cast<TeamSync*>(buf + ((words + 255) & ~(size_t)255));
+    int* status = reinterpret_cast<int*>(reinterpret_cast<char*>(ts) + sizeof(TeamSync));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = fill_zero_bytes(buf, (long long)need, s);
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess)
+        e = exchange_probe((int)W, (int)m, (int)n, (int)q, rounds, buf, ts, status, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    int hst = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hst, status, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return hip_status(e);
+    if (hst != MEK_OK) return hst;
+    *us_per_round = (double)ms * 1e3 / (double)rounds;
+    return MEK_OK;
+}
+
 int mek_residual_split(int pieces, int64_t nb, int64_t m, int64_t p, int64_t q, int64_t n,
                        const float* A, const float* X, const float* B, const double* C, float* R,
                        void* stream) {

@@ -243,6 +243,7 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
 // same fixed-order summation follows.
 constexpr int kGStride = 33;   // 16-byte slots per output channel of the gradient tile (odd)
 constexpr int kXStride = 37;   // slots per input channel of a shifted copy (18 rows x 2, + 1)
+constexpr int kWgTiles = 4;    // pixel tiles per block of the matrix-core weight gradient
 
 template <int CO>
 __global__ void __launch_bounds__(256)
@@ -257,93 +258,99 @@ conv3x3_wgrad_mfma_kernel(const uint16_t* __restrict__ x, int H, int W,
     __shared__ uint4 gs[COP * kGStride];
     __shared__ uint16_t xsh[3 * CI * kXStride * 8];
     __shared__ float bsum[4][COP];
-    const int tiles_w = (W + kCT - 1) / kCT;
-    const int th = blockIdx.x / tiles_w, tw = blockIdx.x - th * tiles_w;
+    const int tiles_w = (W + kCT - 1) / kCT, tiles = tiles_w * ((H + kCT - 1) / kCT);
     const int n = blockIdx.y;
-    const int h0 = th * kCT, w0 = tw * kCT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    // Gradient tile (gated), zero outside the image and in padded channels;
-    // the bias gradient from the same values.
-    for (int e = tid; e < COP * 32; e += 256) {
-        const int o = e >> 5, chk = e & 31;          // 32 chunks of 8 pixels
-        const int hh = h0 + (chk >> 1), ww0 = w0 + 8 * (chk & 1);
-        uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (o < CO && hh < H) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int ww = ww0 + u;
-                if (ww < W) {
-                    const size_t idx = tidx(n, o, hh, ww, CO, H, W);
-                    uint16_t b = g[idx];
-                    if (gmask && !(bf2f(gmask[idx]) > 0.0f)) b = 0;
-                    v[u] = b;
-                }
-            }
-        }
-        gs[o * kGStride + chk] = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]),
-                                            pack2(v[6], v[7]));
-    }
-    // Input (NHWC): task e = (halo pixel, 8-channel chunk), one 16-byte load;
-    // each of its 8 values goes to the shifted copies that hold it.
-    for (int e = tid; e < 4 * kHaloPix; e += 256) {
-        const int r = e >> 2, ch = e & 3;
-        const int hr = r / kHalo, hc = r % kHalo;
-        const int hh = h0 - 1 + hr, ww = w0 - 1 + hc;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (hh >= 0 && hh < H && ww >= 0 && ww < W)
-            v = *reinterpret_cast<const uint4*>(x + (((size_t)n * H + hh) * W + ww) * CI + 8 * ch);
-        const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int col = hc - j;
-            if (col >= 0 && col < 16) {
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int c = 8 * ch + u;
-                    xsh[((j * CI + c) * kXStride + 2 * hr + (col >> 3)) * 8 + (col & 7)] =
-                        (uint16_t)((u & 1) ? (vv[u >> 1] >> 16) : (vv[u >> 1] & 0xffff));
-                }
-            }
-        }
-    }
-    __syncthreads();
-    // Bias gradient: thread (o, part) sums a quarter of the tile's pixels.
-    if (tid < 4 * COP) {
-        const int o = tid % COP, part = tid / COP;
-        float sacc = 0.0f;
-        for (int chk = 8 * part; chk < 8 * part + 8; ++chk) {
-            const uint4 w4 = gs[o * kGStride + chk];
-            const uint32_t ww[4] = {w4.x, w4.y, w4.z, w4.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) sacc += bf2f(ww[u] & 0xffff) + bf2f(ww[u] >> 16);
-        }
-        bsum[part][o] = sacc;
-    }
-
     const int l16 = lane & 15, lq = lane >> 4;
     const uint4* xs4 = reinterpret_cast<const uint4*>(xsh);
     float4_t acc[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) acc[u] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.0f;
+    // kWgTiles consecutive pixel tiles per block, accumulated in order.
+    const int t_end = min(tiles, (int)(blockIdx.x + 1) * kWgTiles);
+    for (int pt = blockIdx.x * kWgTiles; pt < t_end; ++pt) {
+        const int th = pt / tiles_w, tw = pt - th * tiles_w;
+        const int h0 = th * kCT, w0 = tw * kCT;
+        // Gradient tile (gated), zero outside the image and in padded channels;
+        // the bias gradient from the same values.
+        for (int e = tid; e < COP * 32; e += 256) {
+            const int o = e >> 5, chk = e & 31;          // 32 chunks of 8 pixels
+            const int hh = h0 + (chk >> 1), ww0 = w0 + 8 * (chk & 1);
+            uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (o < CO && hh < H) {
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-        // k chunk of this lane: pixel row 2 ks + lq / 2, columns 8 (lq & 1) ..
-        const int prow = 2 * ks + (lq >> 1), half = lq & 1;
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int tile = wave * PER + u;
-            if (tile >= TILES) break;
-            const int t = tile / (OT * CT), rem = tile % (OT * CT);
-            const int ot = rem / CT, ct = rem % CT;
-            const int i = t / 3, j = t % 3;
-            const bf16x8_t fa =
-                __builtin_bit_cast(bf16x8_t, gs[(16 * ot + l16) * kGStride + 2 * prow + half]);
-            const bf16x8_t fb = __builtin_bit_cast(
-                bf16x8_t, xs4[(j * CI + 16 * ct + l16) * kXStride + 2 * (prow + i) + half]);
-            acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[u], 0, 0, 0);
+                for (int u = 0; u < 8; ++u) {
+                    const int ww = ww0 + u;
+                    if (ww < W) {
+                        const size_t idx = tidx(n, o, hh, ww, CO, H, W);
+                        uint16_t b = g[idx];
+                        if (gmask && !(bf2f(gmask[idx]) > 0.0f)) b = 0;
+                        v[u] = b;
+                    }
+                }
+            }
+            gs[o * kGStride + chk] = make_uint4(pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]),
+                                                pack2(v[6], v[7]));
         }
+        // Input (NHWC): task e = (halo pixel, 8-channel chunk), one 16-byte load;
+        // each of its 8 values goes to the shifted copies that hold it.
+        for (int e = tid; e < 4 * kHaloPix; e += 256) {
+            const int r = e >> 2, ch = e & 3;
+            const int hr = r / kHalo, hc = r % kHalo;
+            const int hh = h0 - 1 + hr, ww = w0 - 1 + hc;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (hh >= 0 && hh < H && ww >= 0 && ww < W)
+                v = *reinterpret_cast<const uint4*>(x + (((size_t)n * H + hh) * W + ww) * CI + 8 * ch);
+            const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int col = hc - j;
+                if (col >= 0 && col < 16) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int c = 8 * ch + u;
+                        xsh[((j * CI + c) * kXStride + 2 * hr + (col >> 3)) * 8 + (col & 7)] =
+                            (uint16_t)((u & 1) ? (vv[u >> 1] >> 16) : (vv[u >> 1] & 0xffff));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // Bias gradient: thread (o, part) sums a quarter of the tile's pixels.
+        if (tid < 4 * COP) {
+            const int o = tid % COP, part = tid / COP;
+            float sacc = 0.0f;
+            for (int chk = 8 * part; chk < 8 * part + 8; ++chk) {
+                const uint4 w4 = gs[o * kGStride + chk];
+                const uint32_t ww[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sacc += bf2f(ww[u] & 0xffff) + bf2f(ww[u] >> 16);
+            }
+            bacc += sacc;
+        }
+
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            // k chunk of this lane: pixel row 2 ks + lq / 2, columns 8 (lq & 1) ..
+            const int prow = 2 * ks + (lq >> 1), half = lq & 1;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int tile = wave * PER + u;
+                if (tile >= TILES) break;
+                const int t = tile / (OT * CT), rem = tile % (OT * CT);
+                const int ot = rem / CT, ct = rem % CT;
+                const int i = t / 3, j = t % 3;
+                const bf16x8_t fa =
+                    __builtin_bit_cast(bf16x8_t, gs[(16 * ot + l16) * kGStride + 2 * prow + half]);
+                const bf16x8_t fb = __builtin_bit_cast(
+                    bf16x8_t, xs4[(j * CI + 16 * ct + l16) * kXStride + 2 * (prow + i) + half]);
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[u], 0, 0, 0);
+            }
+        }
+        __syncthreads();   // the tile's LDS is read; the next tile may overwrite it
     }
+    if (tid < 4 * COP) bsum[tid / COP][tid % COP] = bacc;
     __syncthreads();
     const size_t E = (size_t)CO * CI * 9 + CO;
     float* out = partial + ((size_t)n * gridDim.x + blockIdx.x) * E;
@@ -372,6 +379,7 @@ __global__ void sum_partials_kernel(const float* __restrict__ partial, long long
     const long long k = blockIdx.y;
     const long long t0 = k * T / S, t1 = (k + 1) * T / S;
     float s = 0.0f;
+#pragma unroll 8
     for (long long t = t0; t < t1; ++t) s += partial[t * E + e];
     mid[k * E + e] = s;
 }
@@ -381,6 +389,7 @@ __global__ void sum_mid_kernel(const float* __restrict__ mid, int S, long long E
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
     float s = 0.0f;
+#pragma unroll 8
     for (int k = 0; k < S; ++k) s += mid[(long long)k * E + e];
     if (e < nw) dw[e] = s;
     else db[e - nw] = s;
@@ -654,12 +663,14 @@ hipError_t cnn_conv3x3_grad_weight(int N, int Cin, int H, int W, int Cout, const
                                    float* dw, float* db, hipStream_t s) {
     const int tiles = ((H + kCT - 1) / kCT) * ((W + kCT - 1) / kCT);
     dim3 grid(tiles, N);
-    if (Cin == 32 && Cout == 32)
-        hipLaunchKernelGGL(conv3x3_wgrad_mfma_kernel<32>, grid, dim3(256), 0, s, x, H, W, g, gmask,
-                           partial);
-    else if (Cin == 32 && Cout == 3)
-        hipLaunchKernelGGL(conv3x3_wgrad_mfma_kernel<3>, grid, dim3(256), 0, s, x, H, W, g, gmask,
-                           partial);
+    const bool mm = Cin == 32;
+    dim3 grid_mm((tiles + kWgTiles - 1) / kWgTiles, N);
+    if (mm && Cout == 32)
+        hipLaunchKernelGGL(conv3x3_wgrad_mfma_kernel<32>, grid_mm, dim3(256), 0, s, x, H, W, g,
+                           gmask, partial);
+    else if (mm && Cout == 3)
+        hipLaunchKernelGGL(conv3x3_wgrad_mfma_kernel<3>, grid_mm, dim3(256), 0, s, x, H, W, g,
+                           gmask, partial);
     else switch (Cout) {
         case 32:
             hipLaunchKernelGGL(conv3x3_wgrad_kernel<32>, grid, dim3(kCThreads), 0, s, x, Cin, H, W,
@@ -674,7 +685,7 @@ hipError_t cnn_conv3x3_grad_weight(int N, int Cin, int H, int W, int Cout, const
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long nw = (long long)Cout * Cin * 9, E = nw + Cout;
-    const long long T = (long long)tiles * N;
+    const long long T = (long long)(mm ? grid_mm.x : grid.x) * N;
     const int S = (int)std::min<long long>(T, kSumSplits);
     float* mid = partial + T * E;   // the buffer holds (T + kSumSplits) E floats
     hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((E + 255) / 256), S), dim3(256), 0, s,

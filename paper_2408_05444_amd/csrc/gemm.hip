@@ -181,7 +181,27 @@ gemm_f64_tile_kernel(int M, int N, int K, double alpha, const double* __restrict
             if (t + 1 < nk) step(t + 1, ra[0], rb[0]);
         }
     } else {
-        for (int t = 0; t < nk; ++t) step(t, ra[0], rb[0]);
+        for (int t = 0; t < nk; ++t) {
+            const int cur = t & 1;
+            __syncthreads();   // tile t is in buffer cur; nobody reads cur ^ 1 any more
+            frag(cur, 0, 0);
+#pragma unroll
+            for (int q = 0; q < KS; ++q) {
+                if (q + 1 < KS) frag(cur, 4 * (q + 1), (q + 1) & 1);
+                // Hand the next tile to LDS and fetch the one after while the
+                // MFMAs of the first steps run.
+                if (q == 1 && t + 1 < nk) {
+                    store(cur ^ 1, ra[0], rb[0]);
+                    if (t + 2 < nk) load((t + 2) * kTK, ra[0], rb[0]);
+                }
+#pragma unroll
+                for (int x = 0; x < TM; ++x)
+#pragma unroll
+                    for (int y = 0; y < TN; ++y)
+                        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            fa[q & 1][x], fb[q & 1][y], acc[x][y], 0, 0, 0);
+            }
+        }
     }
 
     // Epilogue: all loads of C first (clamped into the matrix, so always in

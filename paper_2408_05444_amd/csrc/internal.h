@@ -271,6 +271,11 @@ hipError_t launch_philox(uint64_t seed, uint64_t inst, long long k0, long long c
 // Dense kernels (gemm.hip).
 // D = beta * C + alpha * A B, A(i,k) = A[i*a_i + k*a_k], B(k,j) = B[k*b_k + j*b_j],
 // C, D row-major with leading dimensions ldc, ldd (C may be null when beta == 0).
+// The team solver's exchanges and block collectives without arithmetic,
+// `rounds` times (probe.hip); words: 2n + m + q + W zeroed 64-bit words.
+hipError_t exchange_probe(int W, int m, int n, int q, long long rounds, void* words,
+                          TeamSync* sync, int* status, hipStream_t s);
+
 // D_b = beta C_b + alpha A_b B_b (FP32 operands split into `pieces` bf16
 // terms on the BF16 matrix cores, FP32 accumulation; C FP64, D FP32).
 hipError_t gemm_bf16s_batched(int pieces, int nb, int M, int N, int K, double alpha,

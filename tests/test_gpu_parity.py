@@ -479,3 +479,18 @@ def test_error_paths():
                                      mek.ctypes.c_void_p(Ah.ctypes.data),
                                      mek.ctypes.c_void_p(B.data_ptr()), None, None)
     assert code == mek.MEK_EINVAL
+
+
+def test_exchange_floor_is_below_the_update_time():
+    """The exchanges of the large workload's team alone take a positive time
+    per round that is below the measured time of a whole update."""
+    inst = workloads.large()
+    plan = mek.mek_plan_create(cuda(inst.A), cuda(inst.B))
+    res = mek.mek_solve(plan, cuda(inst.C), variant="grbk", max_iters=3000, seed=1)
+    upd_us = res.kernel_ms * 1e3 / res.iters
+    floor = mek.mek_exchange_floor(res.team_wgs, 2000, 2000, 500, rounds=3000)
+    assert 0.5 < floor < upd_us
+    small = mek.mek_exchange_floor(4, 100, 100, 40, rounds=2000)
+    assert 0.0 < small < floor
+    with pytest.raises(mek.MekError):
+        mek.mek_exchange_floor(8, 4, 10, 10)      # fewer rows than work-groups

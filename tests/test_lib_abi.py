@@ -141,4 +141,13 @@ def test_host_validation_rejects_before_any_gpu_work():
                                   None) == EINVAL
     assert L.mek_gram(3, 3, vp(1), 2, vp(2), None) == EINVAL
     assert L.mek_gram(3, 3, vp(1), 0, vp(1), None) == EINVAL
+    assert L.mek_residual_split(0, 1, 1, 1, 1, 1, vp(4), vp(4), vp(4), vp(8), vp(64), None) == EINVAL
+    assert L.mek_residual_split(4, 1, 1, 1, 1, 1, vp(4), vp(4), vp(4), vp(8), vp(64), None) == EINVAL
+    assert L.mek_residual_split(3, 1, 0, 1, 1, 1, vp(4), vp(4), vp(4), vp(8), vp(64), None) == EINVAL
+    assert L.mek_residual_noalloc(4097, 1, 512, 1, vp(8), vp(8), vp(8), vp(8), vp(64), None) == EINVAL
+    assert L.mek_residual_noalloc(0, 1, 1, 1, vp(8), vp(8), vp(8), vp(8), vp(64), None) == EINVAL
+    us = ctypes.c_double()
+    assert L.mek_exchange_floor(0, 10, 10, 10, 10, ctypes.byref(us), None) == EINVAL
+    assert L.mek_exchange_floor(8, 4, 10, 10, 10, ctypes.byref(us), None) == EINVAL
+    assert L.mek_exchange_floor(4, 10, 10, 10, 0, ctypes.byref(us), None) == EINVAL
     assert L.mek_plan_destroy(None) == mek.MEK_OK
