@@ -140,6 +140,64 @@ def gemm_forms(mek, torch, A, B, Xs, C, blur=None, reps=10):
     return out
 
 
+def cnn_forms(mek, torch, N=4, H=256, W=256, reps=20):
+    """The warm-start network's convolutions at the training shape (batch 4,
+    256 x 256): each layer shape's forward, input gradient and weight
+    gradient, `reps` calls each, timed with events on the calls' stream
+    (calls are stream ordered; the time includes the weight-reordering and
+    partial-sum kernels of a call). FLOP = 2 N H W Cin Cout 9 per call."""
+    import ctypes
+    L = mek.lib()
+    d = torch.device("cuda:0")
+    g = torch.Generator(device=d)
+    g.manual_seed(0)
+    p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    def bf16(C, nhwc):
+        shape = (N, H, W, C) if nhwc else (N, C, H, W)
+        return torch.randn(shape, generator=g, device=d).to(torch.bfloat16).view(torch.int16)
+
+    x3, x32 = bf16(3, False), bf16(32, True)
+    g3, g32 = bf16(3, False), bf16(32, True)
+    y32 = torch.empty((N, H, W, 32), dtype=torch.int16, device=d)
+    y3 = torch.empty((N, 3, H, W), dtype=torch.float64, device=d)
+    w = {(o, c): (0.1 * torch.randn(o, c, 3, 3, generator=g, device=d)).to(torch.bfloat16).float()
+         for o, c in [(32, 3), (32, 32), (3, 32)]}
+    b = torch.zeros(32, device=d)
+    dw = torch.empty(32 * 32 * 9, device=d)
+    db = torch.empty(32, device=d)
+    calls = {
+        "fwd_3to32": (lambda: L.mek_cnn_conv3x3(N, 3, H, W, 32, p(x3), p(w[(32, 3)]), p(b), 1,
+                                                p(y32), None, None, None), 3, 32),
+        "fwd_32to32": (lambda: L.mek_cnn_conv3x3(N, 32, H, W, 32, p(x32), p(w[(32, 32)]), p(b), 1,
+                                                 p(y32), None, None, None), 32, 32),
+        "fwd_32to3": (lambda: L.mek_cnn_conv3x3(N, 32, H, W, 3, p(x32), p(w[(3, 32)]), p(b), 0,
+                                                None, p(y3), None, None), 32, 3),
+        "dgrad_32to32": (lambda: L.mek_cnn_conv3x3_grad_input(N, 32, H, W, 32, p(g32), p(x32),
+                                                              p(w[(32, 32)]), p(y32), None), 32, 32),
+        "dgrad_3to32": (lambda: L.mek_cnn_conv3x3_grad_input(N, 3, H, W, 32, p(g3), None,
+                                                             p(w[(3, 32)]), p(y32), None), 3, 32),
+        "wgrad_32x32": (lambda: L.mek_cnn_conv3x3_grad_weight(N, 32, H, W, 32, p(x32), p(g32),
+                                                              p(x32), p(dw), p(db), None), 32, 32),
+        "wgrad_3x32": (lambda: L.mek_cnn_conv3x3_grad_weight(N, 3, H, W, 32, p(x3), p(g32),
+                                                             p(x32), p(dw), p(db), None), 3, 32),
+    }
+    out = {"batch": N, "height": H, "width": W}
+    for name, (fn, ci, co) in calls.items():
+        assert fn() == 0
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        tf = 2.0 * N * H * W * ci * co * 9 / (us * 1e-6) / 1e12
+        out[name] = {"us_per_call": us, "tflops": tf, "frac_of_bf16_peak": tf / MFMA_BF16_PEAK_TFLOPS}
+    return out
+
+
 def blur_tensors(workloads, torch):
     """A, B (512 x 512 blur, shared), C and X* (3 x 512 x 512) on the GPU."""
     chans = workloads.blurred_image(512, 3, 2.0, seed=4, noise_std=1e-3)
@@ -794,6 +852,8 @@ def main():
                     help="only run the paper's Table 4 / Table 2 Gaussian sets and print them")
     ap.add_argument("--sparse-only", action="store_true",
                     help="only run the image forms (dense and sparse-aware updates) and print them")
+    ap.add_argument("--cnn-only", action="store_true",
+                    help="only time the warm-start network's convolutions at batch 4, 256 x 256")
     ap.add_argument("--ragged-only", action="store_true",
                     help="only run the uneven-instance batch form and print it")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -850,6 +910,9 @@ def main():
         print(json.dumps({"blur3_batched": blur_batch_forms(mek, workloads, torch),
                           "blur_sparse_many": sparse_many_forms(mek, workloads, torch)}),
               flush=True)
+        return
+    if args.cnn_only:
+        print(json.dumps({"cnn_convolutions": cnn_forms(mek, torch)}), flush=True)
         return
     if args.ragged_only:
         print(json.dumps({"ragged64_fp32": ragged_batch_forms(mek, workloads, torch),
@@ -910,6 +973,14 @@ def main():
                      "kernel_us_per_update": kernel_ms * 1e3 / max(iters, 1),
                      "algorithmic_bytes_per_update": bpu},
     }
+    # The update is bound by the latency of its exchanges between work-groups,
+    # not by bandwidth (R lives in LDS): the same team's exchanges and block
+    # collectives alone, timed by the library, give the floor under it.
+    floor = mek.mek_exchange_floor(results[-1].team_wgs, m, n, q, rounds=20000)
+    line["roofline"]["regime"] = ("latency: the exchanges between the team's work-groups "
+                                  "(R stays in LDS, 1.5 MB per update crosses HBM)")
+    line["roofline"]["latency_floor_us_per_update"] = floor
+    line["roofline"]["latency_frac"] = floor / (kernel_ms * 1e3 / max(iters, 1))
     if not args.no_forms:
         forms = {}
         # FP32 (residual refreshed from the iterate every 4 m updates on the
@@ -959,6 +1030,7 @@ def main():
         line["forms"] = forms
         line["gemm_mfma_f64"] = gemm_forms(mek, torch, A, B, Xs, C,
                                            blur=blur_tensors(workloads, torch))
+        line["cnn_convolutions"] = cnn_forms(mek, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, seed, workloads)
     print(json.dumps(line), flush=True)

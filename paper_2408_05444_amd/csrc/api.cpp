@@ -228,6 +228,7 @@ struct Layout {
     bool a_lds;
     bool x_lds;
     bool b_lds;
+    bool small;   // the one-row-per-thread kernel (W = 1, R, B, X^T in LDS)
     size_t lds_bytes;
 };
 
@@ -250,6 +251,23 @@ int choose_layout_cap(const mek_plan_s* P, size_t elem, int cap, bool allow_lds,
     if (!allow_lds && P->r_in_lds == 1) return MEK_EUNSUPPORTED;
     const int cus = std::max(1, cap);
     const size_t budget = solve_lds_budget();
+    L->small = false;
+    L->b_lds = false;
+    // Small instances under the automatic layout: one work-group, one row of
+    // R per thread, R, B and X^T in LDS, no exchanges.
+    if (allow_lds && P->team_wgs <= 0 && P->r_in_lds != 0 && m <= kThreads && n <= kThreads &&
+        q <= kThreads && P->p <= kThreads &&
+        solve_small_lds_bytes((int)m, (int)P->p, (int)q, (int)n, elem) <= budget) {
+        L->W = 1;
+        L->rpw = (int)m;
+        L->xpw = (int)q;
+        L->wpw = (int)n;
+        L->lds = true;
+        L->a_lds = L->x_lds = false;
+        L->small = true;
+        L->lds_bytes = solve_small_lds_bytes((int)m, (int)P->p, (int)q, (int)n, elem);
+        return MEK_OK;
+    }
     int W;
     bool lds;
     auto fits = [&](int Wc) {
@@ -442,6 +460,7 @@ int run_kernel(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double a
     K.a_in_lds = L.a_lds ? 1 : 0;
     K.x_in_lds = L.x_lds ? 1 : 0;
     K.b_in_lds = L.b_lds ? 1 : 0;
+    K.small = L.small ? 1 : 0;
     // Pause between polls of exchange words (tuning knob MEK_POLL_SLEEP).
     static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
     K.poll_sleep = poll_sleep;
@@ -2047,6 +2066,7 @@ int enqueue_solve(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, const
     K.a_in_lds = L.a_lds ? 1 : 0;
     K.x_in_lds = L.x_lds ? 1 : 0;
     K.b_in_lds = L.b_lds ? 1 : 0;
+    K.small = L.small ? 1 : 0;
     static const int poll_sleep = getenv("MEK_POLL_SLEEP") ? atoi(getenv("MEK_POLL_SLEEP")) : 1;
     K.poll_sleep = poll_sleep;
     MEK_TRY(fill_zero_bytes(w.sync, (long long)sizeof(TeamSync), s));

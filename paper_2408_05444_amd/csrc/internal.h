@@ -100,6 +100,7 @@ struct SolveParams {
     int a_in_lds;                // keep ||A_i||^2 for all rows in LDS
     int x_in_lds;                // keep this work-group's rows of X^T in LDS
     int b_in_lds;                // keep B and B^T in LDS (one-work-group teams)
+    int small;                   // one work-group, one row of R per thread (small instances)
     int poll_sleep;              // s_sleep length between polls of exchange words
     // Batch: with slots set, nb teams of W work-groups, team b on instance
     // slots[b].id, whose R, X^T, X_ref^T, r, rowbuf, vbuf, wbuf, errpart,
@@ -260,6 +261,7 @@ size_t solve_lds_bytes(int rpw, int n, int q, int xpw, int wpw, size_t elem, boo
                        bool single);
 size_t solve_lds_budget();
 size_t solve_lds_bytes_a(int m);
+size_t solve_small_lds_bytes(int m, int p, int q, int n, size_t elem);
 
 hipError_t launch_select(int variant, int m, const double* r, const double* a, double F_A,
                          double theta, uint64_t seed, uint64_t inst, long long k0,

@@ -602,6 +602,219 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Small instances (m, n, p, q <= kThreads): one work-group holds R, B and
+// X^T in LDS and gives every thread one row of R, so row norms need no
+// reduction, the selection sees one row per thread, and the two dot-product
+// phases are one dot per thread (v_l = R_{i_k} . B_l for l < q, then
+// w_j = sum_l v_l B_lj for j < n), each summed in ascending index order.
+// R and B rows are padded to n + 1 entries (conflict-free LDS columns).
+// Uniform batches: work-group b runs instance b. Same options, stop rules,
+// histories and report as the team kernel.
+constexpr int kSmallU = 8;   // LDS loads per block in the small kernel's loops
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T> P) {
+    extern __shared__ __align__(16) unsigned char dyn_smem[];
+    __shared__ BlockScratch sc;
+    __shared__ double s_c;
+    __shared__ int s_ik;
+    if (P.slots) bind_instance(P, blockIdx.x);
+    if (P.norms) {
+        P.C2 = P.norms[0];
+        P.ref2 = P.norms[1] > 0.0 ? P.norms[1] : 1.0;
+    }
+    const int m = P.m, n = P.n, p = P.p, q = P.q, ld = n + 1;
+    const int tid = threadIdx.x;
+    // LDS: R (m x ld), B (q x ld), X^T (q x p), v (q), w (n), A_{i_k} (p),
+    // Philox draws (kUTable).
+    T* Rl = reinterpret_cast<T*>(dyn_smem);
+    T* Bl = Rl + (size_t)m * ld;
+    T* Xl = Bl + (size_t)q * ld;
+    T* vl = Xl + (size_t)q * p;
+    T* wl = vl + q;
+    T* al = wl + n;
+    double* u_tab = reinterpret_cast<double*>(
+        reinterpret_cast<unsigned char*>(dyn_smem) +
+        ((((size_t)m * ld + (size_t)q * ld + (size_t)q * p + q + n + p) * sizeof(T) + 15) & ~(size_t)15));
+    for (int e = tid; e < m * n; e += kThreads) Rl[(e / n) * ld + e % n] = P.R[e];
+    for (int e = tid; e < q * n; e += kThreads) Bl[(e / n) * ld + e % n] = P.B[e];
+    for (int e = tid; e < q * p; e += kThreads) Xl[e] = P.Xt[e];
+    const bool has_ref = P.Xref_t != nullptr;
+    const double ai = tid < m ? P.a[tid] : 0.0;
+    __syncthreads();
+    // Own row's norm and the first error partial.
+    double ri = 0.0;
+    if (tid < m) {
+        const T* rp = Rl + (size_t)tid * ld;
+        for (int j = 0; j < n; ++j) ri += (double)rp[j] * (double)rp[j];
+    }
+    double ep = 0.0;
+    if (has_ref)
+        for (int e = tid; e < q * p; e += kThreads) {
+            const double d = (double)Xl[e] - P.Xref_t[e];
+            ep += d * d;
+        }
+    double S0 = -1.0, S = 0.0, err = NAN;
+    long long k = 0;
+    int status = kMaxIter, last_set = 0;
+    const int sb = min(m, tid), scnt = tid < m ? 1 : 0;
+    const bool timing = P.phase != nullptr && blockIdx.x == 0 && tid == 0;
+    unsigned long long ph[kPhCount] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long t_last = timing ? wall_clock64() : 0;
+    for (;;) {
+        if ((k % kUTable) == 0) {
+            if (tid < kUTable) u_tab[tid] = philox_uniform(P.seed, P.inst, P.k_offset + k + tid);
+            __syncthreads();
+        }
+        const double u_k = u_tab[k % kUTable];
+        double rr[1] = {scnt ? ri : 0.0}, aa[1] = {ai};
+        double rho[1] = {(scnt && ai > 0.0) ? ri / ai : -1.0};
+        double Sp = rr[0], Mp = rho[0], Ep = ep;
+        block_sum_max_sum(Sp, Mp, Ep, sc);
+        MEK_PHASE(kPhReduce);
+        S = Sp;
+        const double M = Mp;
+        if (S0 < 0.0) S0 = S;
+        err = has_ref ? sqrt(Ep / P.ref2) : NAN;
+        const long long hk = P.hist_offset + k;
+        if (tid == 0 && hk < P.hist_cap) {
+            if (P.resid_hist) P.resid_hist[hk] = S;
+            if (P.err_hist) P.err_hist[hk] = err;
+        }
+        if (P.stop == kStopRelErr && err <= P.tol) { status = kOK; break; }
+        if (P.stop == kStopRelResid && sqrt(S) <= P.tol * sqrt(P.C2)) { status = kOK; break; }
+        if (P.S_target > 0.0 && S <= P.S_target) { status = kOK; break; }
+        if (S == 0.0) { status = kExact; break; }
+        if (!isfinite(S) || (P.diverge > 0.0 && S > P.diverge * S0)) { status = kEDiverged; break; }
+        if (k >= P.max_iters) { status = kMaxIter; break; }
+        int ik;
+        if (P.replay && P.k_offset + k < P.replay_len) {
+            ik = P.replay[P.k_offset + k];
+            last_set = 0;
+        } else {
+            const SelectOut so = select_rows<1>(P.variant, sb, scnt, rr, aa, rho, S, M, P.F_A,
+                                                P.theta, u_k, P.k_offset + k, P.active,
+                                                P.n_active, sc, nullptr, nullptr);
+            ik = so.idx;
+            last_set = so.setsize;
+        }
+        if (tid == 0 && hk < P.hist_cap) {
+            if (P.idx_hist) P.idx_hist[hk] = ik;
+            if (P.set_hist) P.set_hist[hk] = last_set;
+        }
+        MEK_PHASE(kPhSelect);
+        // Operands of the update from device memory, fetched now: A_{i_k}
+        // into LDS, this row's entry of column i_k of A A^T into a register.
+        if (tid == ik) s_c = P.alpha / ai;
+        if (tid < p) al[tid] = P.A[(size_t)ik * p + tid];
+        const T ga = tid < m ? P.GA[(size_t)ik * m + tid] : (T)0;
+        // v_l = R_{i_k} . B_l (pre-update row).
+        // Loops over LDS in blocks of kSmallU, every load of a block issued
+        // before its multiply-adds (sums still in ascending index order).
+        const T* rrow = Rl + (size_t)ik * ld;
+        if (tid < q) {
+            const T* brow = Bl + (size_t)tid * ld;
+            double acc = 0.0;
+            for (int j0 = 0; j0 < n; j0 += kSmallU) {
+                T xa[kSmallU], xb[kSmallU];
+#pragma unroll
+                for (int u = 0; u < kSmallU; ++u) {
+                    xa[u] = j0 + u < n ? rrow[j0 + u] : (T)0;
+                    xb[u] = j0 + u < n ? brow[j0 + u] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < kSmallU; ++u) acc += (double)xa[u] * (double)xb[u];
+            }
+            vl[tid] = (T)acc;
+        }
+        __syncthreads();
+        MEK_PHASE(kPhDots);
+        const double c = s_c;
+        // X^T[l][s] += c A_{i_k, s} v_l, with the error partial; then
+        // w_j = sum_l v_l B_lj.
+        ep = 0.0;
+        for (int e = tid; e < q * p; e += kThreads) {
+            const int l = e / p, s2 = e - l * p;
+            const T nv = Xl[e] + (T)(c * (double)al[s2]) * vl[l];
+            Xl[e] = nv;
+            if (has_ref) {
+                const double d = (double)nv - P.Xref_t[e];
+                ep += d * d;
+            }
+        }
+        if (tid < n) {
+            double acc = 0.0;
+            for (int l0 = 0; l0 < q; l0 += kSmallU) {
+                T xa[kSmallU], xb[kSmallU];
+#pragma unroll
+                for (int u = 0; u < kSmallU; ++u) {
+                    xa[u] = l0 + u < q ? vl[l0 + u] : (T)0;
+                    xb[u] = l0 + u < q ? Bl[(size_t)(l0 + u) * ld + tid] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < kSmallU; ++u) acc += (double)xa[u] * (double)xb[u];
+            }
+            wl[tid] = (T)acc;
+        }
+        __syncthreads();
+        MEK_PHASE(kPhX);
+        // R_h -= (c (A A^T)_{i_k, h}) w and the new norm of row h.
+        if (tid < m) {
+            const T sc_h = (T)(c * (double)ga);
+            T* rp = Rl + (size_t)tid * ld;
+            double acc = 0.0;
+            for (int j0 = 0; j0 < n; j0 += kSmallU) {
+                T xr[kSmallU], xw[kSmallU];
+#pragma unroll
+                for (int u = 0; u < kSmallU; ++u) {
+                    xr[u] = j0 + u < n ? rp[j0 + u] : (T)0;
+                    xw[u] = j0 + u < n ? wl[j0 + u] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < kSmallU; ++u) {
+                    if (j0 + u < n) {
+                        const T v = xr[u] - sc_h * xw[u];
+                        rp[j0 + u] = v;
+                        acc += (double)v * (double)v;
+                    }
+                }
+            }
+            ri = acc;
+        }
+        MEK_PHASE(kPhUpdate);
+        ++k;
+    }
+    if (timing)
+        for (int i2 = 0; i2 < kPhCount; ++i2) P.phase[i2] += ph[i2];
+    for (int e = tid; e < q * p; e += kThreads) P.Xt[e] = Xl[e];
+    if (tid == 0) {
+        P.report->iters = k;
+        P.report->status = status;
+        P.report->last_set = last_set;
+        P.report->S = S;
+        P.report->err = err;
+    }
+}
+
+size_t solve_small_lds_bytes(int m, int p, int q, int n, size_t elem) {
+    const size_t ld = (size_t)n + 1;
+    return (((size_t)m * ld + (size_t)q * ld + (size_t)q * p + q + n + p) * elem + 15) / 16 * 16 +
+           kUTable * sizeof(double);
+}
+
+template <typename T>
+static hipError_t launch_small(const SolveParams<T>& P, size_t lds_bytes, hipStream_t s) {
+    auto kern = solve_small_kernel<T>;
+    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes) != hipSuccess)
+        (void)hipGetLastError();
+    SolveParams<T> copy = P;
+    void* args[] = {&copy};
+    const int blocks = P.slots ? P.nb : 1;
+    return hipLaunchKernel((const void*)kern, dim3(blocks), dim3(kThreads), args, lds_bytes, s);
+}
+
 size_t solve_lds_budget() { return 160 * 1024 - 1024; }
 
 size_t solve_lds_bytes(int rpw, int n, int q, int xpw, int wpw, size_t elem, bool r_in_lds,
@@ -674,11 +887,13 @@ hipError_t launch_solve_multi(const SolveParams<float>& P, int max_m, size_t lds
 
 hipError_t launch_solve(const SolveParams<double>& P, bool r_in_lds, size_t lds_bytes,
                         hipStream_t s) {
+    if (P.small) return launch_small<double>(P, lds_bytes, s);
     return r_in_lds ? launch_sr<double, true>(P, lds_bytes, s)
                     : launch_sr<double, false>(P, lds_bytes, s);
 }
 hipError_t launch_solve(const SolveParams<float>& P, bool r_in_lds, size_t lds_bytes,
                         hipStream_t s) {
+    if (P.small) return launch_small<float>(P, lds_bytes, s);
     return r_in_lds ? launch_sr<float, true>(P, lds_bytes, s)
                     : launch_sr<float, false>(P, lds_bytes, s);
 }
