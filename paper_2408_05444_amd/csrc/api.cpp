@@ -1050,14 +1050,15 @@ int run_block2(mek_plan_s* P, const mek_solve_opts* o, const Layout& L, double C
     if (st == MEK_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess && kernel_ms)
         *kernel_ms += (double)ms;
     if (st == MEK_OK && phases && out->iters > 0) {
-        unsigned long long h[8];
+        unsigned long long h[11];
         int rate_khz = 100000;
         (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, P->device);
         if (hipMemcpy(h, w.phase, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess) {
-            const char* names[8] = {"rows", "cols", "select", "factor", "E", "W", "X", "R"};
+            const char* names[11] = {"rows", "cols", "select", "gram", "chol", "factor", "E",
+                                     "W",    "X",    "R_upd",  "R_score"};
             fprintf(stderr, "[mek block phases] W=%d lds=%d steps=%lld us/step:", L.W, (int)L.lds,
                     (long long)out->iters);
-            for (int i = 0; i < 8; ++i)
+            for (int i = 0; i < 11; ++i)
                 fprintf(stderr, " %s=%.2f", names[i], (double)h[i] / (rate_khz * 1e-3) / out->iters);
             fprintf(stderr, " total_kernel=%.2f\n", ms * 1e3 / out->iters);
         }

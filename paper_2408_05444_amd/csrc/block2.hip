@@ -23,10 +23,12 @@
 //      of the column maxima;
 //   C. each work-group reads all column maxima, then (redundantly, in a fixed
 //      order, so every work-group gets the same result) selects I and J and
-//      factors A_I A_I^T and B_J^T B_J;
+//      factors A_I A_I^T and B_J^T B_J (one wave per factor, rows held in
+//      registers);
 //   D. the owners of the rows in I publish R_IJ; with it every work-group
-//      forms W, updates its columns of X, then its rows of R together with
-//      the next step's row words and column maxima (A of step k + 1).
+//      forms W (one wave, columns then rows of W in registers), updates its
+//      columns of X, then its rows of R together with the next step's row
+//      words and column maxima (A of step k + 1).
 // Reading every row word before publishing its column slice (B) makes every
 // rewrite of a buffer causally after all reads of its previous contents,
 // so one buffer per kind suffices.
@@ -39,12 +41,26 @@ namespace mek {
 
 namespace {
 
-constexpr int kChunk = 4;   // rows of R per pass of the fused update/score loop
+constexpr int kChunk = 8;   // rows of R per pass of the fused update/score loop
 constexpr int kXRows = 8;   // rows of X^T per pass of the X update
+static_assert(kChunk == 8 && kXRows == 8, "block2_fac_doubles sizes the factor region for 8-row passes");
+static_assert(kChunk * kBlkCap <= kThreads && 2 * kXRows * kBlkCap <= kThreads,
+              "one thread per entry of (A A^T)_{i, I}, c and B_{l, J}");
 
 // Optional phase timing (work-group 0, thread 0): wall-clock ticks per phase
 // of a step, summed over the solve.
-enum { kB2Rows, kB2Cols, kB2Select, kB2Factor, kB2E, kB2W, kB2X, kB2R, kB2Count };
+enum { kB2Rows, kB2Cols, kB2Select, kB2Gram, kB2Chol, kB2Factor, kB2E, kB2W, kB2X, kB2RUpd, kB2R,
+       kB2Count };
+
+// Orders a wave's LDS accesses around an exchange between its own lanes. A
+// wave's LDS instructions are performed in issue order, so a store by one
+// lane is seen by a later load of another lane of the same wave; the fences
+// and the wave barrier keep the compiler from moving accesses across.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Order-preserving key of a non-negative double; 0 is reserved for "not a
 // candidate".
@@ -67,6 +83,8 @@ struct Blk2Smem {
     int I[kBlkCap], J[kBlkCap];
     unsigned long long prefix[2];
     int need[2];
+    int bincnt[2];                       // keys in the radix bin that holds the threshold
+    int gcnt[2];                         // keys of that bin gathered (early exit)
     int nsel[2];
     int nI, nJ;
     int fail;
@@ -101,6 +119,55 @@ __device__ __forceinline__ void block_sums_maxes(double (&v)[NS + NM], Blk2Smem&
         v[j] = t;
     }
     __syncthreads();
+}
+
+// Block totals of 16 values per thread, the first 8 summed and the last 8
+// maximised, returned to thread t < 16 (the total of value t). Within a
+// wave the values are reduced and scattered by halving exchanges (lane
+// partner l ^ 32, 16, 8, 4 keeps one half of the remaining values, then
+// l ^ 2 and l ^ 1 complete the single value each lane holds), 34 lane
+// exchanges in place of 16 separate wave reductions; the wave totals are
+// then combined in wave order. Fixed order: identical inputs give identical
+// results in every work-group.
+__device__ __forceinline__ double block_reduce_scatter16(double (&v)[16], Blk2Smem& sm) {
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const bool mx = (lane & 32) != 0;   // this lane ends with one of the maxima
+    double a[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const double send = mx ? v[i] : v[i + 8];
+        const double mine = mx ? v[i + 8] : v[i];
+        const double r = __shfl_xor(send, 32);
+        a[i] = mx ? fmax(mine, r) : mine + r;
+    }
+#pragma unroll
+    for (int half = 4, mask = 16; half >= 1; half >>= 1, mask >>= 1) {
+        const bool up = (lane & mask) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const double send = up ? a[i] : a[i + half];
+            const double mine = up ? a[i + half] : a[i];
+            const double r = __shfl_xor(send, mask);
+            a[i] = mx ? fmax(mine, r) : mine + r;
+        }
+    }
+#pragma unroll
+    for (int mask = 2; mask >= 1; mask >>= 1) {
+        const double r = __shfl_xor(a[0], mask);
+        a[0] = mx ? fmax(a[0], r) : a[0] + r;
+    }
+    const int idx = (mx ? 8 : 0) + ((lane & 16) ? 4 : 0) + ((lane & 8) ? 2 : 0) + ((lane & 4) ? 1 : 0);
+    if ((lane & 3) == 0) sm.red[wv][idx] = a[0];
+    __syncthreads();
+    double t = 0.0;
+    const int tid = threadIdx.x;
+    if (tid < 16) {
+        t = sm.red[0][tid];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) t = (tid < 8) ? t + sm.red[w][tid] : fmax(t, sm.red[w][tid]);
+    }
+    __syncthreads();
+    return t;
 }
 
 // Radix selection of the largest keys, run by the whole block for two key
@@ -174,12 +241,19 @@ __device__ __forceinline__ void select_top(const unsigned long long (&kr)[SR], i
             sm.need[1] = min(capC, totC);
         }
         __syncthreads();
+        // Radix passes, most significant byte first. A kind leaves the passes
+        // early once the bin that holds its threshold has at most kBinMax
+        // keys: those are gathered and ranked directly, which gives the same
+        // threshold key and count of equal keys to take.
+        constexpr int kBinMax = 2 * kWave;
+        unsigned long long* bink = reinterpret_cast<unsigned long long*>(hist + 1024);
+        bool doneR = !radR || startR < 0, doneC = !radC || startC < 0;
         const int dstart = max(startR, startC);
-        for (int d = dstart; d >= 0; --d) {
+        for (int d = dstart; d >= 0 && !(doneR && doneC); --d) {
             int* H = hist + (d & 1) * 512;
             const int sh = 8 * d;
             const unsigned long long pR = sm.prefix[0], pC = sm.prefix[1];
-            const bool inR = radR && d <= startR, inC = radC && d <= startC;
+            const bool inR = !doneR && d <= startR, inC = !doneC && d <= startC;
 #pragma unroll
             for (int j = 0; j < SR; ++j) {
                 if (inR && j < rc && kr[j] != 0ull &&
@@ -209,6 +283,8 @@ __device__ __forceinline__ void select_top(const unsigned long long (&kr)[SR], i
                         const unsigned long long bin = (unsigned long long)(255 - 4 * lane - u);
                         sm.prefix[wv] |= bin << sh;
                         sm.need[wv] = need - run;
+                        sm.bincnt[wv] = c4[u];
+                        sm.gcnt[wv] = 0;
                     }
                     run += c4[u];
                 }
@@ -217,6 +293,40 @@ __device__ __forceinline__ void select_top(const unsigned long long (&kr)[SR], i
                 for (int e = lane; e < 512; e += kWave) Hn[e] = 0;
             }
             __syncthreads();
+            const bool exR = inR && d > 0 && sm.bincnt[0] <= kBinMax;
+            const bool exC = inC && d > 0 && sm.bincnt[1] <= kBinMax;
+            if (exR || exC) {
+                const unsigned long long qR = sm.prefix[0], qC = sm.prefix[1];
+#pragma unroll
+                for (int j = 0; j < SR; ++j) {
+                    if (exR && j < rc && kr[j] != 0ull && (kr[j] >> sh) == (qR >> sh))
+                        bink[atomicAdd(&sm.gcnt[0], 1)] = kr[j];
+                    if (exC && j < cc && kc[j] != 0ull && (kc[j] >> sh) == (qC >> sh))
+                        bink[kBinMax + atomicAdd(&sm.gcnt[1], 1)] = kc[j];
+                }
+                __syncthreads();
+                if (wv < 2 && (wv == 0 ? exR : exC)) {
+                    // The need-th largest key of the bin (with multiplicity)
+                    // and how many keys equal to it are taken.
+                    const unsigned long long* bk = bink + wv * kBinMax;
+                    const int cnt = sm.gcnt[wv], need = sm.need[wv];
+                    for (int l = lane; l < cnt; l += kWave) {
+                        const unsigned long long key = bk[l];
+                        int gt = 0, eq = 0;
+                        for (int u = 0; u < cnt; ++u) {
+                            gt += bk[u] > key;
+                            eq += bk[u] == key;
+                        }
+                        if (gt < need && need <= gt + eq) {
+                            sm.prefix[wv] = key;
+                            sm.need[wv] = need - gt;
+                        }
+                    }
+                }
+                __syncthreads();
+                doneR = doneR || exR;
+                doneC = doneC || exC;
+            }
         }
         thR = sm.prefix[0];
         thC = sm.prefix[1];
@@ -292,16 +402,73 @@ __device__ __forceinline__ void select_top(const unsigned long long (&kr)[SR], i
 
 }  // namespace
 
+// One right-looking triangular sweep over a vector held in registers:
+// forward, pivots x = 0, 1, ..., n - 2 subtract Mt[x][r] e[x] from e[r] for
+// r > x; backward, pivots x = n - 1, ..., 1 subtract it for r < x. Mt holds
+// the pivots' factors as rows of kBlkCap, zero past n, in `cap` >= n rows.
+// Pivots go in pairs: both rows are read together (one LDS round trip per
+// pair), the first pivot's term enters the second pivot's entry, and every
+// other entry takes the two terms in pivot order. The second pivot of a
+// pair (forward) or the first (backward) may lie past n: its terms are
+// then exact zeros (e of it is zero, or its row is; a row past `cap` is
+// read clamped). The (uniform) branch per pair keeps the compiler from
+// fetching further ahead, which would need more registers than the wave
+// has.
+template <bool kFwd>
+__device__ __forceinline__ void tri_sweep(double (&e)[kBlkCap], const double* Mt, int n, int cap) {
+    constexpr int kPiv = kBlkCap - 1;   // pivots 0 .. kBlkCap - 2 (forward) or kBlkCap - 1 .. 1
+#pragma unroll
+    for (int st = 0; st < kPiv; st += 2) {
+        const int x = kFwd ? st : kBlkCap - 1 - st;          // first pivot of the pair
+        const bool two = st + 1 < kPiv;
+        const int x2 = kFwd ? x + 1 : x - 1;                  // second pivot
+        // Forward: the pair has work if its first pivot does; backward, if its
+        // second (lower) one does (the first may lie past n).
+        if (kFwd ? x + 1 < n : (two ? x2 < n : x < n)) {
+            const double* m1 = Mt + min(x, cap - 1) * kBlkCap;
+            const double* m2 = Mt + min(x2, cap - 1) * kBlkCap;
+            double a1[kBlkCap], a2[kBlkCap];
+#pragma unroll
+            for (int r = 0; r < kBlkCap; ++r) {
+                if (kFwd ? r > x : r < x) a1[r] = m1[r];
+                if (two && (kFwd ? r > x2 : r < x2)) a2[r] = m2[r];
+            }
+            const double e1 = e[x];
+            if (two) e[x2] -= a1[x2] * e1;
+            const double e2 = two ? e[x2] : 0.0;
+#pragma unroll
+            for (int r = 0; r < kBlkCap; ++r) {
+                if ((kFwd ? r > x : r < x) && !(two && r == x2)) {
+                    e[r] -= a1[r] * e1;
+                    if (two) e[r] -= a2[r] * e2;
+                }
+            }
+        }
+    }
+}
+
 template <int SR, bool LDS>
 __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     __shared__ Blk2Smem sm;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    // The thread's indices are re-derived at the start of every phase of a
+    // step through an opaque copy, so that the compiler recomputes the many
+    // per-thread addresses of a phase inside it instead of keeping them in
+    // registers across the whole loop.
+    int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    auto fresh_ids = [&]() {
+        int t = threadIdx.x;
+        asm volatile("; thread index, opaque to code motion" : "+v"(t));
+        tid = t;
+        lane = t & (kWave - 1);
+        wv = t / kWave;
+    };
     if (tid == 0) sm.fail = 0;
 
     const int W = P.W, g = blockIdx.x;
     const int m = P.m, n = P.n, p = P.p, q = P.q;
-    const int scap = P.s_cap, tcap = P.t_cap, ldE = tcap + 1;
+    const int scap = P.s_cap, tcap = P.t_cap;
+    constexpr int ldE = kBlkCap + 1;
     const int row0 = g * P.rpw;
     const int nrow = max(0, min(P.rpw, m - row0));
     const int xc0 = g * P.xpw;
@@ -316,24 +483,56 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
     xword* const ex = reinterpret_cast<xword*>(P.ebuf);
     xword* const px = reinterpret_cast<xword*>(P.errpart);
 
-    // LDS: [own rows of R] [E / W, also radix histograms and the column
-    // slice] [L_I] [L_J] [z: kChunk x tcap] [(A A^T)_{i, I}: kChunk x kBlkCap]
-    // [c of the X update: kXRows x kBlkCap].
+    // LDS: [own rows of R] [E / W (kBlkCap x ldE), also the radix histograms,
+    // the column slice and the factorisations' column buffers] [factors:
+    // L_I (s_cap rows), L_J (t_cap rows), each row kBlkCap wide and zero
+    // outside the block] [(A A^T)_{i, I}: kChunk x kBlkCap]. After W is
+    // formed the factors' space holds the X update's c and B_{l, J}, then
+    // the R update's z.
     const size_t r_bytes = LDS ? (((size_t)P.rpw * n * 8 + 15) & ~(size_t)15) : 0;
-    double* Rl = reinterpret_cast<double*>(dyn_smem);
-    unsigned char* ereg = dyn_smem + r_bytes;
-    double* E = reinterpret_cast<double*>(ereg);
-    int* hist = reinterpret_cast<int*>(ereg);
-    unsigned long long* slice = reinterpret_cast<unsigned long long*>(ereg);
-    const size_t e_bytes = block2_ereg_bytes(scap, tcap, ncs);
-    double* LI = reinterpret_cast<double*>(ereg + e_bytes);
-    double* LJ = LI + scap * scap;
-    double* z = LJ + tcap * tcap;
-    double* gaI = z + kChunk * tcap;                   // kChunk x kBlkCap
-    double* cX = gaI + kChunk * kBlkCap;               // kXRows x kBlkCap
-    // Own rows of R: LDS or device memory, fixed at compile time so that
-    // every access is a plain LDS or global instruction.
-    double* Rown = LDS ? Rl : P.R + (size_t)row0 * n;
+    const size_t e_bytes = block2_ereg_bytes(ncs);
+    const int fac = block2_fac_doubles(scap, tcap);
+    double *Rl, *E, *colbuf, *LI, *LJ, *gaI, *cX, *bX, *zT, *Rown;
+    int* hist;
+    unsigned long long* slice;
+    // The region addresses are re-derived with the thread indices (below)
+    // from an opaque zero offset, for the same reason.
+    auto fresh_lds = [&]() {
+        unsigned int z = 0;
+        asm volatile("; LDS base, opaque to code motion" : "+s"(z));
+        unsigned char* base = dyn_smem + z;
+        Rl = reinterpret_cast<double*>(base);
+        unsigned char* ereg = base + r_bytes;
+        E = reinterpret_cast<double*>(ereg);
+        hist = reinterpret_cast<int*>(ereg);
+        slice = reinterpret_cast<unsigned long long*>(ereg);
+        colbuf = reinterpret_cast<double*>(ereg);  // 2 x kBlkCap, during the factorisations
+        LI = reinterpret_cast<double*>(ereg + e_bytes);
+        LJ = LI + scap * kBlkCap;
+        gaI = LI + fac;                            // kChunk x kBlkCap
+        cX = LI;                                   // kXRows x kBlkCap (after W)
+        bX = LI + kXRows * kBlkCap;                // kXRows x kBlkCap (after W)
+        zT = LI;                                   // kBlkCap x kChunk (after the X update)
+        // Own rows of R: LDS or device memory, fixed at compile time so that
+        // every access is a plain LDS or global instruction.
+        Rown = LDS ? Rl : P.R + (size_t)row0 * n;
+    };
+    fresh_lds();
+    auto fresh = [&]() {
+        fresh_ids();
+        fresh_lds();
+    };
+    const bool timing = P.phase != nullptr && g == 0 && tid == 0;
+    unsigned long long ph[kB2Count] = {};
+    unsigned long long t_last = timing ? wall_clock64() : 0;
+#define B2_PHASE(id)                                                    \
+    do {                                                                \
+        if (timing) {                                                   \
+            const unsigned long long now_ = wall_clock64();             \
+            ph[id] += now_ - t_last;                                    \
+            t_last = now_;                                              \
+        }                                                               \
+    } while (0)
 
     if (LDS) {
         const double* src = P.R + (size_t)row0 * n;
@@ -342,39 +541,45 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         __syncthreads();
     }
 
+    // (A A^T)_{i, I} of rows c0 .. c0 + kChunk of this work-group, as the
+    // value thread tid < kChunk * kBlkCap stores to gaI[tid] (zero outside
+    // the rows and the block).
+    auto fetch_gaI = [&](int c0, int nI) -> double {
+        const int ii = tid / kBlkCap, x = tid - ii * kBlkCap;
+        if (tid < kChunk * kBlkCap && c0 + ii < nrow && x < nI)
+            return P.GA[(size_t)(row0 + c0 + ii) * m + sm.I[x]];
+        return 0.0;
+    };
+
     // Fused pass over own rows: optional update R_i -= z_i (B^T B)_{J,:}, then
     // ||R_i||^2, max_j omega_ij and this work-group's column maxima; publishes
     // the row words and column maxima with `tag`. Thread t handles columns
-    // t, t + kThreads, ... (coalesced), kChunk rows at a time.
-    auto update_and_score = [&](bool upd, int nJ, unsigned int tag) {
-        double cm[SR];
-#pragma unroll
-        for (int u = 0; u < SR; ++u) cm[u] = 0.0;
-        for (int c0 = 0; c0 < nrow; c0 += kChunk) {
+    // t, t + kThreads, ... (coalesced), kChunk rows at a time. With `upd`,
+    // gaI holds the first chunk's (A A^T)_{i, I} on entry and E holds W,
+    // zero outside nI x nJ.
+    auto update_and_score = [&](bool upd, int nI, int nJ, unsigned int tag) {
+        for (int c0 = 0; upd && c0 < nrow; c0 += kChunk) {
             const int cr = min(kChunk, nrow - c0);
-            if (upd) {
-                // z_i = (A A^T)_{i, I} W for the chunk's rows: the entries
-                // (A A^T)_{i, I} are loaded once, all in flight together.
-                const int nI = sm.nI;
-                for (int e = tid; e < cr * nI; e += kThreads) {
-                    const int ii = e / nI, x = e - ii * nI;
-                    gaI[ii * kBlkCap + x] = P.GA[(size_t)(row0 + c0 + ii) * m + sm.I[x]];
+            {
+                if (c0 > 0) {
+                    const double gv = fetch_gaI(c0, nI);
+                    __syncthreads();   // every thread is done with the previous chunk
+                    if (tid < kChunk * kBlkCap) gaI[tid] = gv;
+                    __syncthreads();
                 }
-                __syncthreads();
-                for (int e = tid; e < cr * nJ; e += kThreads) {
-                    const int ii = e / nJ, y = e - ii * nJ;
+                // z_i = (A A^T)_{i, I} W, stored transposed (zT[y][i]); the
+                // terms past nI are exact zeros.
+                if (tid < kChunk * kBlkCap) {
+                    const int ii = tid & (kChunk - 1), y = tid / kChunk;
                     double a0 = 0.0, a1 = 0.0;
-                    int x = 0;
-                    for (; x + 1 < nI; x += 2) {
+#pragma unroll
+                    for (int x = 0; x < kBlkCap; x += 2) {
                         a0 += gaI[ii * kBlkCap + x] * E[x * ldE + y];
                         a1 += gaI[ii * kBlkCap + x + 1] * E[(x + 1) * ldE + y];
                     }
-                    if (x < nI) a0 += gaI[ii * kBlkCap + x] * E[x * ldE + y];
-                    z[ii * tcap + y] = a0 + a1;
+                    zT[y * kChunk + ii] = a0 + a1;
                 }
                 __syncthreads();
-            }
-            if (upd) {
                 // R_i -= z_i (B^T B)_{J,:}: columns in groups of 4 per thread,
                 // so each z value read from LDS serves four columns.
 #pragma unroll
@@ -385,28 +590,30 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
 #pragma unroll
                         for (int ii = 0; ii < kChunk; ++ii) acc[u][ii] = 0.0;
                     // Rows J_y of B^T B, 8 at a time with every load issued
-                    // before the multiply-adds that use them.
+                    // before the multiply-adds that use them (row index made
+                    // uniform, column clamped: the loads need no branch).
+                    unsigned int jc[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) jc[u] = (unsigned int)min(tid + (u0 + u) * kThreads, n - 1);
                     for (int y0 = 0; y0 < nJ; y0 += 8) {
                         double gb[8][4];
 #pragma unroll
                         for (int yy = 0; yy < 8; ++yy) {
-                            const int y = y0 + yy;
-                            const double* gbr = P.GB + (size_t)sm.J[y < nJ ? y : 0] * n;
+                            const int Jy = __builtin_amdgcn_readfirstlane(sm.J[min(y0 + yy, nJ - 1)]);
+                            const double* gbr = P.GB + (size_t)Jy * n;
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int j = tid + (u0 + u) * kThreads;
-                                gb[yy][u] = (y < nJ && u0 + u < SR && j < n) ? gbr[j] : 0.0;
-                            }
+                            for (int u = 0; u < 4; ++u) gb[yy][u] = (u0 + u < SR) ? gbr[jc[u]] : 0.0;
                         }
 #pragma unroll
                         for (int yy = 0; yy < 8; ++yy) {
                             if (y0 + yy < nJ) {
+                                double zv[kChunk];
 #pragma unroll
-                                for (int ii = 0; ii < kChunk; ++ii) {
-                                    const double zv = z[ii * tcap + y0 + yy];
+                                for (int ii = 0; ii < kChunk; ++ii) zv[ii] = zT[(y0 + yy) * kChunk + ii];
 #pragma unroll
-                                    for (int u = 0; u < 4; ++u) acc[u][ii] += zv * gb[yy][u];
-                                }
+                                for (int ii = 0; ii < kChunk; ++ii)
+#pragma unroll
+                                    for (int u = 0; u < 4; ++u) acc[u][ii] += zv[ii] * gb[yy][u];
                             }
                         }
                     }
@@ -421,23 +628,38 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
                     }
                 }
             }
-            // Norms, row maxima and column maxima of omega over the chunk's
-            // rows (the same thread's columns, so no barrier is needed).
+        }
+        if (upd) B2_PHASE(kB2RUpd);
+        fresh();
+        // Norms, row maxima and column maxima of omega, kChunk rows at a time
+        // (every thread reads its own columns, so no barrier after the
+        // update). With one chunk a column's maximum over the work-group's
+        // rows is final once its rows are scored and is published at once;
+        // with several it is carried over the chunks in cm.
+        // Every global load of the pass is issued before its first store: a
+        // wave's vector memory operations are counted in issue order, so a
+        // load behind a store would also wait for the store.
+        auto score = [&](int c0, int cr, double (&cm)[SR], bool carry) {
             double aa[kChunk];
 #pragma unroll
             for (int ii = 0; ii < kChunk; ++ii) aa[ii] = (ii < cr) ? P.a[row0 + c0 + ii] : 0.0;
+            double bv[SR];
+#pragma unroll
+            for (int u = 0; u < SR; ++u) bv[u] = P.b[min(tid + u * kThreads, n - 1)];
             double v[2 * kChunk];
 #pragma unroll
             for (int ii = 0; ii < kChunk; ++ii) {
                 v[ii] = 0.0;            // ||R_i||^2 partial
                 v[kChunk + ii] = 0.0;   // max_j omega_ij partial
             }
+            double cmo[SR];
 #pragma unroll
             for (int u = 0; u < SR; ++u) {
                 const int j = tid + u * kThreads;
+                cmo[u] = 0.0;
                 if (j < n) {
-                    const double bj = P.b[j];
-                    double cmu = cm[u];
+                    const double bj = bv[u];
+                    double cmu = carry ? cm[u] : 0.0;
 #pragma unroll
                     for (int ii = 0; ii < kChunk; ++ii) {
                         if (ii < cr) {
@@ -451,89 +673,116 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
                             }
                         }
                     }
-                    cm[u] = cmu;
+                    if (carry) cm[u] = cmu;
+                    cmo[u] = cmu;
                 }
             }
-            block_sums_maxes<kChunk, kChunk>(v, sm);
+            if (!carry) {
 #pragma unroll
-            for (int ii = 0; ii < kChunk; ++ii) {
-                if (ii < cr && tid == ii) xstore(&rx[row0 + c0 + ii], pack_word(v[ii], tag));
-                if (ii < cr && tid == kChunk + ii)
-                    xstore(&hx[row0 + c0 + ii], pack_word(v[kChunk + ii], tag));
+                for (int u = 0; u < SR; ++u) {
+                    const int j = tid + u * kThreads;
+                    if (j < n) xstore(&cx[(size_t)g * n + j], pack_word(cmo[u], tag));
+                }
             }
-        }
+            static_assert(2 * kChunk == 16, "the scoring reduction takes 8 sums and 8 maxima");
+            const double tot = block_reduce_scatter16(v, sm);
+            if (tid < cr) xstore(&rx[row0 + c0 + tid], pack_word(tot, tag));
+            else if (tid >= kChunk && tid - kChunk < cr) xstore(&hx[row0 + c0 + tid - kChunk], pack_word(tot, tag));
+        };
+        if (nrow <= kChunk) {
+            double none[SR];
+            score(0, nrow, none, false);
+        } else {
+            double cm[SR];
 #pragma unroll
-        for (int u = 0; u < SR; ++u) {
-            const int j = tid + u * kThreads;
-            if (j < n) xstore(&cx[(size_t)g * n + j], pack_word(cm[u], tag));
+            for (int u = 0; u < SR; ++u) cm[u] = 0.0;
+            for (int c0 = 0; c0 < nrow; c0 += kChunk) score(c0, min(kChunk, nrow - c0), cm, true);
+#pragma unroll
+            for (int u = 0; u < SR; ++u) {
+                const int j = tid + u * kThreads;
+                if (j < n) xstore(&cx[(size_t)g * n + j], pack_word(cm[u], tag));
+            }
         }
     };
 
+    // B_{l, J_y} for rows l0 .. l0 + kXRows of this work-group's X^T, as the
+    // value thread kThreads - kXRows * kBlkCap + e stores to bX[e].
+    constexpr int kBxT0 = kThreads - kXRows * kBlkCap;
+    auto fetch_bX = [&](int l0, int nJ) -> double {
+        const int e = tid - kBxT0, l = e / kBlkCap, y = e - l * kBlkCap;
+        if (e >= 0 && l0 + l < nx && y < nJ) return P.B[(size_t)(xc0 + l0 + l) * n + sm.J[y]];
+        return 0.0;
+    };
+
     // X^T rows of this work-group, kXRows at a time:
-    //   c[l][x] = sum_y W[x][y] B[l][J_y] (LDS), then
+    //   c[l][x] = sum_y W[x][y] B[l][J_y] (LDS, stored as cX[x][l]), then
     //   X^T[l, s] += sum_x c[l][x] A[I_x][s], a thread per column s,
-    // with the entries of A loaded 8 at a time, all in flight together.
+    // with the column's entries of A loaded before c is formed, all in
+    // flight together. bpre: this thread's fetch_bX(0) value. W (in E) and
+    // c are zero outside the block, so the sums run over kBlkCap terms.
     // Leaves the squared-error partial of the updated rows in sm.err_w.
-    auto update_x = [&](int nI, int nJ) {
+    auto update_x = [&](int nI, int nJ, double bpre) {
         double ep = 0.0;
         for (int l0 = 0; l0 < nx; l0 += kXRows) {
             const int lc = min(kXRows, nx - l0);
-            for (int e = tid; e < lc * nI; e += kThreads) {
-                const int l = e / nI, x = e - l * nI;
-                const double* brow = P.B + (size_t)(xc0 + l0 + l) * n;
-                double a0 = 0.0, a1 = 0.0;
-                for (int y0 = 0; y0 < nJ; y0 += 8) {
-                    double bv[8];
+            for (int s0 = 0; s0 < p; s0 += kThreads) {
+                const int s2 = s0 + tid, s2c = min(s2, p - 1);
+                double av[kBlkCap];
 #pragma unroll
-                    for (int yy = 0; yy < 8; ++yy)
-                        bv[yy] = (y0 + yy < nJ) ? brow[sm.J[y0 + yy]] : 0.0;
-#pragma unroll
-                    for (int yy = 0; yy < 8; yy += 2) {
-                        if (y0 + yy < nJ) a0 += E[x * ldE + y0 + yy] * bv[yy];
-                        if (y0 + yy + 1 < nJ) a1 += E[x * ldE + y0 + yy + 1] * bv[yy + 1];
-                    }
+                for (int x = 0; x < kBlkCap; ++x) {
+                    const int Ix = __builtin_amdgcn_readfirstlane(sm.I[x < nI ? x : 0]);
+                    av[x] = P.A[(size_t)Ix * p + (unsigned int)s2c];
                 }
-                cX[l * kBlkCap + x] = a0 + a1;
-            }
-            __syncthreads();
-            for (int s2 = tid; s2 < p; s2 += kThreads) {
-                double acc[kXRows];
+                if (s0 == 0) {
+                    const double bv = (l0 == 0) ? bpre : fetch_bX(l0, nJ);
+                    if (tid >= kBxT0) bX[tid - kBxT0] = bv;
+                    __syncthreads();
+                    if (tid < kXRows * kBlkCap) {
+                        const int x = tid / kXRows, l = tid - x * kXRows;
+                        double a0 = 0.0, a1 = 0.0;
+#pragma unroll 4
+                        for (int y = 0; y < kBlkCap; y += 2) {
+                            a0 += E[x * ldE + y] * bX[l * kBlkCap + y];
+                            a1 += E[x * ldE + y + 1] * bX[l * kBlkCap + y + 1];
+                        }
+                        cX[x * kXRows + l] = a0 + a1;
+                    }
+                    __syncthreads();
+                }
+                // Rows of the chunk two at a time, with A's entries kept in
+                // registers across the pairs.
+                for (int lp = 0; lp < lc; lp += 2) {
+                    double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
-                for (int l = 0; l < kXRows; ++l) acc[l] = 0.0;
-                for (int x0 = 0; x0 < nI; x0 += 8) {
-                    double av[8];
+                    for (int x = 0; x < kBlkCap; ++x) {
+                        acc0 += cX[x * kXRows + lp] * av[x];
+                        acc1 += cX[x * kXRows + lp + 1] * av[x];
+                    }
+                    if (s2 < p) {
 #pragma unroll
-                    for (int xx = 0; xx < 8; ++xx)
-                        av[xx] = (x0 + xx < nI) ? P.A[(size_t)sm.I[x0 + xx] * p + s2] : 0.0;
-#pragma unroll
-                    for (int xx = 0; xx < 8; ++xx) {
-                        if (x0 + xx < nI) {
-#pragma unroll
-                            for (int l = 0; l < kXRows; ++l) acc[l] += cX[l * kBlkCap + x0 + xx] * av[xx];
+                        for (int l2 = 0; l2 < 2; ++l2) {
+                            const int l = lp + l2;
+                            if (l < lc) {
+                                const size_t off = (size_t)(xc0 + l0 + l) * p + s2;
+                                const double nv = P.Xt[off] + (l2 ? acc1 : acc0);
+                                P.Xt[off] = nv;
+                                if (P.Xref_t) {
+                                    const double d = nv - P.Xref_t[off];
+                                    ep += d * d;
+                                }
+                            }
                         }
                     }
                 }
-#pragma unroll
-                for (int l = 0; l < kXRows; ++l) {
-                    if (l < lc) {
-                        const size_t off = (size_t)(xc0 + l0 + l) * p + s2;
-                        const double nv = P.Xt[off] + acc[l];
-                        P.Xt[off] = nv;
-                        if (P.Xref_t) {
-                            const double d = nv - P.Xref_t[off];
-                            ep += d * d;
-                        }
-                    }
-                }
             }
-            __syncthreads();
+            __syncthreads();   // before the next chunk rewrites bX and cX
         }
         ep = wave_sum(ep);
         if (lane == 0) sm.err_w[wv] = ep;
     };
 
     // ---- Set-up: the first row words, column maxima and error partial.
-    update_and_score(false, 0, seq_tag(0));
+    update_and_score(false, 0, 0, seq_tag(0));
     {
         double ep = 0.0;
         if (P.Xref_t) {
@@ -548,26 +797,22 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         if (tid == 0) xstore(&px[g], pack_word(v[0], seq_tag(0)));
     }
 
-    const bool timing = P.phase != nullptr && g == 0 && tid == 0;
-    unsigned long long ph[kB2Count] = {0, 0, 0, 0, 0, 0, 0, 0};
-    unsigned long long t_last = timing ? wall_clock64() : 0;
-#define B2_PHASE(id)                                                    \
-    do {                                                                \
-        if (timing) {                                                   \
-            const unsigned long long now_ = wall_clock64();             \
-            ph[id] += now_ - t_last;                                    \
-            t_last = now_;                                              \
-        }                                                               \
-    } while (0)
     const int cs = (max(m, n) + kThreads - 1) / kThreads;   // chunk per thread (<= SR)
-    const int rb = min(m, tid * cs), rcnt = min(m, rb + cs) - rb;
-    const int cb = min(n, tid * cs), ccnt = min(n, cb + cs) - cb;
+    int rb, rcnt, cb, ccnt;
     double S0 = -1.0, S = 0.0, err = NAN;
     long long k = 0;
     int status = kMaxIter, last_nI = 0;
     bool ok = true;
     const bool has_ref = P.Xref_t != nullptr;
+    if (timing) t_last = wall_clock64();
     while (ok) {
+        {
+            fresh();
+            rb = min(m, tid * cs);
+            rcnt = min(m, rb + cs) - rb;
+            cb = min(n, tid * cs);
+            ccnt = min(n, cb + cs) - cb;
+        }
         const unsigned int tag = seq_tag(k);
         // ---- B. Row words, error partials, and a slice of the column maxima.
         for (int c = tid; c < ncs; c += kThreads) slice[c] = 0ull;
@@ -633,6 +878,7 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         if (k >= P.max_iters) { status = kMaxIter; break; }
         B2_PHASE(kB2Rows);
 
+        fresh();
         // ---- C. Column maxima; selection of I and J.
         double gg[SR];
         if (!poll_words<double, SR>(gx + cb, ccnt, tag, gg, P.sync, P.poll_sleep)) sm.fail = 1;
@@ -651,60 +897,74 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         __syncthreads();   // every thread is past its use of `slice` (same LDS as hist)
         if (sm.fail) { ok = false; break; }
         B2_PHASE(kB2Cols);
+        fresh();
         select_top<SR>(kr, rb, rcnt, kc, cb, ccnt, scap, tcap, hist, sm);
         B2_PHASE(kB2Select);
         const int nsR = sm.nsel[0], nsC = sm.nsel[1];
-        // Gram blocks of the ranked candidates, then an in-place right-looking
-        // Cholesky in rank order that skips dependent candidates.
-        for (int e = tid; e < nsR * nsR; e += kThreads) {
-            const int x = e / nsR, y = e - x * nsR;
-            LI[x * scap + y] = P.GA[(size_t)sm.sidx[0][x] * m + sm.sidx[0][y]];
+        fresh();
+        // Gram blocks of the ranked candidates (lower triangles, zero
+        // elsewhere), then an in-place right-looking Cholesky in rank order
+        // that skips dependent candidates.
+        for (int e = tid; e < scap * kBlkCap; e += kThreads) {
+            const int x = e / kBlkCap, y = e - x * kBlkCap;
+            LI[e] = (x < nsR && y <= x) ? P.GA[(size_t)sm.sidx[0][x] * m + sm.sidx[0][y]] : 0.0;
         }
-        for (int e = tid; e < nsC * nsC; e += kThreads) {
-            const int x = e / nsC, y = e - x * nsC;
-            LJ[x * tcap + y] = P.GB[(size_t)sm.sidx[1][x] * n + sm.sidx[1][y]];
+        for (int e = tid; e < tcap * kBlkCap; e += kThreads) {
+            const int x = e / kBlkCap, y = e - x * kBlkCap;
+            LJ[e] = (x < nsC && y <= x) ? P.GB[(size_t)sm.sidx[1][x] * n + sm.sidx[1][y]] : 0.0;
         }
         if (tid < nsR) sm.diag[0][tid] = P.GA[(size_t)sm.sidx[0][tid] * (m + 1)];
         else if (tid >= kWave && tid < kWave + nsC)
             sm.diag[1][tid - kWave] = P.GB[(size_t)sm.sidx[1][tid - kWave] * (n + 1)];
         __syncthreads();
-        const int npiv = max(nsR, nsC);
-        // Thread t owns entries (t / 32 + 16 h, t % 32), h = 0, 1, of both
-        // Gram blocks (at most 32 x 32 each).
-        const int er0 = tid >> 5, ec = tid & 31;
-        for (int c = 0; c < npiv; ++c) {
-            // Every thread reads the pivot and takes the same decision.
-            const bool doR = c < nsR, doC = c < nsC;
-            const double dR = doR ? LI[c * scap + c] : 0.0;
-            const double dC = doC ? LJ[c * tcap + c] : 0.0;
-            const bool keepR = doR && dR > P.tau * sm.diag[0][c];
-            const bool keepC = doC && dC > P.tau * sm.diag[1][c];
-            if (tid == 0) {
-                if (doR) { sm.keep[0][c] = keepR; sm.dpiv[0][c] = dR; }
-                if (doC) { sm.keep[1][c] = keepC; sm.dpiv[1][c] = dC; }
-            }
-            // Trailing update of the lower triangle below the pivot:
-            // G[r][q] -= G[r][c] G[q][c] / d for c < q <= r.
-            if (keepR) {
-                const double rdR = 1.0 / dR;
+        B2_PHASE(kB2Gram);
+        // One wave per Gram block (wave 0: A_I A_I^T, wave 1: B_J^T B_J), no
+        // block barrier per pivot. Lane l holds row l / 2 of the block, the
+        // entries of columns of parity l % 2, in registers; for pivot c the
+        // lanes holding column c put it in LDS and every lane reads the
+        // pivot, its own G[r][c] and the G[q][c] of its columns from there.
+        // Trailing update: G[r][q] -= G[r][c] G[q][c] / d for c < q <= r.
+        if (wv < 2) {
+            const int side = wv, ns = side ? nsC : nsR;
+            double* G = side ? LJ : LI;
+            double* col = colbuf + side * kBlkCap;
+            const int r = lane >> 1, h = lane & 1;
+            double gr[kBlkCap / 2];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int r = er0 + 16 * h;
-                    if (r < nsR && ec > c && ec <= r)
-                        LI[r * scap + ec] -= LI[r * scap + c] * LI[ec * scap + c] * rdR;
+            for (int i = 0; i < kBlkCap / 2; ++i) gr[i] = (r < ns) ? G[r * kBlkCap + 2 * i + h] : 0.0;
+#pragma unroll
+            for (int c = 0; c < kBlkCap; ++c) {
+                if (c < ns) {
+                    if (h == (c & 1)) col[r] = gr[c >> 1];
+                    wave_lds_sync();
+                    const double d = col[c];
+                    const bool keep = d > P.tau * sm.diag[side][c];
+                    if (lane == 0) {
+                        sm.keep[side][c] = keep;
+                        sm.dpiv[side][c] = d;
+                    }
+                    if (keep) {
+                        // Entries outside c < q <= r < ns take a zero factor:
+                        // their term is an exact zero.
+                        const double rd = 1.0 / d;
+                        const double grc = col[r];
+#pragma unroll
+                        for (int i = c >> 1; i < kBlkCap / 2; ++i) {
+                            const int qq = 2 * i + h;
+                            const double f = (qq > c && qq <= r && r < ns) ? rd : 0.0;
+                            gr[i] -= grc * col[qq] * f;
+                        }
+                    }
+                    wave_lds_sync();
                 }
             }
-            if (keepC) {
-                const double rdC = 1.0 / dC;
+            if (r < ns) {
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int r = er0 + 16 * h;
-                    if (r < nsC && ec > c && ec <= r)
-                        LJ[r * tcap + ec] -= LJ[r * tcap + c] * LJ[ec * tcap + c] * rdC;
-                }
+                for (int i = 0; i < kBlkCap / 2; ++i) G[r * kBlkCap + 2 * i + h] = gr[i];
             }
-            __syncthreads();
         }
+        __syncthreads();
+        B2_PHASE(kB2Chol);
         // Compact the kept candidates into I, J and their Cholesky factors.
         if (tid == 0) {
             int r = 0;
@@ -719,42 +979,47 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         __syncthreads();
         const int nI = sm.nI, nJ = sm.nJ;
         {
-            // L[x][y] = G[px][py] / sqrt(d_py) (y < x), sqrt(d_px) on the diagonal.
-            double lv[2], lw[2];
-            int cntI = 0, cntJ = 0;
-            for (int e = tid, u = 0; e < nI * nI && u < 2; e += kThreads, ++u) {
-                const int x = e / nI, y = e - x * nI;
-                const int px_ = sm.I[x], py_ = sm.I[y];
-                lv[u] = (y > x) ? 0.0
-                        : (y == x) ? sqrt(sm.dpiv[0][px_])
-                                   : LI[px_ * scap + py_] / sqrt(sm.dpiv[0][py_]);
-                ++cntI;
-            }
-            for (int e = tid, u = 0; e < nJ * nJ && u < 2; e += kThreads, ++u) {
-                const int x = e / nJ, y = e - x * nJ;
-                const int px_ = sm.J[x], py_ = sm.J[y];
-                lw[u] = (y > x) ? 0.0
-                        : (y == x) ? sqrt(sm.dpiv[1][px_])
-                                   : LJ[px_ * tcap + py_] / sqrt(sm.dpiv[1][py_]);
-                ++cntJ;
-            }
-            __syncthreads();
-            for (int u = 0; u < cntI; ++u) {
-                const int e = tid + u * kThreads, x = e / nI, y = e - x * nI;
-                LI[x * scap + y] = lv[u];
-            }
-            for (int u = 0; u < cntJ; ++u) {
-                const int e = tid + u * kThreads, x = e / nJ, y = e - x * nJ;
-                LJ[x * tcap + y] = lw[u];
+            // The factors L (L[x][y] = G[px][py] / sqrt(d_py) for y < x, with
+            // L[x][x] = sqrt(d_px)) enter the solves only through the products
+            // L[x][y] / L[y][y] (forward) and L[x][y] / L[x][x] (backward),
+            // which are formed here: M[a][b] = L[max(a, b)][min(a, b)] / L[b][b]
+            // for a != b, zero on the diagonal and outside the block, stored
+            // transposed (row b holds column b of M, the factors of pivot b);
+            // rd[x] = 1 / L[x][x] (zero past the block).
+            double mv[2][2];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const double* G = side ? LJ : LI;
+                const int* pos = side ? sm.J : sm.I;
+                const int nk = side ? nJ : nI;
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int e = tid + u * kThreads, b = e / kBlkCap, a = e - b * kBlkCap;
+                    double v = 0.0;
+                    if (a < nk && b < nk && a != b) {
+                        const int ph = pos[max(a, b)], pl = pos[min(a, b)];
+                        const double l = G[ph * kBlkCap + pl] / sqrt(sm.dpiv[side][pl]);
+                        v = l * (1.0 / sqrt(sm.dpiv[side][pos[b]]));
+                    }
+                    mv[side][u] = v;
+                }
             }
             __syncthreads();
-            if (tid < nI) {
-                sm.I[tid] = sm.sidx[0][sm.I[tid]];
-                sm.rd[0][tid] = 1.0 / LI[tid * scap + tid];
-            } else if (tid >= kWave && tid < kWave + nJ) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                double* G = side ? LJ : LI;
+                const int ne = (side ? tcap : scap) * kBlkCap;
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (tid + u * kThreads < ne) G[tid + u * kThreads] = mv[side][u];
+            }
+            if (tid < kBlkCap) {
+                sm.rd[0][tid] = tid < nI ? 1.0 / sqrt(sm.dpiv[0][sm.I[tid]]) : 0.0;
+                if (tid < nI) sm.I[tid] = sm.sidx[0][sm.I[tid]];
+            } else if (tid >= kWave && tid < kWave + kBlkCap) {
                 const int y = tid - kWave;
-                sm.J[y] = sm.sidx[1][sm.J[y]];
-                sm.rd[1][y] = 1.0 / LJ[y * tcap + y];
+                sm.rd[1][y] = y < nJ ? 1.0 / sqrt(sm.dpiv[1][sm.J[y]]) : 0.0;
+                if (y < nJ) sm.J[y] = sm.sidx[1][sm.J[y]];
             }
             __syncthreads();
         }
@@ -769,6 +1034,11 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         if (nI == 0 || nJ == 0) { status = kEInval; break; }
         B2_PHASE(kB2Factor);
 
+        fresh();
+        // Operands of the X and R updates that need only I and J, fetched
+        // first (ahead of the stores below) and in flight while R_IJ is.
+        const double gaI0 = fetch_gaI(0, nI);
+        const double bX0 = fetch_bX(0, nJ);
         // ---- D. R_IJ from the owners of the rows in I. Every word of the
         // s_cap x t_cap block is rewritten every step (zeros outside I x J;
         // work-group 0 writes the rows past nI), so no word can keep a value
@@ -803,90 +1073,63 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
                 if (u < cnt) E[(e / nJ) * ldE + (e % nJ)] = vals[u];
             }
         }
+        if (tid < kChunk * kBlkCap) gaI[tid] = gaI0;
         __syncthreads();
         if (sm.fail) { ok = false; break; }
         B2_PHASE(kB2E);
-        // W = (A_I A_I^T)^{-1} R_IJ (B_J^T B_J)^{-1}, in place in E, by
-        // right-looking triangular solves over the whole block (one barrier
-        // per pivot): first L_I and L_I^T on the columns of E, then L_J and
-        // L_J^T on its rows. Entry (x, y) of E belongs to thread
-        // (x / 16 + ...), see below; rows are kept unscaled until the end of
-        // each sweep.
-        {
-            // Thread t handles entries (t / 32 + 16 h, t % 32) of E, h = 0, 1.
-            const int ex0 = tid >> 5, ey = tid & 31;
-            // L_I: forward (E[x'] -= L[x'][x] / L[x][x] * E[x] for x' > x).
-            for (int x = 0; x + 1 < nI; ++x) {
-                const double rx = sm.rd[0][x];
+        fresh();
+        // W = (A_I A_I^T)^{-1} R_IJ (B_J^T B_J)^{-1}, in place in E, by one
+        // wave with no block barrier: lane y < 32 takes column y of E
+        // into registers and solves with L_I (forward, pivots ascending) and
+        // L_I^T (backward, pivots descending), scaling by 1 / L[x][x] after
+        // each sweep; through LDS, lane x then takes row x and does the same
+        // with L_J and L_J^T. Right-looking: pivot x subtracts M[r][x] e[x]
+        // from every other entry r it reaches, independent multiply-adds
+        // whose factors are one contiguous row of the stored M^T. Entries
+        // outside the block are zeros, whose terms are exact zeros, and E
+        // is left zero outside nI x nJ. Lanes 32-63 stay idle: every factor
+        // is a broadcast LDS read, whose cost grows with the active lanes.
+        if (tid < kBlkCap) {
+            const int y = lane;
+            double ev[kBlkCap];
+            // Entries outside the block are cleared by a bit mask (no branch;
+            // the LDS there may hold any bit pattern).
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int r = ex0 + 16 * h;
-                    if (r > x && r < nI && ey < nJ)
-                        E[r * ldE + ey] -= LI[r * scap + x] * rx * E[x * ldE + ey];
-                }
-                __syncthreads();
+            for (int x = 0; x < kBlkCap; ++x) {
+                const long long keep = (x < nI && y < nJ) ? -1ll : 0ll;
+                ev[x] = __longlong_as_double(__double_as_longlong(E[x * ldE + y]) & keep);
             }
+            tri_sweep<true>(ev, LI, nI, scap);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = ex0 + 16 * h;
-                if (r < nI && ey < nJ) E[r * ldE + ey] *= sm.rd[0][r];
-            }
-            __syncthreads();
-            // L_I^T: backward (E[x'] -= L[x][x'] / L[x][x] * E[x] for x' < x).
-            for (int x = nI - 1; x > 0; --x) {
-                const double rx = sm.rd[0][x];
+            for (int r = 0; r < kBlkCap; ++r) ev[r] *= sm.rd[0][r];
+            tri_sweep<false>(ev, LI, nI, scap);
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int r = ex0 + 16 * h;
-                    if (r < x && ey < nJ) E[r * ldE + ey] -= LI[x * scap + r] * rx * E[x * ldE + ey];
-                }
-                __syncthreads();
-            }
+            for (int r = 0; r < kBlkCap; ++r) ev[r] *= sm.rd[0][r];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = ex0 + 16 * h;
-                if (r < nI && ey < nJ) E[r * ldE + ey] *= sm.rd[0][r];
-            }
-            __syncthreads();
-            // L_J on the rows: column y plays the role of row x above.
-            for (int y = 0; y + 1 < nJ; ++y) {
-                const double ry = sm.rd[1][y];
+            for (int x = 0; x < kBlkCap; ++x) E[x * ldE + y] = ev[x];
+            wave_lds_sync();
+            const int xr = lane;
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int r = ex0 + 16 * h;
-                    if (r < nI && ey > y && ey < nJ)
-                        E[r * ldE + ey] -= LJ[ey * tcap + y] * ry * E[r * ldE + y];
-                }
-                __syncthreads();
-            }
+            for (int yy = 0; yy < kBlkCap; ++yy) ev[yy] = E[xr * ldE + yy];
+            wave_lds_sync();
+            tri_sweep<true>(ev, LJ, nJ, tcap);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = ex0 + 16 * h;
-                if (r < nI && ey < nJ) E[r * ldE + ey] *= sm.rd[1][ey];
-            }
-            __syncthreads();
-            for (int y = nJ - 1; y > 0; --y) {
-                const double ry = sm.rd[1][y];
+            for (int c = 0; c < kBlkCap; ++c) ev[c] *= sm.rd[1][c];
+            tri_sweep<false>(ev, LJ, nJ, tcap);
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int r = ex0 + 16 * h;
-                    if (r < nI && ey < y) E[r * ldE + ey] -= LJ[y * tcap + ey] * ry * E[r * ldE + y];
-                }
-                __syncthreads();
-            }
+            for (int c = 0; c < kBlkCap; ++c) ev[c] *= sm.rd[1][c];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = ex0 + 16 * h;
-                if (r < nI && ey < nJ) E[r * ldE + ey] *= sm.rd[1][ey];
-            }
-            __syncthreads();
+            for (int yy = 0; yy < kBlkCap; ++yy) E[xr * ldE + yy] = ev[yy];
         }
+        __syncthreads();
+        fresh();
         // ---- X and R updates; A of step k + 1.
         B2_PHASE(kB2W);
-        update_x(nI, nJ);
+        update_x(nI, nJ, bX0);
         B2_PHASE(kB2X);
         const unsigned int ntag = seq_tag(k + 1);
-        update_and_score(true, nJ, ntag);
+        fresh();
+        update_and_score(true, nI, nJ, ntag);
         if (tid == 0) {
             double e = 0.0;
             for (int w2 = 0; w2 < kWaves; ++w2) e += sm.err_w[w2];
@@ -912,9 +1155,8 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
 size_t block2_lds_bytes(int rpw, int n, int W, int s_cap, int t_cap, bool r_in_lds) {
     const int ncs = (n + W - 1) / W;
     size_t b = r_in_lds ? (((size_t)rpw * n * 8 + 15) & ~(size_t)15) : 0;
-    b += block2_ereg_bytes(s_cap, t_cap, ncs);
-    b += ((size_t)s_cap * s_cap + (size_t)t_cap * t_cap + (size_t)kChunk * t_cap +
-          (size_t)kChunk * kBlkCap + (size_t)kXRows * kBlkCap) * 8;
+    b += block2_ereg_bytes(ncs);
+    b += ((size_t)block2_fac_doubles(s_cap, t_cap) + (size_t)kChunk * kBlkCap) * 8;
     return b;
 }
 

@@ -230,13 +230,20 @@ struct Block2Params {
     unsigned long long* phase;   // optional: per-phase wall-clock ticks of work-group 0
 };
 
-// Bytes of the block kernel's LDS region shared by R_IJ / W, the radix
-// histograms and the column slice of exchange B.
-__host__ __device__ inline size_t block2_ereg_bytes(int s_cap, int t_cap, int ncs) {
-    size_t e = (size_t)s_cap * (t_cap + 1) * 8;
+// Bytes of the block kernel's LDS region shared by R_IJ / W (kBlkCap rows
+// of kBlkCap + 1), the radix histograms and the column slice of exchange B.
+__host__ __device__ inline size_t block2_ereg_bytes(int ncs) {
+    size_t e = (size_t)kBlkCap * (kBlkCap + 1) * 8;
     e = e > 1024 * sizeof(int) ? e : 1024 * sizeof(int);
     e = e > (size_t)ncs * 8 ? e : (size_t)ncs * 8;
     return (e + 15) & ~(size_t)15;
+}
+// Doubles of the block kernel's factor region: L_I and L_J (s_cap and t_cap
+// rows of kBlkCap), later the X update's two kXRows x kBlkCap arrays and the
+// R update's kBlkCap x kChunk array (kXRows = kChunk = 8).
+__host__ __device__ inline int block2_fac_doubles(int s_cap, int t_cap) {
+    const int f = (s_cap + t_cap) * kBlkCap;
+    return f > 2 * 8 * kBlkCap ? f : 2 * 8 * kBlkCap;
 }
 hipError_t launch_block2(const Block2Params& P, size_t lds_bytes, hipStream_t s);
 size_t block2_lds_bytes(int rpw, int n, int W, int s_cap, int t_cap, bool r_in_lds);
