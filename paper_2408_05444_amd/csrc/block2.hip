@@ -245,7 +245,7 @@ __device__ __forceinline__ void select_top(const unsigned long long (&kr)[SR], i
         // early once the bin that holds its threshold has at most kBinMax
         // keys: those are gathered and ranked directly, which gives the same
         // threshold key and count of equal keys to take.
-        constexpr int kBinMax = 2 * kWave;
+        constexpr int kBinMax = kWave;
         unsigned long long* bink = reinterpret_cast<unsigned long long*>(hist + 1024);
         bool doneR = !radR || startR < 0, doneC = !radC || startC < 0;
         const int dstart = max(startR, startC);
@@ -307,20 +307,25 @@ __device__ __forceinline__ void select_top(const unsigned long long (&kr)[SR], i
                 __syncthreads();
                 if (wv < 2 && (wv == 0 ? exR : exC)) {
                     // The need-th largest key of the bin (with multiplicity)
-                    // and how many keys equal to it are taken.
-                    const unsigned long long* bk = bink + wv * kBinMax;
+                    // and how many keys equal to it are taken: lane l holds
+                    // key l and compares it with every other lane's.
                     const int cnt = sm.gcnt[wv], need = sm.need[wv];
-                    for (int l = lane; l < cnt; l += kWave) {
-                        const unsigned long long key = bk[l];
-                        int gt = 0, eq = 0;
-                        for (int u = 0; u < cnt; ++u) {
-                            gt += bk[u] > key;
-                            eq += bk[u] == key;
+                    const unsigned long long key = lane < cnt ? bink[wv * kBinMax + lane] : 0ull;
+                    int gt = 0, eq = 0;
+#pragma unroll
+                    for (int u = 0; u < kBinMax; ++u) {
+                        if (u < cnt) {
+                            const unsigned long long ku =
+                                ((unsigned long long)(unsigned int)__builtin_amdgcn_readlane((int)(key >> 32), u)
+                                 << 32) |
+                                (unsigned int)__builtin_amdgcn_readlane((int)key, u);
+                            gt += ku > key;
+                            eq += ku == key;
                         }
-                        if (gt < need && need <= gt + eq) {
-                            sm.prefix[wv] = key;
-                            sm.need[wv] = need - gt;
-                        }
+                    }
+                    if (lane < cnt && gt < need && need <= gt + eq) {
+                        sm.prefix[wv] = key;
+                        sm.need[wv] = need - gt;
                     }
                 }
                 __syncthreads();
@@ -383,16 +388,23 @@ __device__ __forceinline__ void select_top(const unsigned long long (&kr)[SR], i
     }
     __syncthreads();
     // Rank order: count the keys above (and equal keys at lower indices).
+    // Each lane compares its key with the others' taken from registers.
     if (wv < 2) {
         const int ns = sm.nsel[wv];
-        if (lane < ns) {
-            const unsigned long long key = sm.ukey[wv][lane];
-            const int idx = sm.uidx[wv][lane];
-            int rank = 0;
-            for (int u = 0; u < ns; ++u) {
-                const unsigned long long ku = sm.ukey[wv][u];
-                rank += (ku > key) || (ku == key && sm.uidx[wv][u] < idx);
+        const unsigned long long key = lane < ns ? sm.ukey[wv][lane] : 0ull;
+        const int idx = lane < ns ? sm.uidx[wv][lane] : 0;
+        int rank = 0;
+#pragma unroll
+        for (int u = 0; u < kBlkCap; ++u) {
+            if (u < ns) {
+                const unsigned long long ku =
+                    ((unsigned long long)(unsigned int)__builtin_amdgcn_readlane((int)(key >> 32), u) << 32) |
+                    (unsigned int)__builtin_amdgcn_readlane((int)key, u);
+                const int iu = __builtin_amdgcn_readlane(idx, u);
+                rank += (ku > key) || (ku == key && iu < idx);
             }
+        }
+        if (lane < ns) {
             sm.sidx[wv][rank] = idx;
             sm.skey[wv][rank] = key;
         }
