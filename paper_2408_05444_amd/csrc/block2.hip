@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         E = reinterpret_cast<double*>(ereg);
         hist = reinterpret_cast<int*>(ereg);
         slice = reinterpret_cast<unsigned long long*>(ereg);
-        colbuf = reinterpret_cast<double*>(ereg);  // 2 x kBlkCap, during the factorisations
+        colbuf = reinterpret_cast<double*>(ereg);  // 4 x kBlkCap, during the factorisations
         LI = reinterpret_cast<double*>(ereg + e_bytes);
         LJ = LI + scap * kBlkCap;
         gaI = LI + fac;                            // kChunk x kBlkCap
@@ -931,41 +931,60 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         __syncthreads();
         B2_PHASE(kB2Gram);
         // One wave per Gram block (wave 0: A_I A_I^T, wave 1: B_J^T B_J), no
-        // block barrier per pivot. Lane l holds row l / 2 of the block, the
-        // entries of columns of parity l % 2, in registers; for pivot c the
-        // lanes holding column c put it in LDS and every lane reads the
-        // pivot, its own G[r][c] and the G[q][c] of its columns from there.
-        // Trailing update: G[r][q] -= G[r][c] G[q][c] / d for c < q <= r.
+        // block barrier per pivot. Lane l holds row r = l / 2 of the block,
+        // the entries of columns of parity h = l % 2, in registers.
+        // Trailing update of pivot c: G[r][q] -= G[r][c] G[q][c] / d_c for
+        // c < q <= r (d_c the pivot, kept or skipped as above). Pivots go in
+        // pairs (c, c + 1), whose columns sit in the same register of the
+        // two parities: both columns go to LDS at once, and every lane forms
+        // column c + 1 after pivot c's update itself (the same expression
+        // the owning lanes evaluate), so the second pivot needs no second
+        // round trip; each entry then takes the two terms in pivot order.
         if (wv < 2) {
             const int side = wv, ns = side ? nsC : nsR;
             double* G = side ? LJ : LI;
-            double* col = colbuf + side * kBlkCap;
+            double* ca = colbuf + side * 2 * kBlkCap;   // column c
+            double* cb = ca + kBlkCap;                  // column c + 1
             const int r = lane >> 1, h = lane & 1;
             double gr[kBlkCap / 2];
 #pragma unroll
             for (int i = 0; i < kBlkCap / 2; ++i) gr[i] = (r < ns) ? G[r * kBlkCap + 2 * i + h] : 0.0;
+            const double tau = P.tau;
 #pragma unroll
-            for (int c = 0; c < kBlkCap; ++c) {
+            for (int c = 0; c < kBlkCap; c += 2) {
                 if (c < ns) {
-                    if (h == (c & 1)) col[r] = gr[c >> 1];
+                    (h ? cb : ca)[r] = gr[c >> 1];
                     wave_lds_sync();
-                    const double d = col[c];
-                    const bool keep = d > P.tau * sm.diag[side][c];
+                    const bool two = c + 1 < ns;
+                    const double d0 = ca[c];
+                    const bool k0 = d0 > tau * sm.diag[side][c];
+                    const double f0 = k0 ? 1.0 / d0 : 0.0;
+                    // Column c + 1 after pivot c (exact zero term if skipped).
+                    const double g10 = ca[c + 1];
+                    auto col1 = [&](int q) { return __builtin_fma(-(ca[q] * g10), f0, cb[q]); };
+                    const double d1 = col1(c + 1);
+                    const bool k1 = two && d1 > tau * sm.diag[side][two ? c + 1 : c];
+                    const double f1 = k1 ? 1.0 / d1 : 0.0;
                     if (lane == 0) {
-                        sm.keep[side][c] = keep;
-                        sm.dpiv[side][c] = d;
-                    }
-                    if (keep) {
-                        // Entries outside c < q <= r < ns take a zero factor:
-                        // their term is an exact zero.
-                        const double rd = 1.0 / d;
-                        const double grc = col[r];
-#pragma unroll
-                        for (int i = c >> 1; i < kBlkCap / 2; ++i) {
-                            const int qq = 2 * i + h;
-                            const double f = (qq > c && qq <= r && r < ns) ? rd : 0.0;
-                            gr[i] -= grc * col[qq] * f;
+                        sm.keep[side][c] = k0;
+                        sm.dpiv[side][c] = d0;
+                        if (two) {
+                            sm.keep[side][c + 1] = k1;
+                            sm.dpiv[side][c + 1] = d1;
                         }
+                    }
+                    // Entries outside c < q <= r < ns (c + 1 < q for the
+                    // second pivot) take a zero factor: exact zero terms.
+                    const double grc = ca[r];
+                    const double grc1 = col1(r);
+                    if (h == 1 && c + 1 <= r && r < ns) gr[c >> 1] = grc1;
+#pragma unroll
+                    for (int i = (c >> 1) + 1; i < kBlkCap / 2; ++i) {
+                        const int qq = 2 * i + h;
+                        const bool in = qq <= r && r < ns;
+                        const double a0 = in ? f0 : 0.0, a1 = in ? f1 : 0.0;
+                        gr[i] = __builtin_fma(-(grc * ca[qq]), a0, gr[i]);
+                        gr[i] = __builtin_fma(-(grc1 * col1(qq)), a1, gr[i]);
                     }
                     wave_lds_sync();
                 }
