@@ -184,7 +184,10 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     }
     const int W = P.W;
     const bool team = W > 1;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    // Re-derived at the top of every update through an opaque copy, so that
+    // the compiler recomputes per-thread addresses inside the update instead
+    // of carrying them in registers across the loop.
+    int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int m = P.m, n = P.n, p = P.p, q = P.q;
     const int row0 = g * P.rpw;
     const int nrow = max(0, min(P.rpw, m - row0));
@@ -281,8 +284,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     unsigned long long ph[kPhCount] = {0, 0, 0, 0, 0, 0, 0, 0};
     unsigned long long t_last = timing ? wall_clock64() : 0;
     const int cs = (m + kThreads - 1) / kThreads;
-    const int sb = min(m, tid * cs);
-    const int scnt = min(m, sb + cs) - sb;
+    int sb, scnt;
     double S0 = -1.0, S = 0.0, err = NAN;
     long long k = 0;
     int status = kMaxIter, last_set = 0;
@@ -293,6 +295,15 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     // X_ref) are loaded right after the selection, into registers.
     const bool ref_regs = has_ref && nx <= kWaves && p <= kAPre * kWave;
     while (ok) {
+        {
+            int t = threadIdx.x;
+            asm volatile("; thread index, opaque to code motion" : "+v"(t));
+            tid = t;
+            lane = t & (kWave - 1);
+            wv = t / kWave;
+            sb = min(m, tid * cs);
+            scnt = min(m, sb + cs) - sb;
+        }
         const unsigned int tag = seq_tag(k);
         // Draws depend only on (seed, instance, k): every kUTable updates the
         // threads compute the next kUTable of them in parallel (one each), so
