@@ -615,21 +615,40 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
 
 // ---------------------------------------------------------------------------
 // Small instances (m, n, p, q <= kThreads): one work-group holds R, B and
-// X^T in LDS and gives every thread one row of R, so row norms need no
-// reduction, the selection sees one row per thread, and the two dot-product
-// phases are one dot per thread (v_l = R_{i_k} . B_l for l < q, then
-// w_j = sum_l v_l B_lj for j < n), each summed in ascending index order.
-// R and B rows are padded to n + 1 entries (conflict-free LDS columns).
-// Uniform batches: work-group b runs instance b. Same options, stop rules,
+// X^T in LDS; the selection sees one row per thread (thread t holds row t's
+// norm). The two dot-product phases (v_l = R_{i_k} . B_l for l < q, then
+// w_j = sum_l v_l B_lj for j < n) and the R update with the new row norms
+// give each dot or row to a group of G lanes (G a power of two, G times the
+// count at most kThreads): lane g of a group takes entries g, g + G, ...,
+// and the group adds its partial sums by lane exchanges (fixed order). The
+// operands the update reads from device memory (A_{i_k}, the column i_k of
+// A A^T) are fetched right after the selection and used after the dot
+// products; X_ref's entries of the first kSmallXr passes of the X update
+// stay in registers. R and B rows are padded to n + 1 entries. Uniform
+// batches: work-group b runs instance b. Same options, stop rules,
 // histories and report as the team kernel.
-constexpr int kSmallU = 8;   // LDS loads per block in the small kernel's loops
+constexpr int kSmallXr = 4;   // X update passes whose X_ref entries stay in registers
+
+// Lanes per group for `count` dots or rows: the largest power of two G <= 64
+// with G * count <= kThreads.
+__device__ __forceinline__ int small_group(int count) {
+    int g = 1;
+    while (g < kWave && 2 * g * count <= kThreads) g *= 2;
+    return g;
+}
+
+// Sum over aligned groups of G lanes (G a power of two <= 64): every lane
+// of a group gets the group's total, added in butterfly order.
+__device__ __forceinline__ double group_sum(double v, int G) {
+    for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T> P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     __shared__ BlockScratch sc;
     __shared__ double s_c;
-    __shared__ int s_ik;
     if (P.slots) bind_instance(P, blockIdx.x);
     if (P.norms) {
         P.C2 = P.norms[0];
@@ -648,6 +667,8 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
     double* u_tab = reinterpret_cast<double*>(
         reinterpret_cast<unsigned char*>(dyn_smem) +
         ((((size_t)m * ld + (size_t)q * ld + (size_t)q * p + q + n + p) * sizeof(T) + 15) & ~(size_t)15));
+    double* rn = u_tab + kUTable;   // new row norms, m
+    const int G1 = small_group(q), G2 = small_group(n), G3 = small_group(m);
     for (int e = tid; e < m * n; e += kThreads) Rl[(e / n) * ld + e % n] = P.R[e];
     for (int e = tid; e < q * n; e += kThreads) Bl[(e / n) * ld + e % n] = P.B[e];
     for (int e = tid; e < q * p; e += kThreads) Xl[e] = P.Xt[e];
@@ -666,6 +687,12 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
             const double d = (double)Xl[e] - P.Xref_t[e];
             ep += d * d;
         }
+    double xr[kSmallXr];
+#pragma unroll
+    for (int u = 0; u < kSmallXr; ++u) {
+        const int e = tid + u * kThreads;
+        xr[u] = (has_ref && e < q * p) ? P.Xref_t[e] : 0.0;
+    }
     double S0 = -1.0, S = 0.0, err = NAN;
     long long k = 0;
     int status = kMaxIter, last_set = 0;
@@ -715,37 +742,46 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
             if (P.set_hist) P.set_hist[hk] = last_set;
         }
         MEK_PHASE(kPhSelect);
-        // Operands of the update from device memory, fetched now: A_{i_k}
-        // into LDS, this row's entry of column i_k of A A^T into a register.
+        // Operands of the update from device memory, fetched now and used
+        // after the dot products: A_{i_k} (into LDS then) and the entry of
+        // column i_k of A A^T for the row this lane updates.
         if (tid == ik) s_c = P.alpha / ai;
-        if (tid < p) al[tid] = P.A[(size_t)ik * p + tid];
-        const T ga = tid < m ? P.GA[(size_t)ik * m + tid] : (T)0;
-        // v_l = R_{i_k} . B_l (pre-update row).
-        // Loops over LDS in blocks of kSmallU, every load of a block issued
-        // before its multiply-adds (sums still in ascending index order).
-        const T* rrow = Rl + (size_t)ik * ld;
-        if (tid < q) {
-            const T* brow = Bl + (size_t)tid * ld;
+        const T aval = tid < p ? P.A[(size_t)ik * p + tid] : (T)0;
+        const int h3 = tid / G3, g3 = tid - h3 * G3;
+        const T ga = h3 < m ? P.GA[(size_t)ik * m + h3] : (T)0;
+        // v_l = R_{i_k} . B_l (pre-update row), G1 lanes per dot.
+        {
+            const int l = tid / G1, g1 = tid - l * G1;
+            const T* rrow = Rl + (size_t)ik * ld;
             double acc = 0.0;
-            for (int j0 = 0; j0 < n; j0 += kSmallU) {
-                T xa[kSmallU], xb[kSmallU];
-#pragma unroll
-                for (int u = 0; u < kSmallU; ++u) {
-                    xa[u] = j0 + u < n ? rrow[j0 + u] : (T)0;
-                    xb[u] = j0 + u < n ? brow[j0 + u] : (T)0;
-                }
-#pragma unroll
-                for (int u = 0; u < kSmallU; ++u) acc += (double)xa[u] * (double)xb[u];
+            if (l < q) {
+                const T* brow = Bl + (size_t)l * ld;
+                for (int j = g1; j < n; j += G1) acc += (double)rrow[j] * (double)brow[j];
             }
-            vl[tid] = (T)acc;
+            acc = group_sum(acc, G1);
+            if (l < q && g1 == 0) vl[l] = (T)acc;
         }
+        if (tid < p) al[tid] = aval;
         __syncthreads();
         MEK_PHASE(kPhDots);
         const double c = s_c;
         // X^T[l][s] += c A_{i_k, s} v_l, with the error partial; then
-        // w_j = sum_l v_l B_lj.
+        // w_j = sum_l v_l B_lj, G2 lanes per entry.
         ep = 0.0;
-        for (int e = tid; e < q * p; e += kThreads) {
+#pragma unroll
+        for (int u = 0; u < kSmallXr; ++u) {
+            const int e = tid + u * kThreads;
+            if (e < q * p) {
+                const int l = e / p, s2 = e - l * p;
+                const T nv = Xl[e] + (T)(c * (double)al[s2]) * vl[l];
+                Xl[e] = nv;
+                if (has_ref) {
+                    const double d = (double)nv - xr[u];
+                    ep += d * d;
+                }
+            }
+        }
+        for (int e = tid + kSmallXr * kThreads; e < q * p; e += kThreads) {
             const int l = e / p, s2 = e - l * p;
             const T nv = Xl[e] + (T)(c * (double)al[s2]) * vl[l];
             Xl[e] = nv;
@@ -754,45 +790,35 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
                 ep += d * d;
             }
         }
-        if (tid < n) {
+        {
+            const int j = tid / G2, g2 = tid - j * G2;
             double acc = 0.0;
-            for (int l0 = 0; l0 < q; l0 += kSmallU) {
-                T xa[kSmallU], xb[kSmallU];
-#pragma unroll
-                for (int u = 0; u < kSmallU; ++u) {
-                    xa[u] = l0 + u < q ? vl[l0 + u] : (T)0;
-                    xb[u] = l0 + u < q ? Bl[(size_t)(l0 + u) * ld + tid] : (T)0;
-                }
-#pragma unroll
-                for (int u = 0; u < kSmallU; ++u) acc += (double)xa[u] * (double)xb[u];
-            }
-            wl[tid] = (T)acc;
+            if (j < n)
+                for (int l = g2; l < q; l += G2) acc += (double)vl[l] * (double)Bl[(size_t)l * ld + j];
+            acc = group_sum(acc, G2);
+            if (j < n && g2 == 0) wl[j] = (T)acc;
         }
         __syncthreads();
         MEK_PHASE(kPhX);
-        // R_h -= (c (A A^T)_{i_k, h}) w and the new norm of row h.
-        if (tid < m) {
-            const T sc_h = (T)(c * (double)ga);
-            T* rp = Rl + (size_t)tid * ld;
+        // R_h -= (c (A A^T)_{i_k, h}) w and the new norm of row h, G3 lanes
+        // per row; the norms go through LDS to the lane that owns the row in
+        // the selection.
+        {
             double acc = 0.0;
-            for (int j0 = 0; j0 < n; j0 += kSmallU) {
-                T xr[kSmallU], xw[kSmallU];
-#pragma unroll
-                for (int u = 0; u < kSmallU; ++u) {
-                    xr[u] = j0 + u < n ? rp[j0 + u] : (T)0;
-                    xw[u] = j0 + u < n ? wl[j0 + u] : (T)0;
-                }
-#pragma unroll
-                for (int u = 0; u < kSmallU; ++u) {
-                    if (j0 + u < n) {
-                        const T v = xr[u] - sc_h * xw[u];
-                        rp[j0 + u] = v;
-                        acc += (double)v * (double)v;
-                    }
+            if (h3 < m) {
+                const T sc_h = (T)(c * (double)ga);
+                T* rp = Rl + (size_t)h3 * ld;
+                for (int j = g3; j < n; j += G3) {
+                    const T v = rp[j] - sc_h * wl[j];
+                    rp[j] = v;
+                    acc += (double)v * (double)v;
                 }
             }
-            ri = acc;
+            acc = group_sum(acc, G3);
+            if (h3 < m && g3 == 0) rn[h3] = acc;
         }
+        __syncthreads();
+        ri = tid < m ? rn[tid] : 0.0;
         MEK_PHASE(kPhUpdate);
         ++k;
     }
@@ -811,7 +837,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
 size_t solve_small_lds_bytes(int m, int p, int q, int n, size_t elem) {
     const size_t ld = (size_t)n + 1;
     return (((size_t)m * ld + (size_t)q * ld + (size_t)q * p + q + n + p) * elem + 15) / 16 * 16 +
-           kUTable * sizeof(double);
+           (kUTable + (size_t)m) * sizeof(double);
 }
 
 template <typename T>
