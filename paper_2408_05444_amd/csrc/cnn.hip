@@ -488,10 +488,17 @@ __global__ void prep_weights_kernel(const float* __restrict__ w, uint16_t* __res
 // Input x: 32 channels, NHWC. mask (input gradient): the ReLU output of the
 // layer whose gradient x is, same layout; entries whose mask is not > 0 read
 // as zero. Output: NHWC BF16 for 32 channels, NCHW (BF16 or FP64 + add) for 3.
-template <int CO, bool TRANS>
+//
+// Persistent over tiles: a block puts the weights in LDS once, then takes
+// tiles blockIdx.x, blockIdx.x + gridDim.x, ... (tile = image, row band,
+// column band); the next tile's input is fetched into registers while the
+// current one's products run.
+constexpr int kMPre = (4 * kMPix + 255) / 256;   // 16-byte input chunks per thread and tile
+
+template <int CO, bool TRANS, bool MASK>
 __global__ void __launch_bounds__(256)
-conv3x3_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ mask, int H,
-                    int W, const uint16_t* __restrict__ wb, const float* __restrict__ bias,
+conv3x3_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ mask, int N,
+                    int H, int W, const uint16_t* __restrict__ wb, const float* __restrict__ bias,
                     int relu, uint16_t* __restrict__ yb, double* __restrict__ yd,
                     const double* __restrict__ add) {
     constexpr int CI = 32;
@@ -499,97 +506,149 @@ conv3x3_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__
     constexpr int OT = COP / 16;
     __shared__ uint4 xs[kMPix * kSlot];
     __shared__ uint4 ws[9 * COP * kSlot];
-    const int tiles_w = (W + kMW - 1) / kMW;
-    const int th = blockIdx.x / tiles_w, tw = blockIdx.x - th * tiles_w;
-    const int n = blockIdx.y;
-    const int h0 = th * kMT, w0 = tw * kMW;
+    const int tiles_w = (W + kMW - 1) / kMW, tiles_h = (H + kMT - 1) / kMT;
+    const int per_img = tiles_w * tiles_h, total = N * per_img;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
+    // Weights, already in MFMA order: one 16-byte load per slot, once.
+    for (int e = tid; e < 9 * COP * 4; e += 256)
+        ws[(e >> 2) * kSlot + (e & 3)] = *reinterpret_cast<const uint4*>(wb + 8 * e);
+
     // Input tile: task e = (halo pixel, chunk of 8 channels), one 16-byte
-    // load each (four lanes cover a pixel's 64 bytes).
-    for (int e = tid; e < 4 * kMPix; e += 256) {
-        const int px = e >> 2, ch = e & 3;
-        const int hh = h0 - 1 + px / kMHc, ww = w0 - 1 + px % kMHc;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
-            const size_t off = (((size_t)n * H + hh) * W + ww) * CI + 8 * ch;
-            v = *reinterpret_cast<const uint4*>(x + off);
-            if (mask) {
-                const uint4 mk = *reinterpret_cast<const uint4*>(mask + off);
+    // load each (four lanes cover a pixel's 64 bytes); the mask, if any,
+    // is fetched beside it and applied on the way into LDS.
+    uint4 pre[kMPre], mpre[MASK ? kMPre : 1];
+    auto fetch = [&](int tile) {
+        const int n = tile / per_img, rest = tile - n * per_img;
+        const int th = rest / tiles_w, tw = rest - th * tiles_w;
+        const int h0 = th * kMT, w0 = tw * kMW;
+#pragma unroll
+        for (int u = 0; u < kMPre; ++u) {
+            const int e = tid + 256 * u;
+            const int px = e >> 2, ch = e & 3;
+            const int hh = h0 - 1 + px / kMHc, ww = w0 - 1 + px % kMHc;
+            pre[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (MASK) mpre[MASK ? u : 0] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < 4 * kMPix && hh >= 0 && hh < H && ww >= 0 && ww < W) {
+                const size_t off = (((size_t)n * H + hh) * W + ww) * CI + 8 * ch;
+                pre[u] = *reinterpret_cast<const uint4*>(x + off);
+                if (MASK) mpre[MASK ? u : 0] = *reinterpret_cast<const uint4*>(mask + off);
+            }
+        }
+    };
+    // This lane's output channels 16 a + 4 lq + jj: their biases, once.
+    float bv[OT][4];
+#pragma unroll
+    for (int a = 0; a < OT; ++a)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int o = 16 * a + 4 * (lane >> 4) + jj;
+            bv[a][jj] = (bias && o < CO) ? bias[o] : 0.0f;
+        }
+    int tile = blockIdx.x;
+    if (tile < total) fetch(tile);
+    for (; tile < total; tile += gridDim.x) {
+        __syncthreads();   // every wave is done with the previous tile's input
+#pragma unroll
+        for (int u = 0; u < kMPre; ++u) {
+            const int e = tid + 256 * u;
+            if (e >= 4 * kMPix) continue;
+            uint4 v = pre[u];
+            if (MASK) {
+                const uint4 mk = mpre[MASK ? u : 0];
                 uint32_t vv[4] = {v.x, v.y, v.z, v.w};
                 const uint32_t mm[4] = {mk.x, mk.y, mk.z, mk.w};
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t lo = (bf2f(mm[u] & 0xffff) > 0.0f) ? 0x0000ffffu : 0u;
-                    const uint32_t hi = (bf2f(mm[u] >> 16) > 0.0f) ? 0xffff0000u : 0u;
-                    vv[u] &= (lo | hi);
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t lo = (bf2f(mm[q] & 0xffff) > 0.0f) ? 0x0000ffffu : 0u;
+                    const uint32_t hi = (bf2f(mm[q] >> 16) > 0.0f) ? 0xffff0000u : 0u;
+                    vv[q] &= (lo | hi);
                 }
                 v = make_uint4(vv[0], vv[1], vv[2], vv[3]);
             }
+            xs[(e >> 2) * kSlot + (e & 3)] = v;
         }
-        xs[px * kSlot + ch] = v;
-    }
-    // Weights, already in MFMA order: one 16-byte load per slot.
-    for (int e = tid; e < 9 * COP * 4; e += 256)
-        ws[(e >> 2) * kSlot + (e & 3)] = *reinterpret_cast<const uint4*>(wb + 8 * e);
-    __syncthreads();
+        __syncthreads();
+        const int n = tile / per_img, rest = tile - n * per_img;
+        const int th = rest / tiles_w, tw = rest - th * tiles_w;
+        const int h0 = th * kMT, w0 = tw * kMW;
+        if (tile + (int)gridDim.x < total) fetch(tile + gridDim.x);
 
-    const int l16 = lane & 15, lq = lane >> 4;
-    const int r0 = wave * 4;   // this wave's first output row in the tile
-    float4_t acc[4][OT];
+        const int l16 = lane & 15, lq = lane >> 4;
+        const int r0 = wave * 4;   // this wave's first output row in the tile
+        float4_t acc[4][OT];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int a = 0; a < OT; ++a) acc[r][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
+            for (int a = 0; a < OT; ++a) acc[r][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int i = t / 3, j = t % 3;
-        bf16x8_t fa[OT];
-#pragma unroll
-        for (int a = 0; a < OT; ++a)
-            fa[a] = __builtin_bit_cast(bf16x8_t, ws[(t * COP + 16 * a + l16) * kSlot + lq]);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const bf16x8_t fb =
-                __builtin_bit_cast(bf16x8_t, xs[((r0 + r + i) * kMHc + l16 + j) * kSlot + lq]);
+        for (int t = 0; t < 9; ++t) {
+            const int i = t / 3, j = t % 3;
+            bf16x8_t fa[OT];
 #pragma unroll
             for (int a = 0; a < OT; ++a)
-                acc[r][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb, acc[r][a], 0, 0, 0);
-        }
-    }
-
-    // Lane (l16, lq) holds output channels 16 a + 4 lq + jj of pixel l16.
-    const int wq = w0 + l16;
+                fa[a] = __builtin_bit_cast(bf16x8_t, ws[(t * COP + 16 * a + l16) * kSlot + lq]);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int h = h0 + r0 + r;
-        if (h >= H || wq >= W) continue;
+            for (int r = 0; r < 4; ++r) {
+                const bf16x8_t fb =
+                    __builtin_bit_cast(bf16x8_t, xs[((r0 + r + i) * kMHc + l16 + j) * kSlot + lq]);
 #pragma unroll
-        for (int a = 0; a < OT; ++a) {
-            float v[4];
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int o = 16 * a + 4 * lq + jj;
-                v[jj] = acc[r][a][jj] + ((bias && o < CO) ? bias[o] : 0.0f);
-                if (relu) v[jj] = fmaxf(v[jj], 0.0f);
+                for (int a = 0; a < OT; ++a)
+                    acc[r][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb, acc[r][a], 0, 0, 0);
             }
-            if (CO == 32) {
-                // Four consecutive channels of one pixel: one 8-byte store.
-                const size_t off = (((size_t)n * H + h) * W + wq) * 32 + 16 * a + 4 * lq;
-                *reinterpret_cast<uint2*>(yb + off) =
-                    make_uint2(pack2(f2bf(v[0]), f2bf(v[1])), pack2(f2bf(v[2]), f2bf(v[3])));
-            } else {
+        }
+
+        // Lane (l16, lq) holds output channels 16 a + 4 lq + jj of pixel l16.
+        const int wq = w0 + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int h = h0 + r0 + r;
+            if (h >= H || wq >= W) continue;
+#pragma unroll
+            for (int a = 0; a < OT; ++a) {
+                float v[4];
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
-                    const int o = 16 * a + 4 * lq + jj;
-                    if (o >= CO) continue;
-                    const size_t idx = (((size_t)n * CO + o) * H + h) * W + wq;
-                    if (yb) yb[idx] = f2bf(v[jj]);
-                    else yd[idx] = (add ? add[idx] : 0.0) + (double)v[jj];
+                    v[jj] = acc[r][a][jj] + bv[a][jj];
+                    if (relu) v[jj] = fmaxf(v[jj], 0.0f);
+                }
+                if (CO == 32) {
+                    // Four consecutive channels of one pixel: one 8-byte store.
+                    const size_t off = (((size_t)n * H + h) * W + wq) * 32 + 16 * a + 4 * lq;
+                    *reinterpret_cast<uint2*>(yb + off) =
+                        make_uint2(pack2(f2bf(v[0]), f2bf(v[1])), pack2(f2bf(v[2]), f2bf(v[3])));
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int o = 16 * a + 4 * lq + jj;
+                        if (o >= CO) continue;
+                        const size_t idx = (((size_t)n * CO + o) * H + h) * W + wq;
+                        if (yb) yb[idx] = f2bf(v[jj]);
+                        else yd[idx] = (add ? add[idx] : 0.0) + (double)v[jj];
+                    }
                 }
             }
         }
     }
+}
+
+// Work-groups of a persistent matrix-core convolution: at most per_cu per
+// compute unit (3 with 32 output channels, 49 KB of LDS each; 4 with 3), as
+// few as keep the same number of rounds of tiles, so that every work-group
+// takes the same number of tiles.
+static int conv_mfma_blocks(int tiles, int per_cu) {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
+            cus = c;
+        else
+            cus = 256;
+    }
+    const int slots = per_cu * cus;
+    const int rounds = (tiles + slots - 1) / slots;
+    return (tiles + rounds - 1) / rounds;
 }
 
 template <bool TRANS>
@@ -600,18 +659,26 @@ hipError_t conv_dispatch(int N, int Cin, int H, int W, int Cout, const uint16_t*
     if (Cin == 32) {
         // 32 input channels: the matrix-core form, weights put in MFMA order
         // first.
-        const int tiles = ((H + kMT - 1) / kMT) * ((W + kMW - 1) / kMW);
-        dim3 grid(tiles, N);
+        const int tiles = ((H + kMT - 1) / kMT) * ((W + kMW - 1) / kMW) * N;
+        const dim3 grid(conv_mfma_blocks(tiles, Cout == 32 ? 3 : 4));
         if (Cout == 32) {
             hipLaunchKernelGGL((prep_weights_kernel<32, TRANS>), dim3((9 * 32 * 32 + 255) / 256),
                                dim3(256), 0, s, w, wb);
-            hipLaunchKernelGGL((conv3x3_mfma_kernel<32, TRANS>), grid, dim3(256), 0, s, x, mask,
-                               H, W, wb, b, relu, yb, yd, add);
+            if (mask)
+                hipLaunchKernelGGL((conv3x3_mfma_kernel<32, TRANS, true>), grid, dim3(256), 0, s, x,
+                                   mask, N, H, W, wb, b, relu, yb, yd, add);
+            else
+                hipLaunchKernelGGL((conv3x3_mfma_kernel<32, TRANS, false>), grid, dim3(256), 0, s, x,
+                                   mask, N, H, W, wb, b, relu, yb, yd, add);
         } else if (Cout == 3) {
             hipLaunchKernelGGL((prep_weights_kernel<3, TRANS>), dim3((9 * 16 * 32 + 255) / 256),
                                dim3(256), 0, s, w, wb);
-            hipLaunchKernelGGL((conv3x3_mfma_kernel<3, TRANS>), grid, dim3(256), 0, s, x, mask,
-                               H, W, wb, b, relu, yb, yd, add);
+            if (mask)
+                hipLaunchKernelGGL((conv3x3_mfma_kernel<3, TRANS, true>), grid, dim3(256), 0, s, x,
+                                   mask, N, H, W, wb, b, relu, yb, yd, add);
+            else
+                hipLaunchKernelGGL((conv3x3_mfma_kernel<3, TRANS, false>), grid, dim3(256), 0, s, x,
+                                   mask, N, H, W, wb, b, relu, yb, yd, add);
         } else {
             return hipErrorInvalidValue;
         }
