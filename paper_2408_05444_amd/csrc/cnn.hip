@@ -230,6 +230,92 @@ conv3x3_wgrad_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
     }
 }
 
+// Weight and bias gradient partial sums of one 16 x 16 tile for few input
+// channels (Cin <= kFewC, the network's first layer) and 32 output
+// channels: thread (o, part) takes output channel o and 32 of the tile's
+// 256 pixels, every input channel and tap; the 8 parts are then added in
+// part order through LDS. (One thread per (input channel, output group)
+// would leave most of the block idle with 3 input channels.)
+constexpr int kFewC = 4;
+__global__ void __launch_bounds__(kCThreads)
+conv3x3_wgrad_fewc_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
+                          const uint16_t* __restrict__ g, const uint16_t* __restrict__ gmask,
+                          float* __restrict__ partial) {
+    constexpr int CO = 32, NA = kFewC * 9 + 1, PARTS = kCThreads / CO;
+    __shared__ float xs[kFewC * kChanStride];
+    __shared__ float gs[CO * kGsStride];
+    __shared__ float red[PARTS * CO * NA];
+    const int tiles_w = (W + kCT - 1) / kCT;
+    const int th = blockIdx.x / tiles_w, tw = blockIdx.x - th * tiles_w;
+    const int n = blockIdx.y;
+    const int h0 = th * kCT, w0 = tw * kCT;
+    stage_halo(xs, x, nullptr, n, Cin, H, W, h0, w0);
+    // Gradient (channels-last): task e = (pixel, 8-channel chunk), one
+    // 16-byte load (and one of the gate), 8 values to the channels' rows.
+    for (int e = threadIdx.x; e < 4 * kCThreads; e += kCThreads) {
+        const int p = e >> 2, q = e & 3;
+        const int hh = h0 + p / kCT, ww = w0 + p % kCT;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u), mk = make_uint4(0u, 0u, 0u, 0u);
+        if (hh < H && ww < W) {
+            const size_t off = (((size_t)n * H + hh) * W + ww) * CO + 8 * q;
+            v = *reinterpret_cast<const uint4*>(g + off);
+            if (gmask) mk = *reinterpret_cast<const uint4*>(gmask + off);
+        }
+        const uint32_t vv[4] = {v.x, v.y, v.z, v.w}, mm[4] = {mk.x, mk.y, mk.z, mk.w};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t b = (u & 1) ? (vv[u >> 1] >> 16) : (vv[u >> 1] & 0xffff);
+            float f = bf2f(b);
+            if (gmask) {
+                const uint32_t mb = (u & 1) ? (mm[u >> 1] >> 16) : (mm[u >> 1] & 0xffff);
+                if (!(bf2f(mb) > 0.0f)) f = 0.0f;
+            }
+            gs[(8 * q + u) * kGsStride + p] = f;
+        }
+    }
+    __syncthreads();
+    const int o = threadIdx.x % CO, part = threadIdx.x / CO;
+    float acc[kFewC][9], bacc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kFewC; ++c)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[c][t] = 0.0f;
+    for (int pp = 0; pp < kCThreads / PARTS; ++pp) {
+        const int p = part * (kCThreads / PARTS) + pp;
+        const int py = p / kCT, px = p % kCT;
+        const float gv = gs[o * kGsStride + p];
+        bacc += gv;
+#pragma unroll
+        for (int c = 0; c < kFewC; ++c) {
+            if (c < Cin) {
+                const float* xc = xs + c * kChanStride + py * kHalo + px;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) acc[c][i * 3 + j] = fmaf(gv, xc[i * kHalo + j], acc[c][i * 3 + j]);
+            }
+        }
+    }
+    float* rp = red + (part * CO + o) * NA;
+#pragma unroll
+    for (int c = 0; c < kFewC; ++c)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) rp[c * 9 + t] = acc[c][t];
+    rp[kFewC * 9] = bacc;
+    __syncthreads();
+    const size_t E = (size_t)CO * Cin * 9 + CO;
+    float* out = partial + ((size_t)n * gridDim.x + blockIdx.x) * E;
+    const int per_o = Cin * 9 + 1;
+    for (int e = threadIdx.x; e < CO * per_o; e += kCThreads) {
+        const int oo = e / per_o, r = e - oo * per_o;
+        const int slot = r < Cin * 9 ? r : kFewC * 9;
+        float sacc = 0.0f;
+        for (int q = 0; q < PARTS; ++q) sacc += red[(q * CO + oo) * NA + slot];
+        if (r < Cin * 9) out[((size_t)oo * Cin + r / 9) * 9 + r % 9] = sacc;
+        else out[(size_t)CO * Cin * 9 + oo] = sacc;
+    }
+}
+
 // Weight and bias gradient partial sums of one 16 x 16 pixel tile on the
 // BF16 matrix cores, for 32 input channels: per tap t, D_t[o][c] =
 // sum over the tile's pixels of g'[o][p] x[c][p + shift_t], the 256 pixels
@@ -273,7 +359,39 @@ conv3x3_wgrad_mfma_kernel(const uint16_t* __restrict__ x, int H, int W,
         const int th = pt / tiles_w, tw = pt - th * tiles_w;
         const int h0 = th * kCT, w0 = tw * kCT;
         // Gradient tile (gated), zero outside the image and in padded channels;
-        // the bias gradient from the same values.
+        // the bias gradient from the same values. 32 channels (channels-last):
+        // task e = (pixel, 8-channel chunk), one 16-byte load (and one of the
+        // mask), its 8 values stored to the 8 channels' pixel rows.
+        if (CO == 32) {
+            uint16_t* gs16 = reinterpret_cast<uint16_t*>(gs);
+            for (int e = tid; e < 4 * kCT * kCT; e += 256) {
+                const int px = e >> 2, q = e & 3;
+                const int hh = h0 + (px >> 4), ww = w0 + (px & 15);
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (hh < H && ww < W) {
+                    const size_t off = (((size_t)n * H + hh) * W + ww) * 32 + 8 * q;
+                    v = *reinterpret_cast<const uint4*>(g + off);
+                    if (gmask) {
+                        const uint4 mk = *reinterpret_cast<const uint4*>(gmask + off);
+                        const uint32_t mm[4] = {mk.x, mk.y, mk.z, mk.w};
+                        uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const uint32_t lo = (bf2f(mm[u] & 0xffff) > 0.0f) ? 0x0000ffffu : 0u;
+                            const uint32_t hi = (bf2f(mm[u] >> 16) > 0.0f) ? 0xffff0000u : 0u;
+                            vv[u] &= (lo | hi);
+                        }
+                        v = make_uint4(vv[0], vv[1], vv[2], vv[3]);
+                    }
+                }
+                const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+                const int chk = 2 * (px >> 4) + ((px & 15) >> 3), pos = px & 7;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    gs16[((8 * q + u) * kGStride + chk) * 8 + pos] =
+                        (uint16_t)((u & 1) ? (vv[u >> 1] >> 16) : (vv[u >> 1] & 0xffff));
+            }
+        } else
         for (int e = tid; e < COP * 32; e += 256) {
             const int o = e >> 5, chk = e & 31;          // 32 chunks of 8 pixels
             const int hh = h0 + (chk >> 1), ww0 = w0 + 8 * (chk & 1);
@@ -737,6 +855,9 @@ hipError_t cnn_conv3x3_grad_weight(int N, int Cin, int H, int W, int Cout, const
                            gmask, partial);
     else if (mm && Cout == 3)
         hipLaunchKernelGGL(conv3x3_wgrad_mfma_kernel<3>, grid_mm, dim3(256), 0, s, x, H, W, g,
+                           gmask, partial);
+    else if (Cin <= kFewC && Cout == 32)
+        hipLaunchKernelGGL(conv3x3_wgrad_fewc_kernel, grid, dim3(kCThreads), 0, s, x, Cin, H, W, g,
                            gmask, partial);
     else switch (Cout) {
         case 32:
