@@ -74,57 +74,51 @@ __device__ __forceinline__ void stage_halo(float* xs, const uint16_t* __restrict
     }
 }
 
-// Forward (TRANS = false): CO output channels from Cin inputs with weights
-// w (CO, Cin, 3, 3). Input gradient (TRANS = true): the layer's weights W
-// (Cin, CO, 3, 3) read as W[ci][co][2-i][2-j], no bias, no ReLU. Writes BF16
-// (yb) or FP64 (yd) outputs; an FP64 output may add a tensor of its shape.
+// Forward (TRANS = false): CO output channels from kFewIn = 3 input
+// channels with weights w (CO, 3, 3, 3). Input gradient (TRANS = true): the
+// layer's weights W (3, CO, 3, 3) read as W[ci][co][2-i][2-j], no bias, no
+// ReLU. Writes BF16 (yb) or FP64 (yd) outputs; an FP64 output may add a
+// tensor of its shape. One thread per output pixel keeps its 27 inputs in
+// registers; the weights are the same in every lane, so they are read from
+// device memory with uniform addresses (the scalar unit, scalar registers
+// as the multiply-add operands) rather than through LDS.
+constexpr int kFewIn = 3;
 template <int CO, bool TRANS>
 __global__ void __launch_bounds__(kCThreads)
-conv3x3_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ mask, int Cin, int H,
-               int W, const float* __restrict__ w, const float* __restrict__ bias, int relu,
+conv3x3_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ mask, int H, int W,
+               const float* __restrict__ w, const float* __restrict__ bias, int relu,
                uint16_t* __restrict__ yb, double* __restrict__ yd, const double* __restrict__ add) {
-    // Weights staged as ws[c][i][j][o] (o padded to a multiple of 4), so that
-    // the CO weights of one input tap are one run of 16-byte LDS reads, the
-    // same address in every lane.
-    constexpr int COP = (CO + 3) & ~3;
-    __shared__ float xs[kMaxC * kChanStride];
-    __shared__ __align__(16) float ws[kMaxC * 9 * COP];
+    constexpr int KT = kFewIn * 9;
+    __shared__ float xs[kFewIn * kChanStride];
     const int tiles_w = (W + kCT - 1) / kCT;
     const int th = blockIdx.x / tiles_w, tw = blockIdx.x - th * tiles_w;
     const int n = blockIdx.y;
     const int h0 = th * kCT, w0 = tw * kCT;
-    stage_halo(xs, x, mask, n, Cin, H, W, h0, w0);
-    for (int e = threadIdx.x; e < Cin * 9 * COP; e += kCThreads) {
-        const int o = e % COP, t = e / COP;
-        const int c = t / 9, i = (t % 9) / 3, j = t % 3;
-        float v = 0.0f;
-        if (o < CO)
-            v = TRANS ? w[((c * CO + o) * 3 + (2 - i)) * 3 + (2 - j)]
-                      : w[((o * Cin + c) * 3 + i) * 3 + j];
-        ws[e] = v;
-    }
+    stage_halo(xs, x, mask, n, kFewIn, H, W, h0, w0);
     __syncthreads();
     const int ty = threadIdx.x / kCT, tx = threadIdx.x % kCT;
-    float acc[COP];
+    float xv[KT];
 #pragma unroll
-    for (int o = 0; o < COP; ++o) acc[o] = 0.0f;
-    for (int c = 0; c < Cin; ++c) {
-        const float* xc = xs + c * kChanStride + ty * kHalo + tx;
+    for (int c = 0; c < kFewIn; ++c)
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const float xv = xc[i * kHalo + j];
-                const float4* wp = reinterpret_cast<const float4*>(ws + ((c * 3 + i) * 3 + j) * COP);
+            for (int j = 0; j < 3; ++j) xv[(c * 3 + i) * 3 + j] = xs[c * kChanStride + (ty + i) * kHalo + tx + j];
+    float acc[CO];
 #pragma unroll
-                for (int o4 = 0; o4 < COP / 4; ++o4) {
-                    const float4 w4 = wp[o4];
-                    acc[4 * o4 + 0] = fmaf(xv, w4.x, acc[4 * o4 + 0]);
-                    acc[4 * o4 + 1] = fmaf(xv, w4.y, acc[4 * o4 + 1]);
-                    acc[4 * o4 + 2] = fmaf(xv, w4.z, acc[4 * o4 + 2]);
-                    acc[4 * o4 + 3] = fmaf(xv, w4.w, acc[4 * o4 + 3]);
+    for (int o = 0; o < CO; ++o) {
+        float a = 0.0f;
+#pragma unroll
+        for (int c = 0; c < kFewIn; ++c)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const float wv = TRANS ? w[((c * CO + o) * 3 + (2 - i)) * 3 + (2 - j)]
+                                           : w[((o * kFewIn + c) * 3 + i) * 3 + j];
+                    a = fmaf(xv[(c * 3 + i) * 3 + j], wv, a);
                 }
-            }
+        acc[o] = a;
     }
     const int h = h0 + ty, wq = w0 + tx;
     if (h >= H || wq >= W) return;
@@ -804,14 +798,15 @@ hipError_t conv_dispatch(int N, int Cin, int H, int W, int Cout, const uint16_t*
     }
     const int tiles = ((H + kCT - 1) / kCT) * ((W + kCT - 1) / kCT);
     dim3 grid(tiles, N);
+    if (Cin != kFewIn) return hipErrorInvalidValue;
     switch (Cout) {
         case 32:
-            hipLaunchKernelGGL((conv3x3_kernel<32, TRANS>), grid, dim3(kCThreads), 0, s, x, mask,
-                               Cin, H, W, w, b, relu, yb, yd, add);
+            hipLaunchKernelGGL((conv3x3_kernel<32, TRANS>), grid, dim3(kCThreads), 0, s, x, mask, H, W,
+                               w, b, relu, yb, yd, add);
             break;
         case 3:
-            hipLaunchKernelGGL((conv3x3_kernel<3, TRANS>), grid, dim3(kCThreads), 0, s, x, mask,
-                               Cin, H, W, w, b, relu, yb, yd, add);
+            hipLaunchKernelGGL((conv3x3_kernel<3, TRANS>), grid, dim3(kCThreads), 0, s, x, mask, H, W,
+                               w, b, relu, yb, yd, add);
             break;
         default: return hipErrorInvalidValue;
     }
