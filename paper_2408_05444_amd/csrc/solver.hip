@@ -46,57 +46,86 @@ __device__ __forceinline__ double row16_sum(double v) {
 // the rows in device memory, run by the whole work-group. Short vectors
 // (len <= 16 * kDotUnroll) take 16 lanes per dot, four dots per wave;
 // longer ones are cut into segments of kDotSeg entries, one wave task per
-// (dot, segment), with kDotUnroll loads in flight per lane. Partial sums
-// go to `part` (LDS) and are added in segment order, so the result does
-// not depend on scheduling. Ends with a barrier.
-template <typename T, typename RowFn, typename SinkFn>
+// (dot, segment), with kDotUnroll loads in flight per lane. A wave takes TG
+// of its tasks (or groups of four short dots) at a time, all their loads
+// issued before the first sum, so that small work-groups that run many
+// tasks each keep TG times the bytes in flight. Partial sums go to `part`
+// (LDS) and are added in segment order; a task's sum does not depend on TG
+// or on scheduling. Ends with a barrier.
+template <typename T, int TG = 1, typename RowFn, typename SinkFn>
 __device__ __forceinline__ void block_dots(const T* x, int len, int D, RowFn row_of, SinkFn sink,
                                            double* part) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     int nseg = 1;
     if (len <= 16 * kDotUnroll) {
         const int sub = lane >> 4, l16 = lane & 15;
-        for (int d0 = wv * 4; d0 < D; d0 += kWaves * 4) {
-            const int d = d0 + sub;
-            double acc = 0.0;
-            if (d < D) {
-                const T* mr = row_of(d);
-                T yv[kDotUnroll];
+        for (int d0 = wv * 4; d0 < D; d0 += kWaves * 4 * TG) {
+            T yv[TG][kDotUnroll];
 #pragma unroll
-                for (int u = 0; u < kDotUnroll; ++u) {
-                    const int j = l16 + 16 * u;
-                    yv[u] = (j < len) ? mr[j] : (T)0;
-                }
+            for (int g = 0; g < TG; ++g) {
+                // Dots past D read a valid row (the last) and are not kept.
+                const int d = min(d0 + g * kWaves * 4 + sub, D - 1);
+                if (g == 0 || d0 + g * kWaves * 4 < D) {
+                    const T* mr = row_of(d);
 #pragma unroll
-                for (int u = 0; u < kDotUnroll; ++u) {
-                    const int j = l16 + 16 * u;
-                    if (j < len) acc += (double)x[j] * (double)yv[u];
+                    for (int u = 0; u < kDotUnroll; ++u) {
+                        const int j = l16 + 16 * u;
+                        yv[g][u] = (j < len) ? mr[j] : (T)0;
+                    }
                 }
             }
-            acc = row16_sum(acc);
-            if (l16 == 0 && d < D) part[d] = acc;
+#pragma unroll
+            for (int g = 0; g < TG; ++g) {
+                const int d = d0 + g * kWaves * 4 + sub;
+                if (g == 0 || d0 + g * kWaves * 4 < D) {
+                    double acc = 0.0;
+                    if (d < D) {
+#pragma unroll
+                        for (int u = 0; u < kDotUnroll; ++u) {
+                            const int j = l16 + 16 * u;
+                            if (j < len) acc += (double)x[j] * (double)yv[g][u];
+                        }
+                    }
+                    acc = row16_sum(acc);
+                    if (l16 == 0 && d < D) part[d] = acc;
+                }
+            }
         }
     } else {
         nseg = (len + kDotSeg - 1) / kDotSeg;
         const int ntask = D * nseg;
-        for (int task = wv; task < ntask; task += kWaves) {
-            const int d = task / nseg, sg = task - d * nseg;
-            const T* mr = row_of(d);
-            const int j0 = sg * kDotSeg + lane;
-            T yv[kDotUnroll];
+        for (int t0 = wv; t0 < ntask; t0 += kWaves * TG) {
+            T yv[TG][kDotUnroll];
 #pragma unroll
-            for (int u = 0; u < kDotUnroll; ++u) {
-                const int j = j0 + u * kWave;
-                yv[u] = (j < len) ? mr[j] : (T)0;
-            }
-            double acc = 0.0;
+            for (int g = 0; g < TG; ++g) {
+                const int task = t0 + g * kWaves;
+                if (task < ntask) {   // uniform in the wave
+                    const int d = task / nseg, sg = task - d * nseg;
+                    const T* mr = row_of(d);
+                    const int j0 = sg * kDotSeg + lane;
 #pragma unroll
-            for (int u = 0; u < kDotUnroll; ++u) {
-                const int j = j0 + u * kWave;
-                if (j < len) acc += (double)x[j] * (double)yv[u];
+                    for (int u = 0; u < kDotUnroll; ++u) {
+                        const int j = j0 + u * kWave;
+                        yv[g][u] = (j < len) ? mr[j] : (T)0;
+                    }
+                }
             }
-            acc = wave_sum(acc);
-            if (lane == 0) part[task] = acc;
+#pragma unroll
+            for (int g = 0; g < TG; ++g) {
+                const int task = t0 + g * kWaves;
+                if (task < ntask) {
+                    const int sg = task % nseg;
+                    const int j0 = sg * kDotSeg + lane;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int u = 0; u < kDotUnroll; ++u) {
+                        const int j = j0 + u * kWave;
+                        if (j < len) acc += (double)x[j] * (double)yv[g][u];
+                    }
+                    acc = wave_sum(acc);
+                    if (lane == 0) part[task] = acc;
+                }
+            }
         }
     }
     __syncthreads();
@@ -159,6 +188,10 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     __shared__ int s_fail;   // set once a cross-work-group wait gives up
     __shared__ double s_err[kWaves];
     if (threadIdx.x == 0) s_fail = 0;
+    // Dot tasks per wave in flight: with R in device memory the work-groups
+    // are few per instance and run many dot tasks each; the registers allow
+    // four FP32 or two FP64 tasks when the selection holds few rows.
+    constexpr int kDotTG = (!LDS && SR <= 4) ? (sizeof(T) == 4 ? 4 : 2) : 1;
 
     int g = blockIdx.x;
     if (MULTI) {
@@ -428,7 +461,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
         // v = R_{i_k} B^T: this work-group's entries (rows xc0.. of B), into
         // LDS and, in a team, published for the others.
         xword* const v_x = reinterpret_cast<xword*>(P.vbuf);
-        block_dots<T>(rowsrc, n, nx, [&](int d) { return Bsrc + (size_t)(xc0 + d) * n; },
+        block_dots<T, kDotTG>(rowsrc, n, nx, [&](int d) { return Bsrc + (size_t)(xc0 + d) * n; },
                       [&](int d, double val) {
                           vl[d] = val;
                           if (team) xstore(&v_x[xc0 + d], pack_word((T)val, tag));
@@ -491,7 +524,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
             vfull = vec;
         }
         // w = v B for this work-group's entries (rows wc0.. of B^T).
-        block_dots<T>(vfull, q, nw, [&](int d) { return BTsrc + (size_t)(wc0 + d) * q; },
+        block_dots<T, kDotTG>(vfull, q, nw, [&](int d) { return BTsrc + (size_t)(wc0 + d) * q; },
                       [&](int d, double val) {
                           if (team) xstore(&w_x[wc0 + d], pack_word((T)val, tag));
                           else part[wslot + d] = val;
