@@ -1044,6 +1044,7 @@ def main():
         line["cnn_convolutions"] = cnn_forms(mek, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, seed, workloads)
+    torch.cuda.synchronize()   # nothing of ours is in flight at interpreter exit
     print(json.dumps(line), flush=True)
 
 
