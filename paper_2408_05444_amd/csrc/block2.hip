@@ -43,6 +43,8 @@ namespace {
 
 constexpr int kChunk = 8;   // rows of R per pass of the fused update/score loop
 constexpr int kXRows = 8;   // rows of X^T per pass of the X update
+constexpr int kInvWaves = 2;   // waves that invert the Gram blocks while the others exchange R_IJ
+static_assert(kBlkCap * kBlkCap == 2 * kThreads, "W products: two entries per thread");
 static_assert(kChunk == 8 && kXRows == 8, "block2_fac_doubles sizes the factor region for 8-row passes");
 static_assert(kChunk * kBlkCap <= kThreads && 2 * kXRows * kBlkCap <= kThreads,
               "one thread per entry of (A A^T)_{i, I}, c and B_{l, J}");
@@ -88,6 +90,10 @@ struct Blk2Smem {
     int nsel[2];
     int nI, nJ;
     int fail;
+    // Phase timing (thread 0 of work-group 0 only): the clock at the last
+    // mark and the ticks per phase, in LDS rather than in registers.
+    unsigned long long t_last;
+    unsigned long long ph[kB2Count];
 };
 
 // Sum (first NS values) and max (next NM values) over the block, results in
@@ -535,14 +541,16 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         fresh_lds();
     };
     const bool timing = P.phase != nullptr && g == 0 && tid == 0;
-    unsigned long long ph[kB2Count] = {};
-    unsigned long long t_last = timing ? wall_clock64() : 0;
+    if (timing) {
+        for (int i = 0; i < kB2Count; ++i) sm.ph[i] = 0;
+        sm.t_last = wall_clock64();
+    }
 #define B2_PHASE(id)                                                    \
     do {                                                                \
         if (timing) {                                                   \
             const unsigned long long now_ = wall_clock64();             \
-            ph[id] += now_ - t_last;                                    \
-            t_last = now_;                                              \
+            sm.ph[id] += now_ - sm.t_last;                              \
+            sm.t_last = now_;                                           \
         }                                                               \
     } while (0)
 
@@ -556,9 +564,9 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
     // (A A^T)_{i, I} of rows c0 .. c0 + kChunk of this work-group, as the
     // value thread tid < kChunk * kBlkCap stores to gaI[tid] (zero outside
     // the rows and the block).
-    auto fetch_gaI = [&](int c0, int nI) -> double {
-        const int ii = tid / kBlkCap, x = tid - ii * kBlkCap;
-        if (tid < kChunk * kBlkCap && c0 + ii < nrow && x < nI)
+    auto fetch_gaI = [&](int c0, int nI, int e) -> double {
+        const int ii = e / kBlkCap, x = e - ii * kBlkCap;
+        if (e < kChunk * kBlkCap && c0 + ii < nrow && x < nI)
             return P.GA[(size_t)(row0 + c0 + ii) * m + sm.I[x]];
         return 0.0;
     };
@@ -574,7 +582,7 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
             const int cr = min(kChunk, nrow - c0);
             {
                 if (c0 > 0) {
-                    const double gv = fetch_gaI(c0, nI);
+                    const double gv = fetch_gaI(c0, nI, tid);
                     __syncthreads();   // every thread is done with the previous chunk
                     if (tid < kChunk * kBlkCap) gaI[tid] = gv;
                     __syncthreads();
@@ -816,7 +824,7 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
     int status = kMaxIter, last_nI = 0;
     bool ok = true;
     const bool has_ref = P.Xref_t != nullptr;
-    if (timing) t_last = wall_clock64();
+    if (timing) sm.t_last = wall_clock64();
     while (ok) {
         {
             fresh();
@@ -1066,91 +1074,127 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
         B2_PHASE(kB2Factor);
 
         fresh();
-        // Operands of the X and R updates that need only I and J, fetched
-        // first (ahead of the stores below) and in flight while R_IJ is.
-        const double gaI0 = fetch_gaI(0, nI);
-        const double bX0 = fetch_bX(0, nJ);
-        // ---- D. R_IJ from the owners of the rows in I. Every word of the
-        // s_cap x t_cap block is rewritten every step (zeros outside I x J;
-        // work-group 0 writes the rows past nI), so no word can keep a value
-        // from four steps back that carries the current 2-bit tag.
-        for (int e = tid; e < scap * tcap; e += kThreads) {
-            const int x = e / tcap, y = e - x * tcap;
-            if (x < nI) {
-                const int i = sm.I[x];
-                if (i >= row0 && i < row0 + nrow) {
-                    const double v = (y < nJ) ? Rown[(size_t)(i - row0) * n + sm.J[y]] : 0.0;
-                    xstore(&ex[x * kBlkCap + y], pack_word(v, tag));
+        double bX0 = 0.0;   // fetch_bX(0) of this thread (zero below kBxT0)
+        static_assert(kBxT0 >= kInvWaves * kWave, "the inverting waves hold no B entries");
+        if (wv < kInvWaves) {
+            // ---- The inverses of the Gram blocks, G_I^{-1} by wave 0 and
+            // G_J^{-1} by wave 1, while the other waves exchange R_IJ: lane y
+            // < 32 solves G e = e_y with the factor (forward sweep over L,
+            // pivots ascending, scaling by 1 / L[x][x], backward sweep over
+            // L^T, pivots descending, scaling again). Right-looking: pivot x
+            // subtracts M[r][x] e[x] from every later entry r, independent
+            // multiply-adds whose factors are one contiguous row of the
+            // stored M^T. Column y is written over column y of the factor's
+            // own LDS rows once the whole wave is past its last factor read
+            // (the lanes run in lockstep and every read was consumed); it is
+            // zero outside the block (the unit entry of y past the block
+            // meets only zero factors and a zero scale), and the rows past
+            // the factor's capacity are zero, so they are not stored.
+            const int side = __builtin_amdgcn_readfirstlane(wv);   // uniform: scalar branches
+            double* const Mt = side ? LJ : LI;
+            const int nk = side ? nJ : nI, cap = side ? tcap : scap;
+            if (lane < kBlkCap) {
+                double ev[kBlkCap];
+#pragma unroll
+                for (int x = 0; x < kBlkCap; ++x) ev[x] = (x == lane) ? 1.0 : 0.0;
+                tri_sweep<true>(ev, Mt, nk, cap);
+#pragma unroll
+                for (int r = 0; r < kBlkCap; ++r) ev[r] *= sm.rd[side][r];
+                tri_sweep<false>(ev, Mt, nk, cap);
+#pragma unroll
+                for (int r = 0; r < kBlkCap; ++r) ev[r] *= sm.rd[side][r];
+                wave_lds_sync();
+#pragma unroll
+                for (int x = 0; x < kBlkCap; ++x)
+                    if (x < cap) Mt[x * kBlkCap + lane] = ev[x];
+            }
+        } else {
+            const int xt = tid - kInvWaves * kWave;
+            constexpr int kXT = kThreads - kInvWaves * kWave;
+            static_assert(kXT >= kChunk * kBlkCap, "one (A A^T)_{i, I} entry per exchanging thread");
+            // Operands of the X and R updates that need only I and J, fetched
+            // first (ahead of the stores below) and in flight while R_IJ is.
+            const double gaI0 = fetch_gaI(0, nI, xt);
+            bX0 = fetch_bX(0, nJ);
+            // ---- D. R_IJ from the owners of the rows in I. Every word of the
+            // s_cap x t_cap block is rewritten every step (zeros outside I x J;
+            // work-group 0 writes the rows past nI), so no word can keep a value
+            // from four steps back that carries the current 2-bit tag.
+            for (int e = xt; e < scap * tcap; e += kXT) {
+                const int x = e / tcap, y = e - x * tcap;
+                if (x < nI) {
+                    const int i = sm.I[x];
+                    if (i >= row0 && i < row0 + nrow) {
+                        const double v = (y < nJ) ? Rown[(size_t)(i - row0) * n + sm.J[y]] : 0.0;
+                        xstore(&ex[x * kBlkCap + y], pack_word(v, tag));
+                    }
+                } else if (g == 0) {
+                    xstore(&ex[x * kBlkCap + y], pack_word(0.0, tag));
                 }
-            } else if (g == 0) {
-                xstore(&ex[x * kBlkCap + y], pack_word(0.0, tag));
             }
-        }
-        for (int e0 = tid; e0 < nI * nJ; e0 += kThreads * 2) {
-            const xword* ptr[2];
-            int cnt = 0;
+            for (int e0 = xt; e0 < nI * nJ; e0 += kXT * 2) {
+                const xword* ptr[2];
+                int cnt = 0;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = e0 + u * kThreads;
-                const int x = (e < nI * nJ) ? e / nJ : 0, y = (e < nI * nJ) ? e - x * nJ : 0;
-                ptr[u] = ex + x * kBlkCap + y;
-                cnt += (e < nI * nJ);
-            }
-            double vals[2];
-            if (!poll_gather<double, 2>(ptr, cnt, tag, vals, P.sync, P.poll_sleep)) sm.fail = 1;
+                for (int u = 0; u < 2; ++u) {
+                    const int e = e0 + u * kXT;
+                    const int x = (e < nI * nJ) ? e / nJ : 0, y = (e < nI * nJ) ? e - x * nJ : 0;
+                    ptr[u] = ex + x * kBlkCap + y;
+                    cnt += (e < nI * nJ);
+                }
+                double vals[2];
+                if (!poll_gather<double, 2>(ptr, cnt, tag, vals, P.sync, P.poll_sleep)) sm.fail = 1;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = e0 + u * kThreads;
-                if (u < cnt) E[(e / nJ) * ldE + (e % nJ)] = vals[u];
+                for (int u = 0; u < 2; ++u) {
+                    const int e = e0 + u * kXT;
+                    if (u < cnt) E[(e / nJ) * ldE + (e % nJ)] = vals[u];
+                }
             }
+            if (xt < kChunk * kBlkCap) gaI[xt] = gaI0;
         }
-        if (tid < kChunk * kBlkCap) gaI[tid] = gaI0;
         __syncthreads();
         if (sm.fail) { ok = false; break; }
         B2_PHASE(kB2E);
         fresh();
-        // W = (A_I A_I^T)^{-1} R_IJ (B_J^T B_J)^{-1}, in place in E, by one
-        // wave with no block barrier: lane y < 32 takes column y of E
-        // into registers and solves with L_I (forward, pivots ascending) and
-        // L_I^T (backward, pivots descending), scaling by 1 / L[x][x] after
-        // each sweep; through LDS, lane x then takes row x and does the same
-        // with L_J and L_J^T. Right-looking: pivot x subtracts M[r][x] e[x]
-        // from every other entry r it reaches, independent multiply-adds
-        // whose factors are one contiguous row of the stored M^T. Entries
-        // outside the block are zeros, whose terms are exact zeros, and E
-        // is left zero outside nI x nJ. Lanes 32-63 stay idle: every factor
-        // is a broadcast LDS read, whose cost grows with the active lanes.
-        if (tid < kBlkCap) {
-            const int y = lane;
-            double ev[kBlkCap];
-            // Entries outside the block are cleared by a bit mask (no branch;
-            // the LDS there may hold any bit pattern).
+        // W = (A_I A_I^T)^{-1} R_IJ (B_J^T B_J)^{-1} from the two inverses
+        // (GI = G_I^{-1} over the factor L_I's rows, GJ = G_J^{-1} over
+        // L_J's, row-major): W1 = G_I^{-1} R_IJ, then W = W1 G_J^{-1}, each
+        // entry a sum over the block in index order by one thread, two
+        // entries per thread (a wave: two rows x, 32 consecutive y), written
+        // over E once every thread has read it. W is zero outside nI x nJ.
+        {
+            const double* GI = LI;
+            const double* GJ = LJ;
+            double wv2[2];
 #pragma unroll
-            for (int x = 0; x < kBlkCap; ++x) {
-                const long long keep = (x < nI && y < nJ) ? -1ll : 0ll;
-                ev[x] = __longlong_as_double(__double_as_longlong(E[x * ldE + y]) & keep);
+            for (int u = 0; u < 2; ++u) {
+                const int e = tid + u * kThreads, x = e / kBlkCap, y = e - x * kBlkCap;
+                double acc = 0.0;
+                if (x < nI && y < nJ)
+                    for (int z = 0; z < nI; ++z) acc += GI[x * kBlkCap + z] * E[z * ldE + y];
+                wv2[u] = acc;
             }
-            tri_sweep<true>(ev, LI, nI, scap);
+            __syncthreads();
 #pragma unroll
-            for (int r = 0; r < kBlkCap; ++r) ev[r] *= sm.rd[0][r];
-            tri_sweep<false>(ev, LI, nI, scap);
+            for (int u = 0; u < 2; ++u) {
+                const int e = tid + u * kThreads, x = e / kBlkCap, y = e - x * kBlkCap;
+                E[x * ldE + y] = wv2[u];
+            }
+            __syncthreads();
 #pragma unroll
-            for (int r = 0; r < kBlkCap; ++r) ev[r] *= sm.rd[0][r];
+            for (int u = 0; u < 2; ++u) {
+                const int e = tid + u * kThreads, x = e / kBlkCap, y = e - x * kBlkCap;
+                double acc = 0.0;
+                if (x < nI && y < nJ)
+                    for (int z = 0; z < nJ; ++z) acc += E[x * ldE + z] * GJ[z * kBlkCap + y];
+                wv2[u] = acc;
+            }
+            __syncthreads();
 #pragma unroll
-            for (int x = 0; x < kBlkCap; ++x) E[x * ldE + y] = ev[x];
-            wave_lds_sync();
-            const int xr = lane;
-#pragma unroll
-            for (int yy = 0; yy < kBlkCap; ++yy) ev[yy] = E[xr * ldE + yy];
-            wave_lds_sync();
-            tri_sweep<true>(ev, LJ, nJ, tcap);
-#pragma unroll
-            for (int c = 0; c < kBlkCap; ++c) ev[c] *= sm.rd[1][c];
-            tri_sweep<false>(ev, LJ, nJ, tcap);
-#pragma unroll
-            for (int c = 0; c < kBlkCap; ++c) ev[c] *= sm.rd[1][c];
-#pragma unroll
-            for (int yy = 0; yy < kBlkCap; ++yy) E[xr * ldE + yy] = ev[yy];
+            for (int u = 0; u < 2; ++u) {
+                const int e = tid + u * kThreads, x = e / kBlkCap, y = e - x * kBlkCap;
+                E[x * ldE + y] = wv2[u];
+            }
         }
         __syncthreads();
         fresh();
@@ -1173,7 +1217,7 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
 #undef B2_PHASE
     if (sm.fail) status = kETimeout;
     if (timing)
-        for (int i = 0; i < kB2Count; ++i) P.phase[i] += ph[i];
+        for (int i = 0; i < kB2Count; ++i) P.phase[i] += sm.ph[i];
     if (g == 0 && tid == 0) {
         P.report->iters = k;
         P.report->status = status;
