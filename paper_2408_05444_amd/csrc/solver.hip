@@ -138,14 +138,16 @@ __device__ __forceinline__ void block_dots(const T* x, int len, int D, RowFn row
 }
 
 // Optional phase timing (work-group 0, thread 0): ticks of the constant-rate
-// wall clock spent in each phase of an update, summed over the solve.
+// wall clock spent in each phase of an update, summed over the solve. The
+// clocks live in LDS (ph[kPhCount] holds the last mark), not in registers
+// that the untimed solves would carry too.
 enum { kPhReduce, kPhSelect, kPhRow, kPhDots, kPhWait, kPhX, kPhUpdate, kPhEnd, kPhCount };
 #define MEK_PHASE(id)                                                   \
     do {                                                                \
         if (timing) {                                                   \
             const unsigned long long now_ = wall_clock64();             \
-            ph[id] += now_ - t_last;                                    \
-            t_last = now_;                                              \
+            ph[id] += now_ - ph[kPhCount];                              \
+            ph[kPhCount] = now_;                                        \
         }                                                               \
     } while (0)
 
@@ -314,8 +316,11 @@ __global__ void __launch_bounds__(kThreads, 1) solve_kernel(SolveParams<T> P) {
     // Timed work-groups: the first, the middle and the last of the team.
     const int tslot = (g == 0) ? 0 : (g == W / 2) ? 1 : (g == W - 1) ? 2 : -1;
     const bool timing = P.phase != nullptr && tslot >= 0 && threadIdx.x == 0;
-    unsigned long long ph[kPhCount] = {0, 0, 0, 0, 0, 0, 0, 0};
-    unsigned long long t_last = timing ? wall_clock64() : 0;
+    __shared__ unsigned long long ph[kPhCount + 1];
+    if (timing) {
+        for (int i = 0; i < kPhCount; ++i) ph[i] = 0;
+        ph[kPhCount] = wall_clock64();
+    }
     const int cs = (m + kThreads - 1) / kThreads;
     int sb, scnt;
     double S0 = -1.0, S = 0.0, err = NAN;
@@ -731,8 +736,11 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
     int status = kMaxIter, last_set = 0;
     const int sb = min(m, tid), scnt = tid < m ? 1 : 0;
     const bool timing = P.phase != nullptr && blockIdx.x == 0 && tid == 0;
-    unsigned long long ph[kPhCount] = {0, 0, 0, 0, 0, 0, 0, 0};
-    unsigned long long t_last = timing ? wall_clock64() : 0;
+    __shared__ unsigned long long ph[kPhCount + 1];
+    if (timing) {
+        for (int i = 0; i < kPhCount; ++i) ph[i] = 0;
+        ph[kPhCount] = wall_clock64();
+    }
     for (;;) {
         if ((k % kUTable) == 0) {
             if (tid < kUTable) u_tab[tid] = philox_uniform(P.seed, P.inst, P.k_offset + k + tid);
