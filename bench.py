@@ -1002,7 +1002,7 @@ def main():
     # collectives alone, timed by the library, give the floor under it.
     floor = mek.mek_exchange_floor(results[-1].team_wgs, m, n, q, rounds=20000)
     line["roofline"]["regime"] = ("latency: the exchanges between the team's work-groups "
-                                  "(R stays in LDS, 0.68 MB per update crosses HBM)")
+                                  "(R stays in LDS, 0.67 MB per update crosses HBM)")
     line["roofline"]["latency_floor_us_per_update"] = floor
     line["roofline"]["latency_frac"] = floor / (kernel_ms * 1e3 / max(iters, 1))
     if not args.no_forms:
