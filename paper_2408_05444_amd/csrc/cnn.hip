@@ -323,7 +323,7 @@ conv3x3_wgrad_fewc_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
 // same fixed-order summation follows.
 constexpr int kGStride = 33;   // 16-byte slots per output channel of the gradient tile (odd)
 constexpr int kXStride = 37;   // slots per input channel of a shifted copy (18 rows x 2, + 1)
-constexpr int kWgTiles = 4;    // pixel tiles per block of the matrix-core weight gradient
+constexpr int kWgTiles = 2;    // pixel tiles per block of the matrix-core weight gradient
 
 template <int CO>
 __global__ void __launch_bounds__(256)
