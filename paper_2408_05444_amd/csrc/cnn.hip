@@ -56,21 +56,41 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 
 // Stage channels [0, C) of the (kHalo x kHalo) input tile at (h0-1, w0-1)
 // of image n into LDS as FP32, zero outside the image; with a mask, entries
-// whose mask value is not > 0 read as zero (a ReLU's gradient gate).
+// whose mask value is not > 0 read as zero (a ReLU's gradient gate). A
+// thread issues kStageU loads before it stores any of them, each from an
+// address clamped into the tensor (no branch around a load), so that their
+// latencies overlap; entries outside the image or past the end are then
+// replaced by zero.
+constexpr int kStageU = 4;
 __device__ __forceinline__ void stage_halo(float* xs, const uint16_t* __restrict__ x,
                                            const uint16_t* __restrict__ mask, int n, int C,
                                            int H, int W, int h0, int w0) {
     const int tot = C * kHaloPix;
-    for (int e = threadIdx.x; e < tot; e += kCThreads) {
-        const int c = e / kHaloPix, r = e - c * kHaloPix;
-        const int hh = h0 - 1 + r / kHalo, ww = w0 - 1 + r % kHalo;
-        float v = 0.0f;
-        if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
-            const size_t idx = tidx(n, c, hh, ww, C, H, W);
-            v = bf2f(x[idx]);
-            if (mask && !(bf2f(mask[idx]) > 0.0f)) v = 0.0f;
+    // Without a mask the gate loads re-read x (cache hits), so that no
+    // branch sits between the loads.
+    const uint16_t* __restrict__ mp = mask ? mask : x;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += kStageU * kCThreads) {
+        uint16_t xv[kStageU], mv[kStageU];
+        bool in[kStageU];
+#pragma unroll
+        for (int u = 0; u < kStageU; ++u) {
+            const int e = min(e0 + u * kCThreads, tot - 1);
+            const int c = e / kHaloPix, r = e - c * kHaloPix;
+            const int hh = h0 - 1 + r / kHalo, ww = w0 - 1 + r % kHalo;
+            in[u] = e0 + u * kCThreads < tot && hh >= 0 && hh < H && ww >= 0 && ww < W;
+            const size_t idx = tidx(n, c, min(max(hh, 0), H - 1), min(max(ww, 0), W - 1), C, H, W);
+            xv[u] = x[idx];
+            mv[u] = mp[idx];
         }
-        xs[c * kChanStride + r] = v;
+#pragma unroll
+        for (int u = 0; u < kStageU; ++u) {
+            const int e = e0 + u * kCThreads;
+            if (e < tot) {
+                const int c = e / kHaloPix, r = e - c * kHaloPix;
+                xs[c * kChanStride + r] =
+                    (in[u] && (!mask || bf2f(mv[u]) > 0.0f)) ? bf2f(xv[u]) : 0.0f;
+            }
+        }
     }
 }
 
@@ -246,15 +266,27 @@ conv3x3_wgrad_fewc_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
     stage_halo(xs, x, nullptr, n, Cin, H, W, h0, w0);
     // Gradient (channels-last): task e = (pixel, 8-channel chunk), one
     // 16-byte load (and one of the gate), 8 values to the channels' rows.
-    for (int e = threadIdx.x; e < 4 * kCThreads; e += kCThreads) {
+    // The four tasks of a thread load first (clamped addresses, no branch
+    // between the loads; without a gate it re-reads g), then store.
+    const uint16_t* __restrict__ gm = gmask ? gmask : g;
+    uint4 gv4[4], gm4[4];
+    bool gin[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = threadIdx.x + u * kCThreads;
         const int p = e >> 2, q = e & 3;
         const int hh = h0 + p / kCT, ww = w0 + p % kCT;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u), mk = make_uint4(0u, 0u, 0u, 0u);
-        if (hh < H && ww < W) {
-            const size_t off = (((size_t)n * H + hh) * W + ww) * CO + 8 * q;
-            v = *reinterpret_cast<const uint4*>(g + off);
-            if (gmask) mk = *reinterpret_cast<const uint4*>(gmask + off);
-        }
+        gin[u] = hh < H && ww < W;
+        const size_t off = (((size_t)n * H + min(hh, H - 1)) * W + min(ww, W - 1)) * CO + 8 * q;
+        gv4[u] = *reinterpret_cast<const uint4*>(g + off);
+        gm4[u] = *reinterpret_cast<const uint4*>(gm + off);
+    }
+#pragma unroll
+    for (int u0 = 0; u0 < 4; ++u0) {
+        const int e = threadIdx.x + u0 * kCThreads;
+        const int p = e >> 2, q = e & 3;
+        const uint4 v = gin[u0] ? gv4[u0] : make_uint4(0u, 0u, 0u, 0u);
+        const uint4 mk = gm4[u0];
         const uint32_t vv[4] = {v.x, v.y, v.z, v.w}, mm[4] = {mk.x, mk.y, mk.z, mk.w};
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
