@@ -256,9 +256,13 @@ conv3x3_wgrad_fewc_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
                           const uint16_t* __restrict__ g, const uint16_t* __restrict__ gmask,
                           float* __restrict__ partial) {
     constexpr int CO = 32, NA = kFewC * 9 + 1, PARTS = kCThreads / CO;
-    __shared__ float xs[kFewC * kChanStride];
-    __shared__ float gs[CO * kGsStride];
-    __shared__ float red[PARTS * CO * NA];
+    // The parts' sums reuse the tiles' LDS once every thread is done with
+    // them (38 KB per block: four blocks fit a compute unit).
+    constexpr int kTileF = kFewC * kChanStride + CO * kGsStride, kRedF = PARTS * CO * NA;
+    __shared__ float smem[kTileF > kRedF ? kTileF : kRedF];
+    float* const xs = smem;
+    float* const gs = smem + kFewC * kChanStride;
+    float* const red = smem;
     const int tiles_w = (W + kCT - 1) / kCT;
     const int th = blockIdx.x / tiles_w, tw = blockIdx.x - th * tiles_w;
     const int n = blockIdx.y;
@@ -322,6 +326,7 @@ conv3x3_wgrad_fewc_kernel(const uint16_t* __restrict__ x, int Cin, int H, int W,
             }
         }
     }
+    __syncthreads();   // the tiles are read; their space takes the parts' sums
     float* rp = red + (part * CO + o) * NA;
 #pragma unroll
     for (int c = 0; c < kFewC; ++c)
