@@ -64,7 +64,9 @@ def absconv(x, W):
                                                     (32, 32, 1, True, "bf16"),
                                                     (32, 32, 0, False, "bf16"),
                                                     (32, 3, 0, True, "f64"),
-                                                    (32, 3, 0, True, "f64+add")])
+                                                    (32, 3, 0, True, "f64+add"),
+                                                    (3, 3, 1, True, "bf16"),
+                                                    (3, 3, 0, False, "f64+add")])
 def test_conv_forward(cin, cout, relu, bias, out):
     rng = np.random.default_rng(cin + cout + relu)
     N, H, W = 2, 20, 37   # ragged 16 x 16 tiles on both axes
@@ -95,7 +97,8 @@ def test_conv_forward(cin, cout, relu, bias, out):
     assert np.all(np.abs(got - ref) <= tol + 1e-30)
 
 
-@pytest.mark.parametrize("cout,cin,gated", [(32, 32, True), (32, 3, True), (3, 32, False)])
+@pytest.mark.parametrize("cout,cin,gated", [(32, 32, True), (32, 3, True), (3, 32, False),
+                                            (3, 32, True), (3, 3, True)])
 def test_conv_grad_input(cout, cin, gated):
     rng = np.random.default_rng(10 + cout + cin)
     N, H, W = 2, 19, 33
