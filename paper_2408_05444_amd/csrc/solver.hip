@@ -682,6 +682,70 @@ __device__ __forceinline__ double group_sum(double v, int G) {
     return v;
 }
 
+// The selection step of Algs. 1-5 by one wave for at most 2 kWave rows:
+// lane l holds rows 2 l and 2 l + 1 (r: ||R_i||^2, a: ||A_i||^2, h: r / a,
+// or -1 without a row or with a = 0), S and M the block totals. The same
+// rules as select_rows on a block: the greedy set {a > 0, h >= t} with
+// t = min(M, theta M + (1 - theta) S / F_A) and weights r (Algs. 3/4),
+// every row with a > 0 and weight a (Alg. 1), the first row of largest h
+// (Alg. 5), the cyclic order over the active rows (Alg. 2); the draw takes
+// the first member whose running weight exceeds u T, else the last member.
+// Returns the row | (set size << 16), the same in every lane.
+__device__ __forceinline__ int small_select(int variant, int lane, int m, double r0, double r1,
+                                            double a0, double a1, double h0, double h1, double S,
+                                            double M, double F_A, double theta, double u,
+                                            long long k, const int* __restrict__ active,
+                                            int n_active) {
+    const double r[2] = {r0, r1}, a[2] = {a0, a1}, h[2] = {h0, h1};
+    if (variant == kBK) return active[k % n_active];
+    if (variant == kMWRBK) {
+        int cand = INT_MAX;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            if (2 * lane + j < m && a[j] > 0.0 && h[j] == M) cand = min(cand, 2 * lane + j);
+        return wave_min_int(cand) | (1 << 16);
+    }
+    const bool greedy = variant == kGRBK || variant == kRGRBK;
+    double t = 0.0;
+    if (greedy) {
+#pragma clang fp contract(off)
+        const double th = (variant == kGRBK) ? 0.5 : theta;
+        t = th * M + (1.0 - th) * (S / F_A);
+        if (t > M) t = M;
+    }
+    bool mem[2];
+    double w[2];
+    double ws = 0.0;
+    int c = 0, lastm = -1;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        mem[j] = 2 * lane + j < m && a[j] > 0.0 && (!greedy || h[j] >= t);
+        w[j] = greedy ? r[j] : a[j];
+        if (mem[j]) {
+            ws += w[j];
+            ++c;
+            lastm = 2 * lane + j;
+        }
+    }
+    const double iv = wave_incl_scan(ws);
+    const int ic = wave_incl_scan_int(c);
+    const double T = readlane_d(iv, kWave - 1);
+    const int tot = __builtin_amdgcn_readlane(ic, kWave - 1);
+    const double target = u * T;
+    double run = iv - ws;
+    int cand = INT_MAX;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        if (mem[j]) {
+            run += w[j];
+            if (cand == INT_MAX && run > target) cand = 2 * lane + j;
+        }
+    }
+    cand = wave_min_int(cand);
+    lastm = wave_max_int(lastm);
+    return (cand != INT_MAX ? cand : lastm) | (tot << 16);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T> P) {
     extern __shared__ __align__(16) unsigned char dyn_smem[];
@@ -706,6 +770,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
         reinterpret_cast<unsigned char*>(dyn_smem) +
         ((((size_t)m * ld + (size_t)q * ld + (size_t)q * p + q + n + p) * sizeof(T) + 15) & ~(size_t)15));
     double* rn = u_tab + kUTable;   // new row norms, m
+    double* epart = rn + m;         // error partials of the threads, kThreads
     const int G1 = small_group(q), G2 = small_group(n), G3 = small_group(m);
     for (int e = tid; e < m * n; e += kThreads) Rl[(e / n) * ld + e % n] = P.R[e];
     for (int e = tid; e < q * n; e += kThreads) Bl[(e / n) * ld + e % n] = P.B[e];
@@ -735,6 +800,18 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
     long long k = 0;
     int status = kMaxIter, last_set = 0;
     const int sb = min(m, tid), scnt = tid < m ? 1 : 0;
+    // Up to 2 kWave rows, wave 0 alone reduces the norms and error partials
+    // and runs the selection (lane l: rows 2 l and 2 l + 1), with no block
+    // barrier until it hands the results over through LDS.
+    const bool wsel = m <= 2 * kWave;
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
+    const double a_lo = (wsel && wv == 0 && 2 * lane < m) ? P.a[2 * lane] : 0.0;
+    const double a_hi = (wsel && wv == 0 && 2 * lane + 1 < m) ? P.a[2 * lane + 1] : 0.0;
+    __shared__ double s_wd[3];
+    __shared__ int s_wi[2];
+    if (tid < m) rn[tid] = ri;
+    epart[tid] = ep;
+    __syncthreads();
     const bool timing = P.phase != nullptr && blockIdx.x == 0 && tid == 0;
     __shared__ unsigned long long ph[kPhCount + 1];
     if (timing) {
@@ -750,7 +827,40 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
         double rr[1] = {scnt ? ri : 0.0}, aa[1] = {ai};
         double rho[1] = {(scnt && ai > 0.0) ? ri / ai : -1.0};
         double Sp = rr[0], Mp = rho[0], Ep = ep;
-        block_sum_max_sum(Sp, Mp, Ep, sc);
+        if (wsel) {
+            if (wv == 0) {
+                double r2[2], h2[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int row = 2 * lane + u;
+                    const double au = u ? a_hi : a_lo;
+                    r2[u] = row < m ? rn[row] : 0.0;
+                    h2[u] = (row < m && au > 0.0) ? r2[u] / au : -1.0;
+                }
+                const double Sw = wave_sum(r2[0] + r2[1]);
+                const double Mw = wave_max(fmax(h2[0], h2[1]));
+                double le = 0.0;
+#pragma unroll
+                for (int j = 0; j < kWaves; ++j) le += epart[lane * kWaves + j];
+                const double Ew = wave_sum(le);
+                const int sel = small_select(P.variant, lane, m, r2[0], r2[1], a_lo, a_hi, h2[0],
+                                             h2[1], Sw, Mw, P.F_A, P.theta, u_k, P.k_offset + k,
+                                             P.active, P.n_active);
+                if (lane == 0) {
+                    s_wd[0] = Sw;
+                    s_wd[1] = Mw;
+                    s_wd[2] = Ew;
+                    s_wi[0] = sel & 0xffff;
+                    s_wi[1] = sel >> 16;
+                }
+            }
+            __syncthreads();
+            Sp = s_wd[0];
+            Mp = s_wd[1];
+            Ep = s_wd[2];
+        } else {
+            block_sum_max_sum(Sp, Mp, Ep, sc);
+        }
         MEK_PHASE(kPhReduce);
         S = Sp;
         const double M = Mp;
@@ -771,6 +881,9 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
         if (P.replay && P.k_offset + k < P.replay_len) {
             ik = P.replay[P.k_offset + k];
             last_set = 0;
+        } else if (wsel) {
+            ik = s_wi[0];
+            last_set = s_wi[1];
         } else {
             const SelectOut so = select_rows<1>(P.variant, sb, scnt, rr, aa, rho, S, M, P.F_A,
                                                 P.theta, u_k, P.k_offset + k, P.active,
@@ -839,6 +952,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
             acc = group_sum(acc, G2);
             if (j < n && g2 == 0) wl[j] = (T)acc;
         }
+        epart[tid] = ep;
         __syncthreads();
         MEK_PHASE(kPhX);
         // R_h -= (c (A A^T)_{i_k, h}) w and the new norm of row h, G3 lanes
@@ -878,7 +992,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
 size_t solve_small_lds_bytes(int m, int p, int q, int n, size_t elem) {
     const size_t ld = (size_t)n + 1;
     return (((size_t)m * ld + (size_t)q * ld + (size_t)q * p + q + n + p) * elem + 15) / 16 * 16 +
-           (kUTable + (size_t)m) * sizeof(double);
+           (kUTable + (size_t)m + kThreads) * sizeof(double);
 }
 
 template <typename T>
