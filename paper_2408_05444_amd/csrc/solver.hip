@@ -770,7 +770,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
         reinterpret_cast<unsigned char*>(dyn_smem) +
         ((((size_t)m * ld + (size_t)q * ld + (size_t)q * p + q + n + p) * sizeof(T) + 15) & ~(size_t)15));
     double* rn = u_tab + kUTable;   // new row norms, m
-    double* epart = rn + m;         // error partials of the threads, kThreads
+    double* epart = rn + m;         // error partials of the waves, kWaves
     const int G1 = small_group(q), G2 = small_group(n), G3 = small_group(m);
     for (int e = tid; e < m * n; e += kThreads) Rl[(e / n) * ld + e % n] = P.R[e];
     for (int e = tid; e < q * n; e += kThreads) Bl[(e / n) * ld + e % n] = P.B[e];
@@ -810,7 +810,10 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
     __shared__ double s_wd[3];
     __shared__ int s_wi[2];
     if (tid < m) rn[tid] = ri;
-    epart[tid] = ep;
+    {
+        const double ew = wave_sum(ep);
+        if (lane == 0) epart[wv] = ew;
+    }
     __syncthreads();
     const bool timing = P.phase != nullptr && blockIdx.x == 0 && tid == 0;
     __shared__ unsigned long long ph[kPhCount + 1];
@@ -839,10 +842,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
                 }
                 const double Sw = wave_sum(r2[0] + r2[1]);
                 const double Mw = wave_max(fmax(h2[0], h2[1]));
-                double le = 0.0;
-#pragma unroll
-                for (int j = 0; j < kWaves; ++j) le += epart[lane * kWaves + j];
-                const double Ew = wave_sum(le);
+                const double Ew = wave_sum(lane < kWaves ? epart[lane] : 0.0);
                 const int sel = small_select(P.variant, lane, m, r2[0], r2[1], a_lo, a_hi, h2[0],
                                              h2[1], Sw, Mw, P.F_A, P.theta, u_k, P.k_offset + k,
                                              P.active, P.n_active);
@@ -952,7 +952,10 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
             acc = group_sum(acc, G2);
             if (j < n && g2 == 0) wl[j] = (T)acc;
         }
-        epart[tid] = ep;
+        {
+            const double ew = wave_sum(ep);
+            if (lane == 0) epart[wv] = ew;
+        }
         __syncthreads();
         MEK_PHASE(kPhX);
         // R_h -= (c (A A^T)_{i_k, h}) w and the new norm of row h, G3 lanes
@@ -992,7 +995,7 @@ __global__ void __launch_bounds__(kThreads, 1) solve_small_kernel(SolveParams<T>
 size_t solve_small_lds_bytes(int m, int p, int q, int n, size_t elem) {
     const size_t ld = (size_t)n + 1;
     return (((size_t)m * ld + (size_t)q * ld + (size_t)q * p + q + n + p) * elem + 15) / 16 * 16 +
-           (kUTable + (size_t)m + kThreads) * sizeof(double);
+           (kUTable + (size_t)m + kWaves) * sizeof(double);
 }
 
 template <typename T>
