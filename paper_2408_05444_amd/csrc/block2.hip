@@ -743,53 +743,59 @@ __global__ void __launch_bounds__(kThreads, 1) block2_kernel(Block2Params P) {
     // Leaves the squared-error partial of the updated rows in sm.err_w.
     auto update_x = [&](int nI, int nJ, double bpre) {
         double ep = 0.0;
+        constexpr int kXH = kBlkCap / 2;   // A's entries in two halves of the block
         for (int l0 = 0; l0 < nx; l0 += kXRows) {
             const int lc = min(kXRows, nx - l0);
             for (int s0 = 0; s0 < p; s0 += kThreads) {
                 const int s2 = s0 + tid, s2c = min(s2, p - 1);
-                double av[kBlkCap];
+                double acc[kXRows];
 #pragma unroll
-                for (int x = 0; x < kBlkCap; ++x) {
-                    const int Ix = __builtin_amdgcn_readfirstlane(sm.I[x < nI ? x : 0]);
-                    av[x] = P.A[(size_t)Ix * p + (unsigned int)s2c];
-                }
-                if (s0 == 0) {
-                    const double bv = (l0 == 0) ? bpre : fetch_bX(l0, nJ);
-                    if (tid >= kBxT0) bX[tid - kBxT0] = bv;
-                    __syncthreads();
-                    if (tid < kXRows * kBlkCap) {
-                        const int x = tid / kXRows, l = tid - x * kXRows;
-                        double a0 = 0.0, a1 = 0.0;
+                for (int l = 0; l < kXRows; ++l) acc[l] = 0.0;
+#pragma unroll
+                for (int hf = 0; hf < 2; ++hf) {
+                    double av[kXH];
+#pragma unroll
+                    for (int x = 0; x < kXH; ++x) {
+                        const int xx = hf * kXH + x;
+                        const int Ix = __builtin_amdgcn_readfirstlane(sm.I[xx < nI ? xx : 0]);
+                        av[x] = P.A[(size_t)Ix * p + (unsigned int)s2c];
+                    }
+                    if (hf == 0 && s0 == 0) {
+                        const double bv = (l0 == 0) ? bpre : fetch_bX(l0, nJ);
+                        if (tid >= kBxT0) bX[tid - kBxT0] = bv;
+                        __syncthreads();
+                        if (tid < kXRows * kBlkCap) {
+                            const int x = tid / kXRows, l = tid - x * kXRows;
+                            double a0 = 0.0, a1 = 0.0;
 #pragma unroll 4
-                        for (int y = 0; y < kBlkCap; y += 2) {
-                            a0 += E[x * ldE + y] * bX[l * kBlkCap + y];
-                            a1 += E[x * ldE + y + 1] * bX[l * kBlkCap + y + 1];
+                            for (int y = 0; y < kBlkCap; y += 2) {
+                                a0 += E[x * ldE + y] * bX[l * kBlkCap + y];
+                                a1 += E[x * ldE + y + 1] * bX[l * kBlkCap + y + 1];
+                            }
+                            cX[x * kXRows + l] = a0 + a1;
                         }
-                        cX[x * kXRows + l] = a0 + a1;
+                        __syncthreads();
                     }
-                    __syncthreads();
+                    // The chunk's rows (terms in x order, first half then
+                    // second), A's entries of this half in registers.
+#pragma unroll
+                    for (int l = 0; l < kXRows; ++l)
+                        if (l < lc) {
+#pragma unroll
+                            for (int x = 0; x < kXH; ++x)
+                                acc[l] += cX[(hf * kXH + x) * kXRows + l] * av[x];
+                        }
                 }
-                // Rows of the chunk two at a time, with A's entries kept in
-                // registers across the pairs.
-                for (int lp = 0; lp < lc; lp += 2) {
-                    double acc0 = 0.0, acc1 = 0.0;
+                if (s2 < p) {
 #pragma unroll
-                    for (int x = 0; x < kBlkCap; ++x) {
-                        acc0 += cX[x * kXRows + lp] * av[x];
-                        acc1 += cX[x * kXRows + lp + 1] * av[x];
-                    }
-                    if (s2 < p) {
-#pragma unroll
-                        for (int l2 = 0; l2 < 2; ++l2) {
-                            const int l = lp + l2;
-                            if (l < lc) {
-                                const size_t off = (size_t)(xc0 + l0 + l) * p + s2;
-                                const double nv = P.Xt[off] + (l2 ? acc1 : acc0);
-                                P.Xt[off] = nv;
-                                if (P.Xref_t) {
-                                    const double d = nv - P.Xref_t[off];
-                                    ep += d * d;
-                                }
+                    for (int l = 0; l < kXRows; ++l) {
+                        if (l < lc) {
+                            const size_t off = (size_t)(xc0 + l0 + l) * p + s2;
+                            const double nv = P.Xt[off] + acc[l];
+                            P.Xt[off] = nv;
+                            if (P.Xref_t) {
+                                const double d = nv - P.Xref_t[off];
+                                ep += d * d;
                             }
                         }
                     }
