@@ -424,43 +424,26 @@ __device__ __forceinline__ void select_top(const unsigned long long (&kr)[SR], i
 // forward, pivots x = 0, 1, ..., n - 2 subtract Mt[x][r] e[x] from e[r] for
 // r > x; backward, pivots x = n - 1, ..., 1 subtract it for r < x. Mt holds
 // the pivots' factors as rows of kBlkCap, zero past n, in `cap` >= n rows.
-// Pivots go in pairs: both rows are read together (one LDS round trip per
-// pair), the first pivot's term enters the second pivot's entry, and every
-// other entry takes the two terms in pivot order. The second pivot of a
-// pair (forward) or the first (backward) may lie past n: its terms are
-// then exact zeros (e of it is zero, or its row is; a row past `cap` is
-// read clamped). The (uniform) branch per pair keeps the compiler from
-// fetching further ahead, which would need more registers than the wave
-// has.
+// One pivot at a time, its factor row in registers: pivots taken in pairs
+// (two rows at once, one LDS round trip per pair) held so many registers
+// that the kernel spilled around the sweeps; the pair form took 5.6 us more
+// per step of the two-sided solve. The (uniform) branch per pivot keeps
+// the compiler from fetching further ahead.
 template <bool kFwd>
 __device__ __forceinline__ void tri_sweep(double (&e)[kBlkCap], const double* Mt, int n, int cap) {
-    constexpr int kPiv = kBlkCap - 1;   // pivots 0 .. kBlkCap - 2 (forward) or kBlkCap - 1 .. 1
 #pragma unroll
-    for (int st = 0; st < kPiv; st += 2) {
-        const int x = kFwd ? st : kBlkCap - 1 - st;          // first pivot of the pair
-        const bool two = st + 1 < kPiv;
-        const int x2 = kFwd ? x + 1 : x - 1;                  // second pivot
-        // Forward: the pair has work if its first pivot does; backward, if its
-        // second (lower) one does (the first may lie past n).
-        if (kFwd ? x + 1 < n : (two ? x2 < n : x < n)) {
+    for (int st = 0; st < kBlkCap - 1; ++st) {
+        const int x = kFwd ? st : kBlkCap - 1 - st;
+        if (x < n) {
             const double* m1 = Mt + min(x, cap - 1) * kBlkCap;
-            const double* m2 = Mt + min(x2, cap - 1) * kBlkCap;
-            double a1[kBlkCap], a2[kBlkCap];
+            double a1[kBlkCap];
 #pragma unroll
-            for (int r = 0; r < kBlkCap; ++r) {
+            for (int r = 0; r < kBlkCap; ++r)
                 if (kFwd ? r > x : r < x) a1[r] = m1[r];
-                if (two && (kFwd ? r > x2 : r < x2)) a2[r] = m2[r];
-            }
             const double e1 = e[x];
-            if (two) e[x2] -= a1[x2] * e1;
-            const double e2 = two ? e[x2] : 0.0;
 #pragma unroll
-            for (int r = 0; r < kBlkCap; ++r) {
-                if ((kFwd ? r > x : r < x) && !(two && r == x2)) {
-                    e[r] -= a1[r] * e1;
-                    if (two) e[r] -= a2[r] * e2;
-                }
-            }
+            for (int r = 0; r < kBlkCap; ++r)
+                if (kFwd ? r > x : r < x) e[r] -= a1[r] * e1;
         }
     }
 }
